@@ -1,0 +1,211 @@
+/*
+ * gvom.h -- C ABI of the MI355X per-scan voxel-mapping library (libgvom.so).
+ *
+ * The library implements the per-scan path of G-VOM (Overbye & Saripalli,
+ * "G-VOM: A GPU Accelerated Voxel Off-Road Mapping System", arXiv 2109.13176):
+ * a lidar scan and its odometry pose go in (Sec. I: the system needs only
+ * odometry and lidar); the points are transformed into the map frame and
+ * binned into a robot-centred voxel map whose voxels carry hits, passes and
+ * the lowest return height (Sec. III-A, III-C); the map is exported as the
+ * lookup table + data array of Sec. III-A and as the 2D height, obstacle,
+ * slope, roughness and negative-obstacle maps of Sec. III-D.
+ *
+ * Conventions for every call:
+ *  - Every call returns an int32_t status: MAP_OK (0) or a negative MAP_E_*.
+ *    Nothing throws or aborts across the ABI.
+ *  - Bulk buffers (points, outputs) are DEVICE pointers owned by the caller.
+ *    Poses, parameters and small results are HOST pointers.  The library owns
+ *    only the map state it allocates in map_create.
+ *  - Work is enqueued on the map's HIP stream (hipStream_t passed as void*;
+ *    NULL = the default stream) and the call returns without waiting, except
+ *    where a call says it synchronises.  Outputs are valid once that stream
+ *    has been synchronised.
+ *  - An error detected before any work is enqueued leaves the map unchanged.
+ *    A HIP runtime error marks the map with the sticky MAP_E_DEVICE, which
+ *    every later call returns until map_reset.
+ *  - Different maps may be used from different threads; one map is not
+ *    thread-safe.
+ *
+ * Coordinates.  World coordinates are metres.  A "Q" value is a coordinate in
+ * units of 2^-16 voxel edge (int32); the voxel of a Q value is floor(Q/2^16).
+ * The window holds nx*ny*nz voxels; its origin (world voxel index of window
+ * voxel (0,0,0)) is always a whole number of voxels (Sec. III-A).  Window-local
+ * voxel (x, y, z) has linear index (x*ny + y)*nz + z; 2D maps are [nx][ny]
+ * with y fastest.
+ */
+#ifndef GVOM_H
+#define GVOM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define MAP_OK                 0
+#define MAP_E_INVALID         -1  /* null pointer, n < 0, bad parameter or flag      */
+#define MAP_E_POSE            -2  /* non-finite pose                                 */
+#define MAP_E_SENSOR_OUTSIDE  -3  /* sensor voxel outside the window, no recentring  */
+#define MAP_E_RANGE           -4  /* sensor |t / res| >= 2^15 voxels                 */
+#define MAP_E_CAPACITY        -5  /* an output buffer is too small                   */
+#define MAP_E_OOM             -6  /* device allocation failed                        */
+#define MAP_E_DEVICE          -7  /* HIP runtime error (sticky until map_reset)      */
+
+/* ---- map_insert_scan flags -------------------------------------------- */
+#define MAP_RECENTER        1u   /* move the window onto the pose before inserting   */
+#define MAP_STATS_DISTINCT  2u   /* also count distinct voxels touched (slower)      */
+/* Performance hint only (results never depend on it): the cloud is ordered
+ * as consecutive firings of b beams (point index = azimuth * b + beam), as a
+ * spinning lidar delivers it.  b in [1, 65535]. */
+#define MAP_FIRING(b)       (((uint32_t)(b) & 0xFFFFu) << 16)
+
+/* ---- parameters -------------------------------------------------------- */
+/* The paper names every parameter below but fixes none of their values. */
+typedef struct {
+  int32_t nx, ny, nz;       /* window size in voxels; nx, ny even in [2, 8192]; nz in
+                               [1, 128]; nx*ny*nz < 2^31 (Sec. III-A)                 */
+  float   res_m;            /* cubic voxel edge in metres, > 0 (Sec. III-A)          */
+  int32_t sensor_z_voxel;   /* window z index of the sensor voxel after recentring   */
+  float   obs_min_m;        /* positive-obstacle band above the ground voxel,        */
+  float   obs_max_m;        /*   min and max height (Sec. III-D)                      */
+  int32_t dens_num;         /* hard obstacle iff band density > dens_num / dens_den  */
+  int32_t dens_den;         /*   (Sec. III-D); dens_den > 0, dens_num >= 0            */
+  int32_t fit_n;            /* odd N of the N x N plane fit, 3..15 (Sec. III-D)       */
+  float   neg_thresh_m;     /* negative-obstacle height-difference threshold         */
+  float   neg_search_m;     /* maximum cone-search distance (Sec. III-D)             */
+} map_params_t;
+
+/* Integer constants the library derives from the parameters (host only).
+ * Rounding is half away from zero, computed in double. */
+typedef struct {
+  float   inv_r;            /* (float)(1 / (double)res_m)                             */
+  int32_t n_lo, n_hi;       /* band in voxels above ground: max(1, round(min/r)),
+                               round(max/r)                                           */
+  int64_t tau_neg_q;        /* floor(neg_thresh / r * 2^16), in Q units              */
+  int32_t search_d;         /* round(neg_search / r) pixels, 1..255                   */
+  int32_t half_fit;         /* (fit_n - 1) / 2                                        */
+} map_derived_t;
+
+/* Outputs of map_export_2d: device arrays of nx*ny elements ([x][y], y fastest).
+ * flags: bit0 height defined, bit1 positive obstacle, bit2 hard, bit3 soft,
+ * bit4 negative obstacle, bit5 slope/roughness defined.  Undefined floats are
+ * the quiet NaN 0x7FC00000. */
+typedef struct {
+  float*   height;    /* m: lowest return of the lowest occupied voxel            */
+  float*   slope;     /* rise over run of the N x N least-squares plane           */
+  float*   rough;     /* m^2: mean squared residual of that plane                 */
+  float*   density;   /* sum hits / sum (hits + passes) over the obstacle band    */
+  uint8_t* flags;
+} map_2d_t;
+
+/* One entry of the data array (Sec. III-A): returns in the voxel, rays that
+ * passed through it, and the lowest return height in Q units. */
+typedef struct {
+  int32_t hits, passes, min_qz;
+} map_voxel_t;
+
+/* Counters of the last map_insert_scan (map_get_stats synchronises). */
+typedef struct {
+  int64_t n_points;         /* points given, including non-finite ones            */
+  int64_t n_nonfinite;      /* skipped: a coordinate is NaN or infinite            */
+  int64_t n_range;          /* skipped: |u| >= 2^15 voxels or >= 2048 voxels from
+                               the sensor on an axis                               */
+  int64_t n_hits;           /* returns whose voxel lies in the window             */
+  int64_t n_pass;           /* pass increments (ray-voxel incidences)             */
+  int64_t n_distinct_pass;  /* distinct voxels passed (-1 without MAP_STATS_DISTINCT) */
+  int64_t n_distinct_hit;   /* distinct voxels hit   (-1 without MAP_STATS_DISTINCT) */
+  int64_t n_cleared;        /* window voxels reset by the recentring              */
+} map_stats_t;
+
+typedef struct map_t map_t;  /* opaque */
+
+/* Checks the parameters and derives the integer constants; host only, no HIP
+ * call.  Returns MAP_E_INVALID for any parameter outside the ranges above. */
+int32_t map_params_validate(const map_params_t* p, map_derived_t* out);
+
+/* Creates an empty map (Sec. III-A storage) on the current HIP device, bound
+ * to `stream`.  Until the first recentring the window is placed so that world
+ * point (0,0,0) lies in voxel (nx/2, ny/2, sensor_z_voxel).  Allocates about
+ * 12 bytes per voxel plus 16 bytes per column.  Synchronises. */
+int32_t map_create(const map_params_t* p, void* stream, map_t** out);
+
+/* Frees the map (synchronises its stream first).  NULL is a no-op. */
+int32_t map_destroy(map_t* m);
+
+/* Empties the map, restores the initial window and clears a sticky error. */
+int32_t map_reset(map_t* m);
+
+/* Inserts one lidar scan (Sec. III-C).
+ *  xyz_dev: device float[n][3], sensor frame, metres; non-finite = no return
+ *           (skipped, counted).  Not modified; must stay valid until the
+ *           stream reaches this work.
+ *  pose:    host float[12], row-major [R | t], sensor to world.
+ *  flags:   MAP_RECENTER, MAP_STATS_DISTINCT, MAP_FIRING(b).
+ * Each point is transformed with one fused multiply-add chain per axis
+ * (t + R0 x + R1 y + R2 z, binary32), scaled to voxel units and quantised to
+ * Q.  Its voxel, if in the window, gets hits += 1 and min_qz = min(min_qz, Qz);
+ * every other window voxel on the segment from the sensor to the point gets
+ * passes += 1 (the voxels of the segment are the distinct cells floor(X(t))
+ * in increasing t; a boundary belongs to the upper cell).  n == 0 is allowed;
+ * the recentring still happens.  Several lidars feed one map by calling this
+ * once per lidar (Sec. III-B). */
+int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float pose[12],
+                        uint32_t flags);
+
+/* Writes the 2D maps of Sec. III-D into the caller's device arrays. */
+int32_t map_export_2d(map_t* m, const map_2d_t* out_dev);
+
+/* Writes the Sec. III-A lookup table and data array:
+ *  lut_dev:   device int32[nx*ny*nz] (local linear index): rank of the voxel
+ *             among occupied voxels (hits >= 1) in increasing index, else
+ *             -1 - passes.
+ *  data_dev:  device map_voxel_t[cap] in rank order; ranks >= cap are not
+ *             written (cap may be 0 with data_dev NULL).
+ *  n_occupied_dev: device int64 receiving the number of occupied voxels M;
+ *             the caller detects truncation by M > cap.
+ *  origin_vox: host int32[3], receives the window origin (world voxel).
+ * Does not synchronise. */
+int32_t map_export_voxels(map_t* m, int32_t* lut_dev, map_voxel_t* data_dev, int64_t cap,
+                          int64_t* n_occupied_dev, int32_t origin_vox[3]);
+
+/* Sets the map state from a lookup table and data array in the format above
+ * (checkpoint / resume).  Every lut entry >= 0 must index data with hits >= 1,
+ * and no entry may be INT32_MIN.  Synchronises; on invalid content the map
+ * is left empty and MAP_E_INVALID is returned. */
+int32_t map_import_voxels(map_t* m, const int32_t* lut_dev, const map_voxel_t* data_dev,
+                          int64_t n_data, const int32_t origin_vox[3]);
+
+/* Counters of the last insert; synchronises the map's stream. */
+int32_t map_get_stats(map_t* m, map_stats_t* out);
+
+/* Current window origin (world voxel index of window voxel (0,0,0)). */
+int32_t map_get_origin(const map_t* m, int32_t origin_vox[3]);
+
+/* Waits for the map's stream and returns the map's (sticky) status. */
+int32_t map_sync(map_t* m);
+
+/* Optional per-phase timing with HIP events recorded on the map's stream
+ * around each kernel group (instrumentation for benchmarks).  Phases:
+ * MAP_PROF_SCROLL (window clears), MAP_PROF_INSERT (transform + returns +
+ * ray traversal kernel), MAP_PROF_COLUMN (column reduction), MAP_PROF_SURFACE
+ * (slope, roughness, negative obstacles), MAP_PROF_LUT (lookup-table export).
+ * map_profile_read synchronises, adds the elapsed milliseconds and launch
+ * counts since the last read into ms[MAP_PROF_N] / count[MAP_PROF_N] (host),
+ * and releases the events. */
+#define MAP_PROF_SCROLL  0
+#define MAP_PROF_INSERT  1
+#define MAP_PROF_COLUMN  2
+#define MAP_PROF_SURFACE 3
+#define MAP_PROF_LUT     4
+#define MAP_PROF_N       5
+int32_t map_profile_enable(map_t* m, int32_t enable);
+int32_t map_profile_read(map_t* m, double ms[MAP_PROF_N], int64_t count[MAP_PROF_N]);
+
+/* Static text for a status code. */
+const char* map_status_str(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GVOM_H */

@@ -1,0 +1,454 @@
+// Export kernels: the per-column reductions and the 2D maps of Sec. III-D of
+// arXiv 2109.13176, the Sec. III-A lookup table / data array, and its import.
+#include <math.h>
+
+#include "gvom_internal.h"
+
+namespace gvom {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr uint32_t kQNaN = 0x7FC00000u;
+
+__device__ __forceinline__ int32_t wrap_add(int32_t s, int32_t n) { return s >= n ? s - n : s; }
+
+// Column occupancy in window-local z order (bit z = local z), nz <= 128.
+struct Mask128 {
+  unsigned long long lo, hi;
+};
+
+__device__ __forceinline__ Mask128 local_mask(const unsigned long long* occ, int64_t col,
+                                              int W, int nz, int roz) {
+  unsigned __int128 m = occ[col * W];
+  if (W > 1) m |= (unsigned __int128)occ[col * W + 1] << 64;
+  if (roz != 0) {
+    const unsigned __int128 full =
+        nz == 128 ? ~(unsigned __int128)0 : (((unsigned __int128)1 << nz) - 1);
+    m = ((m >> roz) | (m << (nz - roz))) & full;
+  }
+  Mask128 r;
+  r.lo = (unsigned long long)m;
+  r.hi = (unsigned long long)(m >> 64);
+  return r;
+}
+
+__device__ __forceinline__ int lowest_bit(const Mask128& m) {
+  if (m.lo) return __ffsll((long long)m.lo) - 1;
+  if (m.hi) return 64 + __ffsll((long long)m.hi) - 1;
+  return -1;
+}
+
+__device__ __forceinline__ bool test_bit(const Mask128& m, int z) {
+  return z < 64 ? ((m.lo >> z) & 1ull) : ((m.hi >> (z - 64)) & 1ull);
+}
+
+// popcount of the bits below z
+__device__ __forceinline__ int rank_below(const Mask128& m, int z) {
+  if (z < 64) return __popcll(m.lo & ((1ull << z) - 1ull));
+  const int zh = z - 64;
+  return __popcll(m.lo) + __popcll(m.hi & ((1ull << zh) - 1ull));
+}
+
+// One lane per map column (window-local pixel).  Ground voxel = lowest
+// occupied voxel; height = its lowest return.  The positive-obstacle band is
+// the occupied voxels n_lo..n_hi above the ground voxel; its density is
+// sum(hits) / sum(hits + passes); hard iff that ratio exceeds num/den
+// (compared exactly in integers), soft otherwise.
+__global__ __launch_bounds__(kBlock) void k_column(ColumnArgs a) {
+  const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= nx * ny) return;
+  const int x = c / ny, y = c - x * ny;
+  const int sx = wrap_add(x + a.d.ro[0], nx), sy = wrap_add(y + a.d.ro[1], ny);
+  const int64_t scol = (int64_t)sx * ny + sy;
+  const Mask128 m = local_mask(a.occ, scol, a.d.W, nz, a.d.ro[2]);
+  const int kg = lowest_bit(m);
+  float height = __uint_as_float(kQNaN), density = __uint_as_float(kQNaN);
+  int32_t hq = INT32_MIN;
+  uint8_t f = 0;
+  if (kg >= 0) {
+    const int64_t base = scol * nz;
+    hq = a.minqz[base + wrap_add(kg + a.d.ro[2], nz)];
+    height = (float)((double)hq * a.res / 65536.0);
+    f = 1;
+    int64_t sh = 0, sa = 0;
+    int cnt = 0;
+    const int zlo = kg + a.n_lo;
+    const int zhi = min(kg + a.n_hi, nz - 1);
+    for (int z = zlo; z <= zhi; z++) {
+      if (!test_bit(m, z)) continue;
+      const int64_t e = base + wrap_add(z + a.d.ro[2], nz);
+      const int32_t h = a.hits[e];
+      sh += h;
+      sa += (int64_t)h + a.passes[e];
+      cnt++;
+    }
+    if (cnt > 0) {
+      density = (float)((double)sh / (double)sa);
+      const bool hard = sh * a.dens_den > (int64_t)a.dens_num * sa;
+      f |= 2 | (hard ? 4 : 8);
+    }
+  }
+  a.height[c] = height;
+  a.density[c] = density;
+  a.flags[c] = f;
+  a.hq[c] = hq;
+}
+
+// 2D surface maps on tiles of kTile x kTile pixels with a halo of H pixels
+// staged in LDS.  Defined pixels get the N x N least-squares plane (integer
+// normal equations, exact determinant, Cramer's rule in double); undefined
+// pixels get the four-cone negative-obstacle search.  A cone ring slice
+// holds a defined cell iff the per-row (per-column) prefix count of defined
+// cells over the slice's span is positive.
+constexpr int kTile = 32;
+
+__global__ __launch_bounds__(kBlock) void k_surface(SurfaceArgs a, int H) {
+  extern __shared__ int32_t lds[];
+  const int T = kTile + 2 * H;  // staged tile edge
+  int32_t* th = lds;                                         // [T][T] heights
+  uint16_t* rpre = (uint16_t*)(lds + T * T);                 // [T][T+1] along y
+  uint16_t* cpre = rpre + T * (T + 1);                       // [T][T+1] along x
+  const int gx0 = blockIdx.x * kTile - H, gy0 = blockIdx.y * kTile - H;
+  for (int i = threadIdx.x; i < T * T; i += kBlock) {
+    const int tx = i / T, ty = i - tx * T;
+    const int gx = gx0 + tx, gy = gy0 + ty;
+    int32_t v = INT32_MIN;
+    if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny) v = a.hq[(int64_t)gx * a.ny + gy];
+    th[i] = v;
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < 2 * T; r += kBlock) {
+    if (r < T) {  // row r: fixed x, running over y
+      uint16_t acc = 0;
+      rpre[r * (T + 1)] = 0;
+      for (int k = 0; k < T; k++) {
+        acc += th[r * T + k] != INT32_MIN;
+        rpre[r * (T + 1) + k + 1] = acc;
+      }
+    } else {  // column r - T: fixed y, running over x
+      const int cc = r - T;
+      uint16_t acc = 0;
+      cpre[cc * (T + 1)] = 0;
+      for (int k = 0; k < T; k++) {
+        acc += th[k * T + cc] != INT32_MIN;
+        cpre[cc * (T + 1) + k + 1] = acc;
+      }
+    }
+  }
+  __syncthreads();
+
+  const int h = a.half_fit, D = a.search_d;
+  for (int p = threadIdx.x; p < kTile * kTile; p += kBlock) {
+    const int px = p / kTile, py = p - px * kTile;
+    const int gx = blockIdx.x * kTile + px, gy = blockIdx.y * kTile + py;
+    if (gx >= a.nx || gy >= a.ny) continue;
+    const int tx = px + H, ty = py + H;
+    const int32_t hc = th[tx * T + ty];
+    const int64_t c = (int64_t)gx * a.ny + gy;
+    uint8_t fl = a.flags[c];
+    float slope = __uint_as_float(kQNaN), rough = __uint_as_float(kQNaN);
+    if (hc != INT32_MIN) {
+      int32_t n = 0, sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0;
+      int64_t sz = 0, sxz = 0, syz = 0;
+      for (int dx = -h; dx <= h; dx++)
+        for (int dy = -h; dy <= h; dy++) {
+          const int32_t v = th[(tx + dx) * T + ty + dy];
+          if (v == INT32_MIN) continue;
+          const int64_t dz = (int64_t)v - hc;
+          n++;
+          sx += dx;
+          sy += dy;
+          sxx += dx * dx;
+          syy += dy * dy;
+          sxy += dx * dy;
+          sz += dz;
+          sxz += dx * dz;
+          syz += dy * dz;
+        }
+      // adjugate of M = [[sxx sxy sx] [sxy syy sy] [sx sy n]] (symmetric)
+      const int64_t c00 = (int64_t)syy * n - (int64_t)sy * sy;
+      const int64_t c01 = (int64_t)sy * sx - (int64_t)sxy * n;
+      const int64_t c02 = (int64_t)sxy * sy - (int64_t)syy * sx;
+      const int64_t c11 = (int64_t)sxx * n - (int64_t)sx * sx;
+      const int64_t c12 = (int64_t)sxy * sx - (int64_t)sxx * sy;
+      const int64_t c22 = (int64_t)sxx * syy - (int64_t)sxy * sxy;
+      const int64_t det = (int64_t)sxx * c00 + (int64_t)sxy * c01 + (int64_t)sx * c02;
+      if (n >= 3 && det != 0) {
+        const double inv = 1.0 / (double)det;
+        const double bx = (double)sxz, by = (double)syz, bz = (double)sz;
+        const double al = ((double)c00 * bx + (double)c01 * by + (double)c02 * bz) * inv;
+        const double be = ((double)c01 * bx + (double)c11 * by + (double)c12 * bz) * inv;
+        const double ga = ((double)c02 * bx + (double)c12 * by + (double)c22 * bz) * inv;
+        double ss = 0.0;
+        for (int dx = -h; dx <= h; dx++)
+          for (int dy = -h; dy <= h; dy++) {
+            const int32_t v = th[(tx + dx) * T + ty + dy];
+            if (v == INT32_MIN) continue;
+            const double e = (double)((int64_t)v - hc) - (al * dx + be * dy + ga);
+            ss += e * e;
+          }
+        slope = (float)(sqrt(al * al + be * be) / 65536.0);
+        rough = (float)(ss / (double)n * a.q2m * a.q2m);
+        fl |= 32;
+      }
+    } else {
+      int64_t lo = INT64_MAX, hi = INT64_MIN;
+      int found = 0;
+      // +x / -x cones: slice = tile row tx +- d, y in [ty - d, ty + d]
+      for (int dir = -1; dir <= 1; dir += 2) {
+        for (int d = 1; d <= D; d++) {
+          const int r = tx + dir * d;
+          const int y0 = ty - d, y1 = ty + d;
+          if (rpre[r * (T + 1) + y1 + 1] - rpre[r * (T + 1) + y0] == 0) continue;
+          for (int y = y0; y <= y1; y++) {
+            const int32_t v = th[r * T + y];
+            if (v == INT32_MIN) continue;
+            found++;
+            lo = min(lo, (int64_t)v);
+            hi = max(hi, (int64_t)v);
+          }
+          break;
+        }
+      }
+      // +y / -y cones: slice = tile column ty +- d, x in [tx - d, tx + d]
+      for (int dir = -1; dir <= 1; dir += 2) {
+        for (int d = 1; d <= D; d++) {
+          const int cc = ty + dir * d;
+          const int x0 = tx - d, x1 = tx + d;
+          if (cpre[cc * (T + 1) + x1 + 1] - cpre[cc * (T + 1) + x0] == 0) continue;
+          for (int x = x0; x <= x1; x++) {
+            const int32_t v = th[x * T + cc];
+            if (v == INT32_MIN) continue;
+            found++;
+            lo = min(lo, (int64_t)v);
+            hi = max(hi, (int64_t)v);
+          }
+          break;
+        }
+      }
+      if (found >= 2 && hi - lo > a.tau_q) fl |= 16;
+    }
+    a.slope[c] = slope;
+    a.rough[c] = rough;
+    a.flags[c] = fl;
+  }
+}
+
+// Lookup-table export, pass 1: occupied voxels per block of 256 columns.
+__global__ __launch_bounds__(kBlock) void k_lut_count(LutArgs a) {
+  __shared__ int32_t part[kBlock / 64];
+  const int nx = a.d.nx, ny = a.d.ny;
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  int cnt = 0;
+  if (c < nx * ny) {
+    const int x = c / ny, y = c - x * ny;
+    const int64_t scol = (int64_t)wrap_add(x + a.d.ro[0], nx) * ny + wrap_add(y + a.d.ro[1], ny);
+    cnt = __popcll(a.occ[scol * a.d.W]);
+    if (a.d.W > 1) cnt += __popcll(a.occ[scol * a.d.W + 1]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+  if (__lane_id() == 0) part[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < kBlock / 64; w++) s += part[w];
+    a.block_base[blockIdx.x] = s;
+  }
+}
+
+// Pass 2 (one block): exclusive scan of the block counts; writes M.
+__global__ __launch_bounds__(1024) void k_lut_scan(int32_t* base, int nb, int64_t* n_occupied) {
+  __shared__ int64_t wsum[16];
+  const int t = threadIdx.x;
+  const int per = (nb + 1023) / 1024;
+  const int b0 = t * per, b1 = min(b0 + per, nb);
+  int64_t s = 0;
+  for (int b = b0; b < b1; b++) s += base[b];
+  // inclusive scan of s across the block
+  const int lane = __lane_id(), w = t >> 6;
+  int64_t v = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t u = __shfl_up(v, o);
+    if (lane >= o) v += u;
+  }
+  if (lane == 63) wsum[w] = v;
+  __syncthreads();
+  if (t == 0) {
+    int64_t acc = 0;
+    for (int k = 0; k < 16; k++) {
+      const int64_t q = wsum[k];
+      wsum[k] = acc;
+      acc += q;
+    }
+    *n_occupied = acc;
+  }
+  __syncthreads();
+  int64_t run = wsum[w] + v - s;  // exclusive prefix of this thread's range
+  for (int b = b0; b < b1; b++) {
+    const int32_t q = base[b];
+    base[b] = (int32_t)run;
+    run += q;
+  }
+}
+
+// Pass 3: each block writes the lookup table and data array of its 256
+// columns; wave w handles columns w, w+4, ...; lane = window-local z.
+__global__ __launch_bounds__(kBlock) void k_lut_write(LutArgs a) {
+  __shared__ int32_t colbase[kBlock];
+  const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, W = a.d.W, roz = a.d.ro[2];
+  const int C = nx * ny;
+  const int c0 = blockIdx.x * kBlock;
+  {
+    const int c = c0 + threadIdx.x;
+    int cnt = 0;
+    if (c < C) {
+      const int x = c / ny, y = c - x * ny;
+      const int64_t scol =
+          (int64_t)wrap_add(x + a.d.ro[0], nx) * ny + wrap_add(y + a.d.ro[1], ny);
+      cnt = __popcll(a.occ[scol * W]);
+      if (W > 1) cnt += __popcll(a.occ[scol * W + 1]);
+    }
+    colbase[threadIdx.x] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t acc = a.block_base[blockIdx.x];
+    for (int k = 0; k < kBlock; k++) {
+      const int32_t q = colbase[k];
+      colbase[k] = acc;
+      acc += q;
+    }
+  }
+  __syncthreads();
+  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+  for (int k = wv; k < kBlock; k += kBlock / 64) {
+    const int c = c0 + k;
+    if (c >= C) break;
+    const int x = c / ny, y = c - x * ny;
+    const int64_t scol = (int64_t)wrap_add(x + a.d.ro[0], nx) * ny + wrap_add(y + a.d.ro[1], ny);
+    const Mask128 m = local_mask(a.occ, scol, W, nz, roz);
+    const int64_t sbase = scol * nz;
+    const int64_t lbase = (int64_t)c * nz;
+    for (int z = lane; z < nz; z += 64) {
+      const int64_t e = sbase + wrap_add(z + roz, nz);
+      int32_t v;
+      if (test_bit(m, z)) {
+        const int32_t rank = colbase[k] + rank_below(m, z);
+        v = rank;
+        if (rank < a.cap) {
+          map_voxel_t d;
+          d.hits = a.hits[e];
+          d.passes = a.passes[e];
+          d.min_qz = a.minqz[e];
+          a.data[rank] = d;
+        }
+      } else {
+        v = -1 - a.passes[e];
+      }
+      a.lut[lbase + z] = v;
+    }
+  }
+}
+
+// Import: one wave per window-local column; lane = local z.
+__global__ __launch_bounds__(kBlock) void k_import(Dims d, const int32_t* lut,
+                                                   const map_voxel_t* data, int64_t n_data,
+                                                   int32_t* hits, int32_t* passes,
+                                                   int32_t* minqz, unsigned long long* occ,
+                                                   int32_t* err) {
+  const int lane = __lane_id();
+  const int64_t c = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  if (c >= (int64_t)nx * ny) return;
+  const int x = (int)(c / ny), y = (int)(c - (int64_t)x * ny);
+  const int64_t scol = (int64_t)wrap_add(x + d.ro[0], nx) * ny + wrap_add(y + d.ro[1], ny);
+  unsigned long long w0 = 0, w1 = 0;
+  for (int zb = 0; zb < nz; zb += 64) {
+    const int z = zb + lane;
+    bool occd = false;
+    if (z < nz) {
+      const int32_t v = lut[c * nz + z];
+      const int sz = wrap_add(z + d.ro[2], nz);
+      const int64_t e = scol * nz + sz;
+      int32_t h = 0, p = 0, mq = INT32_MAX;
+      if (v >= 0) {
+        if (v < n_data && data[v].hits >= 1) {
+          h = data[v].hits;
+          p = data[v].passes;
+          mq = data[v].min_qz;
+          occd = true;
+        } else {
+          atomicOr(err, 1);
+        }
+      } else if (v == INT32_MIN) {
+        atomicOr(err, 1);
+      } else {
+        p = -1 - v;
+      }
+      hits[e] = h;
+      passes[e] = p;
+      minqz[e] = mq;
+      if (occd) {
+        if (sz < 64) w0 |= 1ull << sz; else w1 |= 1ull << (sz - 64);
+      }
+    }
+  }
+  // combine the lanes' bits
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    w0 |= __shfl_xor(w0, o);
+    w1 |= __shfl_xor(w1, o);
+  }
+  if (lane == 0) {
+    occ[scol * d.W] = w0;
+    if (d.W > 1) occ[scol * d.W + 1] = w1;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_column(const ColumnArgs& a, hipStream_t s) {
+  const int C = a.d.nx * a.d.ny;
+  hipLaunchKernelGGL(k_column, dim3((C + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_surface(const SurfaceArgs& a, hipStream_t s) {
+  const int H = a.search_d > a.half_fit ? a.search_d : a.half_fit;
+  const int T = kTile + 2 * H;
+  const size_t lds = (size_t)T * T * 4 + 2 * (size_t)T * (T + 1) * 2;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_surface,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  dim3 g((a.nx + kTile - 1) / kTile, (a.ny + kTile - 1) / kTile);
+  hipLaunchKernelGGL(k_surface, g, dim3(kBlock), lds, s, a, H);
+  return hipGetLastError();
+}
+
+hipError_t launch_lut(const LutArgs& a, hipStream_t s) {
+  const int C = a.d.nx * a.d.ny;
+  const int nb = (C + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_lut_count, dim3(nb), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_lut_scan, dim3(1), dim3(1024), 0, s, a.block_base, nb, a.n_occupied);
+  hipLaunchKernelGGL(k_lut_write, dim3(nb), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_import(const Dims& d, const int32_t* lut, const map_voxel_t* data,
+                         int64_t n_data, int32_t* hits, int32_t* passes, int32_t* minqz,
+                         unsigned long long* occ, int32_t* err, hipStream_t s) {
+  const int64_t threads = (int64_t)d.nx * d.ny * 64;
+  hipLaunchKernelGGL(k_import, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, s, d, lut, data, n_data, hits, passes, minqz, occ, err);
+  return hipGetLastError();
+}
+
+}  // namespace gvom

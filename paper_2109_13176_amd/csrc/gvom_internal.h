@@ -1,0 +1,99 @@
+// Internal declarations shared by the host code and the kernels of libgvom.
+//
+// Storage layout on the device (per map):
+//   hits, passes, min_qz : int32[nx][ny][nz], z fastest, TOROIDAL: world voxel
+//                          g is stored at (g mod nx, g mod ny, g mod nz), so a
+//                          moving window only clears the slabs it enters.
+//   occ                  : uint64[nx*ny][W], W = ceil(nz/64): bit (s mod 64) of
+//                          word s/64 is set iff storage z = s of that column
+//                          holds a return (hits >= 1).
+// "ro" is the ring offset origin mod n per axis: window-local coordinate l
+// is stored at (l + ro) mod n.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gvom.h"
+
+namespace gvom {
+
+struct Dims {
+  int32_t nx, ny, nz, W;  // W = occupancy words per column
+  int32_t ro[3];          // ring offsets
+};
+
+struct InsertArgs {
+  const float* xyz;
+  int32_t n;
+  int32_t fw;             // firing width (1 = identity order)
+  int32_t azimuths;       // n / fw
+  float R[9], t[3];
+  float inv_r;
+  int32_t S[3];           // sensor, Q units
+  int32_t O[3];           // window origin, world voxel
+  Dims d;
+  int32_t* hits;
+  int32_t* passes;
+  int32_t* minqz;
+  unsigned long long* occ;
+  unsigned long long* stats;   // [n_nonfinite, n_range, n_hits, n_pass, dpass, dhit]
+  uint32_t* touch;             // distinct-voxel bitmaps [2][V/32] or null
+};
+
+struct ColumnArgs {
+  Dims d;
+  const int32_t* hits;
+  const int32_t* passes;
+  const int32_t* minqz;
+  const unsigned long long* occ;
+  double res;
+  int32_t n_lo, n_hi;
+  int32_t dens_num, dens_den;
+  float* height;
+  float* density;
+  uint8_t* flags;
+  int32_t* hq;            // ground height Q per local pixel, INT32_MIN = undefined
+};
+
+struct SurfaceArgs {
+  int32_t nx, ny;
+  const int32_t* hq;
+  int32_t half_fit;
+  int32_t search_d;
+  int64_t tau_q;
+  double q2m;             // metres per Q unit = res / 65536
+  float* slope;
+  float* rough;
+  uint8_t* flags;
+};
+
+struct LutArgs {
+  Dims d;
+  const int32_t* hits;
+  const int32_t* passes;
+  const int32_t* minqz;
+  const unsigned long long* occ;
+  int32_t* lut;
+  map_voxel_t* data;
+  int64_t cap;
+  int32_t* block_base;    // per 256-column block: exclusive rank base
+  int64_t* n_occupied;
+};
+
+// Launchers (all enqueue on `s`, return the launch status).
+hipError_t launch_clear_box(const Dims& d, int32_t* hits, int32_t* passes, int32_t* minqz,
+                            int32_t x0, int32_t cx, int32_t y0, int32_t cy, int32_t z0,
+                            int32_t cz, hipStream_t s);
+hipError_t launch_clear_occ(const Dims& d, unsigned long long* occ, int32_t x0, int32_t cx,
+                            int32_t y0, int32_t cy, unsigned long long keep0,
+                            unsigned long long keep1, hipStream_t s);
+hipError_t launch_insert(const InsertArgs& a, bool distinct, hipStream_t s);
+hipError_t launch_column(const ColumnArgs& a, hipStream_t s);
+hipError_t launch_surface(const SurfaceArgs& a, hipStream_t s);
+hipError_t launch_lut(const LutArgs& a, hipStream_t s);
+hipError_t launch_import(const Dims& d, const int32_t* lut, const map_voxel_t* data,
+                         int64_t n_data, int32_t* hits, int32_t* passes, int32_t* minqz,
+                         unsigned long long* occ, int32_t* err, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+
+}  // namespace gvom

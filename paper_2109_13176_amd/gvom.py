@@ -1,0 +1,270 @@
+"""Thin Python binding of libgvom.so (include/gvom.h), argument marshalling only.
+
+Every function has the name of the C entry point it calls.  Device buffers are
+torch CUDA (HIP) tensors; torch supplies device memory and streams, every step
+of the mapping path runs in the library's HIP kernels.  There is no CPU path:
+if the library is not built, or a tensor is not on the GPU, the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgvom.so")
+
+MAP_OK, MAP_E_INVALID, MAP_E_POSE, MAP_E_SENSOR_OUTSIDE = 0, -1, -2, -3
+MAP_E_RANGE, MAP_E_CAPACITY, MAP_E_OOM, MAP_E_DEVICE = -4, -5, -6, -7
+MAP_RECENTER = 1
+MAP_STATS_DISTINCT = 2
+
+
+def MAP_FIRING(b: int) -> int:
+    return (int(b) & 0xFFFF) << 16
+
+
+class map_params_t(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("res_m", ctypes.c_float), ("sensor_z_voxel", ctypes.c_int32),
+                ("obs_min_m", ctypes.c_float), ("obs_max_m", ctypes.c_float),
+                ("dens_num", ctypes.c_int32), ("dens_den", ctypes.c_int32),
+                ("fit_n", ctypes.c_int32), ("neg_thresh_m", ctypes.c_float),
+                ("neg_search_m", ctypes.c_float)]
+
+
+class map_derived_t(ctypes.Structure):
+    _fields_ = [("inv_r", ctypes.c_float), ("n_lo", ctypes.c_int32), ("n_hi", ctypes.c_int32),
+                ("tau_neg_q", ctypes.c_int64), ("search_d", ctypes.c_int32),
+                ("half_fit", ctypes.c_int32)]
+
+
+class map_2d_t(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_void_p), ("slope", ctypes.c_void_p),
+                ("rough", ctypes.c_void_p), ("density", ctypes.c_void_p),
+                ("flags", ctypes.c_void_p)]
+
+
+class map_stats_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("n_points", "n_nonfinite", "n_range", "n_hits", "n_pass",
+                 "n_distinct_pass", "n_distinct_hit", "n_cleared")]
+
+
+EXPORTED = [
+    "map_params_validate", "map_create", "map_destroy", "map_reset", "map_insert_scan",
+    "map_export_2d", "map_export_voxels", "map_import_voxels", "map_get_stats",
+    "map_get_origin", "map_sync", "map_status_str", "map_profile_enable", "map_profile_read",
+]
+PROF_PHASES = ("scroll", "insert", "column", "surface", "lut")
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libgvom.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.map_params_validate.argtypes = [ctypes.POINTER(map_params_t),
+                                          ctypes.POINTER(map_derived_t)]
+        L.map_create.argtypes = [ctypes.POINTER(map_params_t), P, ctypes.POINTER(P)]
+        L.map_destroy.argtypes = [P]
+        L.map_reset.argtypes = [P]
+        L.map_insert_scan.argtypes = [P, P, I64, P, ctypes.c_uint32]
+        L.map_export_2d.argtypes = [P, ctypes.POINTER(map_2d_t)]
+        L.map_export_voxels.argtypes = [P, P, P, I64, P, P]
+        L.map_import_voxels.argtypes = [P, P, P, I64, P]
+        L.map_get_stats.argtypes = [P, ctypes.POINTER(map_stats_t)]
+        L.map_get_origin.argtypes = [P, P]
+        L.map_sync.argtypes = [P]
+        L.map_profile_enable.argtypes = [P, I32]
+        L.map_profile_read.argtypes = [P, P, P]
+        L.map_status_str.argtypes = [I32]
+        L.map_status_str.restype = ctypes.c_char_p
+        for f in EXPORTED:
+            if f != "map_status_str":
+                getattr(L, f).restype = I32
+        _lib = L
+    return _lib
+
+
+def _dev(t, dtype=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _params(p: dict) -> map_params_t:
+    return map_params_t(**{k: p[k] for k, _ in map_params_t._fields_})
+
+
+def map_status_str(status: int) -> str:
+    return lib().map_status_str(status).decode()
+
+
+def map_params_validate(params: dict):
+    d = map_derived_t()
+    s = lib().map_params_validate(ctypes.byref(_params(params)), ctypes.byref(d))
+    return s, {k: getattr(d, k) for k, _ in map_derived_t._fields_}
+
+
+def map_create(params: dict, stream=None):
+    """Returns (status, handle).  `stream` is a torch.cuda.Stream or None (current)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    h = ctypes.c_void_p()
+    s = lib().map_create(ctypes.byref(_params(params)), ctypes.c_void_p(stream.cuda_stream),
+                         ctypes.byref(h))
+    return s, h
+
+
+def map_destroy(h) -> int:
+    return lib().map_destroy(h)
+
+
+def map_reset(h) -> int:
+    return lib().map_reset(h)
+
+
+def map_insert_scan(h, xyz, pose, flags: int = 0) -> int:
+    import torch
+    n = 0 if xyz is None else xyz.shape[0]
+    ptr = ctypes.c_void_p(0) if n == 0 else _dev(xyz, torch.float32, "xyz")
+    if n and (xyz.dim() != 2 or xyz.shape[1] != 3):
+        raise ValueError("xyz must be [n, 3]")
+    pose = np.ascontiguousarray(pose, dtype=np.float32).reshape(12)
+    return lib().map_insert_scan(h, ptr, n, pose.ctypes.data_as(ctypes.c_void_p), flags)
+
+
+def map_export_2d(h, out: dict) -> int:
+    import torch
+    o = map_2d_t(_dev(out["height"], torch.float32, "height"),
+                 _dev(out["slope"], torch.float32, "slope"),
+                 _dev(out["rough"], torch.float32, "rough"),
+                 _dev(out["density"], torch.float32, "density"),
+                 _dev(out["flags"], torch.uint8, "flags"))
+    return lib().map_export_2d(h, ctypes.byref(o))
+
+
+def map_export_voxels(h, lut, data, n_occupied):
+    """lut int32[V], data int32[cap, 3] (or None), n_occupied int64[1]; -> (status, origin)."""
+    import torch
+    cap = 0 if data is None else data.shape[0]
+    dptr = ctypes.c_void_p(0) if data is None else _dev(data, torch.int32, "data")
+    origin = np.zeros(3, np.int32)
+    s = lib().map_export_voxels(h, _dev(lut, torch.int32, "lut"), dptr, cap,
+                                _dev(n_occupied, torch.int64, "n_occupied"),
+                                origin.ctypes.data_as(ctypes.c_void_p))
+    return s, origin
+
+
+def map_import_voxels(h, lut, data, origin) -> int:
+    import torch
+    n = 0 if data is None else data.shape[0]
+    dptr = ctypes.c_void_p(0) if data is None else _dev(data, torch.int32, "data")
+    origin = np.ascontiguousarray(origin, dtype=np.int32).reshape(3)
+    return lib().map_import_voxels(h, _dev(lut, torch.int32, "lut"), dptr, n,
+                                   origin.ctypes.data_as(ctypes.c_void_p))
+
+
+def map_get_stats(h):
+    st = map_stats_t()
+    s = lib().map_get_stats(h, ctypes.byref(st))
+    return s, {k: getattr(st, k) for k, _ in map_stats_t._fields_}
+
+
+def map_get_origin(h):
+    o = np.zeros(3, np.int32)
+    s = lib().map_get_origin(h, o.ctypes.data_as(ctypes.c_void_p))
+    return s, o
+
+
+def map_sync(h) -> int:
+    return lib().map_sync(h)
+
+
+def map_profile_enable(h, enable: bool) -> int:
+    return lib().map_profile_enable(h, 1 if enable else 0)
+
+
+def map_profile_read(h):
+    """-> (status, {phase: (total_ms, launches)})"""
+    ms = np.zeros(len(PROF_PHASES), np.float64)
+    cnt = np.zeros(len(PROF_PHASES), np.int64)
+    s = lib().map_profile_read(h, ms.ctypes.data_as(ctypes.c_void_p),
+                               cnt.ctypes.data_as(ctypes.c_void_p))
+    return s, {p: (float(ms[i]), int(cnt[i])) for i, p in enumerate(PROF_PHASES)}
+
+
+class VoxelMap:
+    """Owns one map and its export buffers (torch tensors on the current device)."""
+
+    def __init__(self, params: dict, stream=None):
+        import torch
+        self.params = dict(params)
+        s, self.h = map_create(params, stream)
+        if s != MAP_OK:
+            raise RuntimeError(f"map_create: {map_status_str(s)}")
+        nx, ny, nz = params["nx"], params["ny"], params["nz"]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.out2d = {k: torch.empty((nx, ny), dtype=torch.float32, device=dev)
+                      for k in ("height", "slope", "rough", "density")}
+        self.out2d["flags"] = torch.empty((nx, ny), dtype=torch.uint8, device=dev)
+        self.lut = torch.empty(nx * ny * nz, dtype=torch.int32, device=dev)
+        self.n_occ = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.data = None
+
+    def close(self):
+        if self.h:
+            map_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, s, what):
+        if s != MAP_OK:
+            raise RuntimeError(f"{what}: {map_status_str(s)}")
+
+    def insert(self, xyz, pose, flags=0):
+        self._check(map_insert_scan(self.h, xyz, pose, flags), "map_insert_scan")
+
+    def export_2d(self):
+        self._check(map_export_2d(self.h, self.out2d), "map_export_2d")
+        return self.out2d
+
+    def export_voxels(self, cap: int | None = None):
+        import torch
+        V = self.lut.numel()
+        cap = V if cap is None else cap
+        if self.data is None or self.data.shape[0] != cap:
+            self.data = torch.empty((max(cap, 1), 3), dtype=torch.int32, device=self.lut.device)
+        s, origin = map_export_voxels(self.h, self.lut, self.data[:cap] if cap else None,
+                                      self.n_occ)
+        self._check(s, "map_export_voxels")
+        return self.lut, self.data, self.n_occ, origin
+
+    def stats(self):
+        s, st = map_get_stats(self.h)
+        self._check(s, "map_get_stats")
+        return st
+
+    def origin(self):
+        return map_get_origin(self.h)[1]
+
+    def sync(self):
+        self._check(map_sync(self.h), "map_sync")

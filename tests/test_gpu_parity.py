@@ -1,0 +1,240 @@
+"""HIP path vs oracle, element by element, on seeded inputs (needs an MI355X)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from conftest import params
+from parity_util import Pair, compare_all, compare_2d, compare_voxels
+from synth import scenegen
+
+pytestmark = pytest.mark.gpu
+
+
+def _rot(yaw, pitch, roll):
+    return scenegen.rot_zyx(yaw, pitch, roll)
+
+
+def _cloud(rng, n, radius):
+    """Points in a ball of `radius` around the sensor (sensor frame), 5% NaN."""
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True) + 1e-12
+    p = d * (radius * rng.uniform(size=(n, 1)) ** 0.5)
+    p[rng.uniform(size=n) < 0.05] = np.nan
+    return p.astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 257, 3001])
+def test_ragged_clouds_tiny_map(n):
+    rng = np.random.default_rng(100 + n)
+    pair = Pair(params(16, 16, 16, 0.5, szv=7))
+    try:
+        pose = scenegen.pose12(_rot(0.3, 0.1, -0.2), [0.7, -0.4, 0.25])
+        assert pair.insert(_cloud(rng, n, 6.0), pose, 0) == 0
+        compare_all(pair, distinct=False)
+    finally:
+        pair.close()
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 16, 0.5), (18, 10, 12, 0.25), (40, 26, 7, 0.3),
+                                  (32, 32, 64, 0.2), (30, 34, 96, 0.1), (20, 22, 128, 0.15),
+                                  (24, 24, 48, 0.4)])
+def test_shapes_and_distinct_counts(dims):
+    nx, ny, nz, res = dims
+    rng = np.random.default_rng(nx * 1000 + nz)
+    pair = Pair(params(nx, ny, nz, res))
+    try:
+        for k in range(3):
+            ang = rng.uniform(-np.pi, np.pi, 3) * np.array([1, 0.3, 0.3])
+            pose = scenegen.pose12(_rot(*ang), rng.uniform(-1, 1, 3) * res * 3)
+            pts = _cloud(rng, 4000, 0.6 * max(nx, ny, nz) * res)
+            assert pair.insert(pts, pose, 2) == 0  # MAP_STATS_DISTINCT
+            compare_all(pair, distinct=True)
+    finally:
+        pair.close()
+
+
+def test_single_scan_16beam_scene():
+    w = scenegen.single_scan_16beam(seed=1)
+    pair = Pair(w["params"])
+    try:
+        assert pair.insert(w["scans"][0], w["poses"][0], 2, firing=16) == 0
+        n, g, o = compare_all(pair, distinct=True)
+        assert n > 1000
+        f = g["flags"]
+        assert (f & 4).any() and (f & 8).any() and (f & 16).any()
+    finally:
+        pair.close()
+
+
+def test_firing_hint_does_not_change_results():
+    w = scenegen.single_scan_16beam(seed=5)
+    outs = []
+    for fw in (0, 16, 32):
+        pair = Pair(w["params"])
+        pair.insert(w["scans"][0], w["poses"][0], 0, firing=fw)
+        lut, data, n_occ, _ = pair.g.export_voxels()
+        o2 = pair.g.export_2d()
+        outs.append((lut.cpu().numpy().copy(), data[:int(n_occ.item())].cpu().numpy().copy(),
+                     {k: v.cpu().numpy().copy() for k, v in o2.items()}))
+        pair.close()
+    for lut, data, o2 in outs[1:]:
+        assert (lut == outs[0][0]).all() and (data == outs[0][1]).all()
+        for k in o2:
+            assert (o2[k].view(np.uint8) == outs[0][2][k].view(np.uint8)).all(), k
+
+
+def test_moving_window_sequence():
+    """Recentring every scan: scrolls in x, y and z (toroidal wrap), one jump
+    larger than the window (full clear), general rotations."""
+    rng = np.random.default_rng(7)
+    p = params(48, 40, 20, 0.5, szv=8)
+    pair = Pair(p)
+    try:
+        pos = np.zeros(3)
+        for k in range(14):
+            if k == 9:
+                pos = pos + np.array([40.0, -3.0, 0.0])  # leaves the window entirely
+            else:
+                pos = pos + rng.uniform(-1.6, 1.6, 3) * np.array([1, 1, 0.6])
+            ang = rng.uniform(-np.pi, np.pi, 3) * np.array([1, 0.15, 0.15])
+            pose = scenegen.pose12(_rot(*ang), pos)
+            pts = _cloud(rng, 3000, 14.0)
+            fl = 1 if k % 4 != 3 else 0  # some inserts without recentring
+            st = pair.insert(pts, pose, fl)
+            assert st in (0, -3)
+            if st == 0:
+                compare_all(pair)
+    finally:
+        pair.close()
+
+
+def _import_both(pair, cols, nz):
+    """Hand-filled voxel states pushed into both maps through the import calls."""
+    nx, ny = pair.params["nx"], pair.params["ny"]
+    V = nx * ny * nz
+    lut = np.full(V, -1, np.int32)
+    data = []
+    for (x, y), vox in cols.items():
+        for z, (h, pz, mq) in vox.items():
+            i = (x * ny + y) * nz + z
+            if h > 0:
+                lut[i] = len(data)
+                data.append((h, pz, mq))
+            else:
+                lut[i] = -1 - pz
+    data = np.array(data, np.int32).reshape(-1, 3)
+    origin = np.array([-5, 7, -3], np.int32)
+    from paper_2109_13176_amd import gvom
+    s = gvom.map_import_voxels(pair.g.h, torch.as_tensor(lut, device="cuda"),
+                               torch.as_tensor(data, device="cuda"), origin)
+    assert s == 0
+    assert pair.o.import_voxels(lut, data, origin) == 0
+
+
+def test_import_column_rules_and_negative_search():
+    nz, Q = 32, 65536
+    p = params(40, 36, nz, 0.4)
+    pair = Pair(p)
+    try:
+        rng = np.random.default_rng(3)
+        cols = {}
+        base = lambda z: (z - 3) * Q + 1234  # noqa: E731  (world z; origin z = -3)
+        for x in range(40):
+            for y in range(36):
+                if rng.uniform() < 0.45:
+                    continue  # unobserved column
+                g = int(rng.integers(2, 6)) if x < 20 else int(rng.integers(8, 11))
+                vox = {g: (int(rng.integers(1, 9)), int(rng.integers(0, 5)), base(g))}
+                for z in range(g + 1, min(nz, g + 9)):
+                    r = rng.uniform()
+                    if r < 0.2:
+                        vox[z] = (int(rng.integers(1, 12)), int(rng.integers(0, 12)), base(z))
+                    elif r < 0.4:
+                        vox[z] = (0, int(rng.integers(1, 40)), 0)
+                cols[(x, y)] = vox
+        # exact equality case of the density rule
+        cols[(0, 0)] = {2: (3, 0, base(2)), 4: (5, 5, base(4))}
+        _import_both(pair, cols, nz)
+        compare_voxels(pair)
+        g, o = compare_2d(pair)
+        assert (g["flags"] & 16).any() and (g["flags"] & 4).any() and (g["flags"] & 8).any()
+        assert g["flags"][0, 0] & 8
+    finally:
+        pair.close()
+
+
+def test_export_capacity_and_import_roundtrip():
+    w = scenegen.single_scan_16beam(seed=2)
+    pair = Pair(w["params"])
+    try:
+        pair.insert(w["scans"][0], w["poses"][0], 0, firing=16)
+        lut, data, n_occ, origin = pair.g.export_voxels()
+        M = int(n_occ.item())
+        full = data[:M].clone()
+        lut2, data2, n2, _ = pair.g.export_voxels(cap=M // 2)
+        torch.cuda.synchronize()
+        assert int(n2.item()) == M
+        assert (data2[:M // 2] == full[:M // 2]).all()
+        assert (lut2 == lut).all()
+        # resume: a fresh map imported from the export equals the original
+        from paper_2109_13176_amd import gvom
+        other = gvom.VoxelMap(w["params"])
+        assert gvom.map_import_voxels(other.h, lut.clone(), full, origin) == 0
+        l3, d3, n3, o3 = other.export_voxels()
+        torch.cuda.synchronize()
+        assert (l3 == lut).all() and (d3[:M] == full).all() and (o3 == origin).all()
+        # invalid content is rejected and leaves the map empty
+        bad = lut.clone()
+        bad[0] = M + 5
+        assert gvom.map_import_voxels(other.h, bad, full, origin) == gvom.MAP_E_INVALID
+        l4, _, n4, _ = other.export_voxels()
+        torch.cuda.synchronize()
+        assert int(n4.item()) == 0
+        other.close()
+    finally:
+        pair.close()
+
+
+def test_error_paths():
+    from paper_2109_13176_amd import gvom
+    p = params(16, 16, 16, 0.5)
+    m = gvom.VoxelMap(p)
+    pts = torch.zeros((4, 3), device="cuda")
+    good = scenegen.pose12(np.eye(3), [0.1, 0.2, 0.3])
+    assert gvom.map_insert_scan(m.h, pts, good, 0) == 0
+    lut0 = m.export_voxels()[0].clone()
+    bad = good.copy()
+    bad[5] = np.inf
+    assert gvom.map_insert_scan(m.h, pts, bad, 0) == gvom.MAP_E_POSE
+    far = scenegen.pose12(np.eye(3), [100.0, 0, 0])
+    assert gvom.map_insert_scan(m.h, pts, far, 0) == gvom.MAP_E_SENSOR_OUTSIDE
+    huge = scenegen.pose12(np.eye(3), [1e6, 0, 0])
+    assert gvom.map_insert_scan(m.h, pts, huge, 1) == gvom.MAP_E_RANGE
+    assert gvom.map_insert_scan(m.h, pts, good, 4) == gvom.MAP_E_INVALID
+    assert gvom.lib().map_insert_scan(m.h, None, 5, good.ctypes.data, 0) == gvom.MAP_E_INVALID
+    assert gvom.lib().map_insert_scan(m.h, pts.data_ptr(), -1, good.ctypes.data, 0) == gvom.MAP_E_INVALID
+    assert (m.export_voxels()[0] == lut0).all()  # errors left the map unchanged
+    assert gvom.map_sync(m.h) == 0
+    m.close()
+    bp = dict(p)
+    bp["fit_n"] = 4
+    s, h = gvom.map_create(bp)
+    assert s == gvom.MAP_E_INVALID
+
+
+def test_reset_and_repeat_bit_identical():
+    w = scenegen.single_scan_16beam(seed=3)
+    from paper_2109_13176_amd import gvom
+    m = gvom.VoxelMap(w["params"])
+    xyz = w["scans"][0].cuda()
+    res = []
+    for _ in range(2):
+        m.insert(xyz, w["poses"][0], gvom.MAP_FIRING(16))
+        m.insert(xyz, w["poses"][0], 0)
+        lut, data, n, _ = m.export_voxels()
+        res.append((lut.cpu().numpy().copy(), data[:int(n.item())].cpu().numpy().copy()))
+        assert gvom.map_reset(m.h) == 0
+    assert (res[0][0] == res[1][0]).all() and (res[0][1] == res[1][1]).all()
+    m.close()
