@@ -83,7 +83,7 @@ typedef struct {
   int32_t n_lo, n_hi;       /* band in voxels above ground: max(1, round(min/r)),
                                round(max/r)                                           */
   int64_t tau_neg_q;        /* floor(neg_thresh / r * 2^16), in Q units              */
-  int32_t search_d;         /* round(neg_search / r) pixels, 1..255                   */
+  int32_t search_d;         /* round(neg_search / r) pixels, 1..64                    */
   int32_t half_fit;         /* (fit_n - 1) / 2                                        */
 } map_derived_t;
 
@@ -184,6 +184,18 @@ int32_t map_get_origin(const map_t* m, int32_t origin_vox[3]);
 
 /* Waits for the map's stream and returns the map's (sticky) status. */
 int32_t map_sync(map_t* m);
+
+/* Launch tuning (performance only: results are bit-identical for every
+ * setting).  seg_len: dominant-axis voxels per ray segment of the traversal
+ * pass, 1..1024 (default 32); trace_waves_per_cu: resident waves per compute
+ * unit requested for the traversal grid, 1..32 (default 32).  A field <= 0
+ * keeps the current value. */
+typedef struct {
+  int32_t seg_len;
+  int32_t trace_waves_per_cu;
+} map_tuning_t;
+int32_t map_set_tuning(map_t* m, const map_tuning_t* t);
+int32_t map_get_tuning(const map_t* m, map_tuning_t* out);
 
 /* Optional per-phase timing with HIP events recorded on the map's stream
  * around each kernel group (instrumentation for benchmarks).  Phases:

@@ -65,7 +65,7 @@ int32_t orc_derive(const orc_params* p, orc_consts* c) {
   c->search_d = (int32_t)lround((double)p->neg_search_m / r);
   c->half_fit = (p->fit_n - 1) / 2;
   if (c->n_hi < c->n_lo) return ORC_E_INVALID;
-  if (c->search_d < 1 || c->search_d > 255) return ORC_E_INVALID;
+  if (c->search_d < 1 || c->search_d > 64) return ORC_E_INVALID;
   return ORC_OK;
 }
 

@@ -29,6 +29,15 @@ struct map_t {
   unsigned long long* stats;  // 8 counters
   int32_t* err;
   uint32_t* touch;            // distinct-voxel bitmaps, allocated on first use
+  int4* items;                // ray segments of the current insert
+  int64_t item_cap;
+  unsigned long long* part_rays;   // per-block counters of the ray pass
+  unsigned long long* part_trace;  // per-block counters of the traversal pass
+  int64_t part_rays_cap, part_trace_cap;
+  int64_t last_ray_blocks, last_trace_blocks;
+  int32_t seg_len;
+  int32_t trace_wpc;
+  int32_t n_cu;
   int32_t sticky;
   int64_t last_points, last_cleared;
   bool last_distinct;
@@ -198,7 +207,7 @@ int32_t map_params_validate(const map_params_t* p, map_derived_t* out) {
   c.search_d = (int32_t)lround((double)p->neg_search_m / r);
   c.half_fit = (p->fit_n - 1) / 2;
   if (c.n_hi < c.n_lo) return MAP_E_INVALID;
-  if (c.search_d < 1 || c.search_d > 255) return MAP_E_INVALID;
+  if (c.search_d < 1 || c.search_d > 64) return MAP_E_INVALID;
   if (out) *out = c;
   return MAP_OK;
 }
@@ -214,16 +223,21 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   m->p = *p;
   m->c = c;
   m->stream = (hipStream_t)stream;
-  if (hipGetDevice(&m->device) != hipSuccess) {
+  if (hipGetDevice(&m->device) != hipSuccess ||
+      hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, m->device) !=
+          hipSuccess) {
     delete m;
     return MAP_E_DEVICE;
   }
+  m->seg_len = 32;
+  m->trace_wpc = 32;
+  m->part_trace_cap = (int64_t)m->n_cu * 32 / 4 + 1;
   m->d.nx = p->nx;
   m->d.ny = p->ny;
   m->d.nz = p->nz;
   m->d.W = (p->nz + 63) / 64;
   const int64_t V = n_vox(m), C = n_col(m);
-  const int64_t nb = (C + 255) / 256;
+  const int64_t nb = (C + 63) / 64;
   hipError_t e = dmalloc(&m->hits, V * 4);
   if (e == hipSuccess) e = dmalloc(&m->passes, V * 4);
   if (e == hipSuccess) e = dmalloc(&m->minqz, V * 4);
@@ -232,6 +246,7 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   if (e == hipSuccess) e = dmalloc(&m->block_base, nb * 4);
   if (e == hipSuccess) e = dmalloc(&m->stats, 8 * 8);
   if (e == hipSuccess) e = dmalloc(&m->err, 4);
+  if (e == hipSuccess) e = dmalloc(&m->part_trace, m->part_trace_cap * 16);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     map_destroy(m);
@@ -263,6 +278,9 @@ int32_t map_destroy(map_t* m) {
   (void)hipFree(m->stats);
   (void)hipFree(m->err);
   (void)hipFree(m->touch);
+  (void)hipFree(m->items);
+  (void)hipFree(m->part_rays);
+  (void)hipFree(m->part_trace);
   delete m;
   return MAP_OK;
 }
@@ -276,6 +294,8 @@ int32_t map_reset(map_t* m) {
   m->last_points = 0;
   m->last_cleared = 0;
   m->last_distinct = false;
+  m->last_ray_blocks = 0;
+  m->last_trace_blocks = 0;
   hipError_t e = clear_all(m);
   if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, 64, m->stream);
   return dev_status(m, e);
@@ -295,6 +315,33 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
     S[i] = (int32_t)floorf(u * 65536.0f);
     sv[i] = S[i] >> 16;
   }
+  // segment buffer for the traversal pass (grows before any work is enqueued)
+  const int64_t need = n > 0 ? gvom::segment_capacity(n, m->d, m->seg_len) : 0;
+  if (need > m->item_cap) {
+    if (hipStreamSynchronize(m->stream) != hipSuccess) return dev_status(m, hipErrorUnknown);
+    (void)hipFree(m->items);
+    m->items = nullptr;
+    m->item_cap = 0;
+    if (dmalloc(&m->items, (size_t)need * sizeof(int4)) != hipSuccess) {
+      (void)hipGetLastError();
+      m->items = nullptr;
+      return MAP_E_OOM;
+    }
+    m->item_cap = need;
+  }
+  const int64_t ray_blocks = (n + gvom::kRayBlock - 1) / gvom::kRayBlock;
+  if (ray_blocks > m->part_rays_cap) {
+    if (hipStreamSynchronize(m->stream) != hipSuccess) return dev_status(m, hipErrorUnknown);
+    (void)hipFree(m->part_rays);
+    m->part_rays = nullptr;
+    m->part_rays_cap = 0;
+    if (dmalloc(&m->part_rays, (size_t)ray_blocks * 32) != hipSuccess) {
+      (void)hipGetLastError();
+      m->part_rays = nullptr;
+      return MAP_E_OOM;
+    }
+    m->part_rays_cap = ray_blocks;
+  }
   hipError_t e = hipSuccess;
   if (flags & MAP_RECENTER) {
     const int32_t o[3] = {sv[0] - m->p.nx / 2, sv[1] - m->p.ny / 2,
@@ -313,6 +360,8 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
   const bool distinct = (flags & MAP_STATS_DISTINCT) != 0;
   m->last_points = n;
   m->last_distinct = distinct;
+  m->last_ray_blocks = 0;
+  m->last_trace_blocks = 0;
   if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, 64, m->stream);
   if (distinct && e == hipSuccess) {
     const int64_t words = (n_vox(m) + 31) / 32;
@@ -341,6 +390,18 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
     a.occ = m->occ;
     a.stats = m->stats;
     a.touch = m->touch;
+    a.items = m->items;
+    a.part_rays = m->part_rays;
+    a.part_trace = m->part_trace;
+    a.item_cap = m->item_cap;
+    a.seg_len = m->seg_len;
+    {
+      const int64_t want = (m->item_cap + 255) / 256;
+      const int64_t lim = (int64_t)m->n_cu * m->trace_wpc / 4;
+      a.trace_blocks = (int32_t)(want < lim ? want : lim);
+    }
+    m->last_ray_blocks = ray_blocks;
+    m->last_trace_blocks = a.trace_blocks;
     const int pm = prof_begin(m, MAP_PROF_INSERT);
     e = gvom::launch_insert(a, distinct, m->stream);
     prof_end(m, pm);
@@ -440,17 +501,35 @@ int32_t map_import_voxels(map_t* m, const int32_t* lut_dev, const map_voxel_t* d
 int32_t map_get_stats(map_t* m, map_stats_t* out) {
   if (!m || !out) return MAP_E_INVALID;
   if (m->sticky) return m->sticky;
-  unsigned long long h[8];
-  hipError_t e = hipMemcpyAsync(h, m->stats, sizeof(h), hipMemcpyDeviceToHost, m->stream);
+  std::vector<unsigned long long> pr((size_t)m->last_ray_blocks * 4 + 1),
+      pt((size_t)m->last_trace_blocks * 2 + 1);
+  hipError_t e = hipSuccess;
+  if (m->last_ray_blocks)
+    e = hipMemcpyAsync(pr.data(), m->part_rays, m->last_ray_blocks * 32, hipMemcpyDeviceToHost,
+                       m->stream);
+  if (e == hipSuccess && m->last_trace_blocks)
+    e = hipMemcpyAsync(pt.data(), m->part_trace, m->last_trace_blocks * 16,
+                       hipMemcpyDeviceToHost, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) return dev_status(m, e);
+  int64_t c[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t b = 0; b < m->last_ray_blocks; b++) {
+    c[0] += (int64_t)pr[4 * b + 0];
+    c[1] += (int64_t)pr[4 * b + 1];
+    c[2] += (int64_t)pr[4 * b + 2];
+    c[5] += (int64_t)pr[4 * b + 3];
+  }
+  for (int64_t b = 0; b < m->last_trace_blocks; b++) {
+    c[3] += (int64_t)pt[2 * b + 0];
+    c[4] += (int64_t)pt[2 * b + 1];
+  }
   out->n_points = m->last_points;
-  out->n_nonfinite = (int64_t)h[0];
-  out->n_range = (int64_t)h[1];
-  out->n_hits = (int64_t)h[2];
-  out->n_pass = (int64_t)h[3];
-  out->n_distinct_pass = m->last_distinct ? (int64_t)h[4] : -1;
-  out->n_distinct_hit = m->last_distinct ? (int64_t)h[5] : -1;
+  out->n_nonfinite = c[0];
+  out->n_range = c[1];
+  out->n_hits = c[2];
+  out->n_pass = c[3];
+  out->n_distinct_pass = m->last_distinct ? c[4] : -1;
+  out->n_distinct_hit = m->last_distinct ? c[5] : -1;
   out->n_cleared = m->last_cleared;
   return MAP_OK;
 }
@@ -465,6 +544,28 @@ int32_t map_sync(map_t* m) {
   if (!m) return MAP_E_INVALID;
   if (m->sticky) return m->sticky;
   return dev_status(m, hipStreamSynchronize(m->stream));
+}
+
+int32_t map_set_tuning(map_t* m, const map_tuning_t* t) {
+  if (!m || !t) return MAP_E_INVALID;
+  if (t->seg_len > 1024 || t->trace_waves_per_cu > 32) return MAP_E_INVALID;
+  if (t->seg_len > 0 && t->seg_len != m->seg_len) {
+    // the segment buffer is sized for the segment length: regrow on next insert
+    if (hipStreamSynchronize(m->stream) != hipSuccess) return dev_status(m, hipErrorUnknown);
+    (void)hipFree(m->items);
+    m->items = nullptr;
+    m->item_cap = 0;
+    m->seg_len = t->seg_len;
+  }
+  if (t->trace_waves_per_cu > 0) m->trace_wpc = t->trace_waves_per_cu;
+  return MAP_OK;
+}
+
+int32_t map_get_tuning(const map_t* m, map_tuning_t* out) {
+  if (!m || !out) return MAP_E_INVALID;
+  out->seg_len = m->seg_len;
+  out->trace_waves_per_cu = m->trace_wpc;
+  return MAP_OK;
 }
 
 int32_t map_profile_enable(map_t* m, int32_t enable) {

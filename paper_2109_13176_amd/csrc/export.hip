@@ -96,22 +96,66 @@ __global__ __launch_bounds__(kBlock) void k_column(ColumnArgs a) {
   a.hq[c] = hq;
 }
 
-// 2D surface maps on tiles of kTile x kTile pixels with a halo of H pixels
-// staged in LDS.  Defined pixels get the N x N least-squares plane (integer
-// normal equations, exact determinant, Cramer's rule in double); undefined
-// pixels get the four-cone negative-obstacle search.  A cone ring slice
-// holds a defined cell iff the per-row (per-column) prefix count of defined
-// cells over the slice's span is positive.
+// 2D surface maps on tiles of kTile x kTile pixels (one pixel per thread)
+// with a halo of H = max(half_fit, D) pixels staged in LDS.  Defined pixels
+// get the N x N least-squares plane (integer normal equations, exact
+// determinant, Cramer's rule in double); undefined pixels get the four-cone
+// negative-obstacle search.
+//
+// Cone test: ring d of the +x cone of pixel (x, y) is the slice of staged row
+// x+d over columns y-d..y+d; it holds a defined cell iff the distance along
+// that row from column y to the nearest defined cell is <= d.  These row
+// (and column) distances are precomputed for the tile's own columns (rows)
+// from per-line bit masks, so each ring costs one LDS byte; only the slice
+// where a cone stops is then read cell by cell.
 constexpr int kTile = 32;
+constexpr int kSurfThreads = kTile * kTile;
+constexpr int kMaxMaskWords = 3;  // staged edge <= 192 cells
 
-__global__ __launch_bounds__(kBlock) void k_surface(SurfaceArgs a, int H) {
+__device__ __forceinline__ unsigned long long span_bits(unsigned long long v, int w, int a,
+                                                        int b) {
+  // bits of word w that fall in the inclusive cell range [a, b]
+  const int lo = a - 64 * w, hi = b - 64 * w;
+  if (lo > 0) v &= ~0ull << lo;
+  if (hi < 63) v &= ~0ull >> (63 - hi);
+  return v;
+}
+
+// distance from cell k of a line (bit mask of MW words, T cells) to its
+// nearest set bit, clamped to 255
+__device__ __forceinline__ int line_distance(const unsigned long long* L, int MW, int T, int k) {
+  int best = 255;
+  for (int w = 0; w < MW; w++) {
+    unsigned long long v = L[w];
+    if (!v) continue;
+    // nearest set bit at or below k, and at or above k, within this word
+    const int base = 64 * w;
+    if (k >= base) {
+      const int top = min(k - base, 63);
+      const unsigned long long below = top == 63 ? v : (v & ((2ull << top) - 1ull));
+      if (below) best = min(best, k - (base + 63 - __clzll((long long)below)));
+    }
+    if (k <= base + 63) {
+      const int bot = max(k - base, 0);
+      const unsigned long long above = v & (~0ull << bot);
+      if (above) best = min(best, base + __ffsll((long long)above) - 1 - k);
+    }
+  }
+  (void)T;
+  return best;
+}
+
+__global__ __launch_bounds__(kSurfThreads) void k_surface(SurfaceArgs a, int H) {
   extern __shared__ int32_t lds[];
-  const int T = kTile + 2 * H;  // staged tile edge
-  int32_t* th = lds;                                         // [T][T] heights
-  uint16_t* rpre = (uint16_t*)(lds + T * T);                 // [T][T+1] along y
-  uint16_t* cpre = rpre + T * (T + 1);                       // [T][T+1] along x
+  const int T = kTile + 2 * H;          // staged tile edge
+  const int MW = (T + 63) >> 6;         // mask words per staged row / column
+  int32_t* th = lds;                                                    // [T][T]
+  unsigned long long* rmask = (unsigned long long*)(lds + ((T * T + 1) & ~1));  // [T][MW]
+  unsigned long long* cmask = rmask + T * MW;                            // [T][MW]
+  uint8_t* rdist = (uint8_t*)(cmask + T * MW);  // [T][kTile]: row r, tile column j
+  uint8_t* cdist = rdist + T * kTile;           // [T][kTile]: column c, tile row i
   const int gx0 = blockIdx.x * kTile - H, gy0 = blockIdx.y * kTile - H;
-  for (int i = threadIdx.x; i < T * T; i += kBlock) {
+  for (int i = threadIdx.x; i < T * T; i += kSurfThreads) {
     const int tx = i / T, ty = i - tx * T;
     const int gx = gx0 + tx, gy = gy0 + ty;
     int32_t v = INT32_MIN;
@@ -119,126 +163,125 @@ __global__ __launch_bounds__(kBlock) void k_surface(SurfaceArgs a, int H) {
     th[i] = v;
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < 2 * T; r += kBlock) {
-    if (r < T) {  // row r: fixed x, running over y
-      uint16_t acc = 0;
-      rpre[r * (T + 1)] = 0;
-      for (int k = 0; k < T; k++) {
-        acc += th[r * T + k] != INT32_MIN;
-        rpre[r * (T + 1) + k + 1] = acc;
-      }
-    } else {  // column r - T: fixed y, running over x
-      const int cc = r - T;
-      uint16_t acc = 0;
-      cpre[cc * (T + 1)] = 0;
-      for (int k = 0; k < T; k++) {
-        acc += th[k * T + cc] != INT32_MIN;
-        cpre[cc * (T + 1) + k + 1] = acc;
-      }
+  {
+    const int lane = __lane_id(), wv = threadIdx.x >> 6;
+    for (int j = wv; j < 2 * T * MW; j += kSurfThreads / 64) {
+      const bool col = j >= T * MW;
+      const int jj = col ? j - T * MW : j;
+      const int r = jj / MW, w = jj - r * MW;
+      const int k = 64 * w + lane;
+      bool d = false;
+      if (k < T) d = (col ? th[k * T + r] : th[r * T + k]) != INT32_MIN;
+      const unsigned long long b = __ballot(d);
+      if (lane == 0) (col ? cmask : rmask)[r * MW + w] = b;
     }
   }
   __syncthreads();
+  for (int i = threadIdx.x; i < 2 * T * kTile; i += kSurfThreads) {
+    const bool col = i >= T * kTile;
+    const int ii = col ? i - T * kTile : i;
+    const int line = ii / kTile, j = ii - line * kTile;
+    const int dd = line_distance((col ? cmask : rmask) + line * MW, MW, T, H + j);
+    (col ? cdist : rdist)[ii] = (uint8_t)dd;
+  }
+  __syncthreads();
 
+  const int px = threadIdx.x / kTile, py = threadIdx.x - px * kTile;
+  const int gx = blockIdx.x * kTile + px, gy = blockIdx.y * kTile + py;
+  if (gx >= a.nx || gy >= a.ny) return;
   const int h = a.half_fit, D = a.search_d;
-  for (int p = threadIdx.x; p < kTile * kTile; p += kBlock) {
-    const int px = p / kTile, py = p - px * kTile;
-    const int gx = blockIdx.x * kTile + px, gy = blockIdx.y * kTile + py;
-    if (gx >= a.nx || gy >= a.ny) continue;
-    const int tx = px + H, ty = py + H;
-    const int32_t hc = th[tx * T + ty];
-    const int64_t c = (int64_t)gx * a.ny + gy;
-    uint8_t fl = a.flags[c];
-    float slope = __uint_as_float(kQNaN), rough = __uint_as_float(kQNaN);
-    if (hc != INT32_MIN) {
-      int32_t n = 0, sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0;
-      int64_t sz = 0, sxz = 0, syz = 0;
+  const int tx = px + H, ty = py + H;
+  const int32_t hc = th[tx * T + ty];
+  const int64_t c = (int64_t)gx * a.ny + gy;
+  uint8_t fl = a.flags[c];
+  float slope = __uint_as_float(kQNaN), rough = __uint_as_float(kQNaN);
+  if (hc != INT32_MIN) {
+    int32_t n = 0, sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0;
+    int64_t sz = 0, sxz = 0, syz = 0;
+    for (int dx = -h; dx <= h; dx++)
+      for (int dy = -h; dy <= h; dy++) {
+        const int32_t v = th[(tx + dx) * T + ty + dy];
+        if (v == INT32_MIN) continue;
+        const int64_t dz = (int64_t)v - hc;
+        n++;
+        sx += dx;
+        sy += dy;
+        sxx += dx * dx;
+        syy += dy * dy;
+        sxy += dx * dy;
+        sz += dz;
+        sxz += dx * dz;
+        syz += dy * dz;
+      }
+    // adjugate of M = [[sxx sxy sx] [sxy syy sy] [sx sy n]] (symmetric)
+    const int64_t c00 = (int64_t)syy * n - (int64_t)sy * sy;
+    const int64_t c01 = (int64_t)sy * sx - (int64_t)sxy * n;
+    const int64_t c02 = (int64_t)sxy * sy - (int64_t)syy * sx;
+    const int64_t c11 = (int64_t)sxx * n - (int64_t)sx * sx;
+    const int64_t c12 = (int64_t)sxy * sx - (int64_t)sxx * sy;
+    const int64_t c22 = (int64_t)sxx * syy - (int64_t)sxy * sxy;
+    const int64_t det = (int64_t)sxx * c00 + (int64_t)sxy * c01 + (int64_t)sx * c02;
+    if (n >= 3 && det != 0) {
+      const double inv = 1.0 / (double)det;
+      const double bx = (double)sxz, by = (double)syz, bz = (double)sz;
+      const double al = ((double)c00 * bx + (double)c01 * by + (double)c02 * bz) * inv;
+      const double be = ((double)c01 * bx + (double)c11 * by + (double)c12 * bz) * inv;
+      const double ga = ((double)c02 * bx + (double)c12 * by + (double)c22 * bz) * inv;
+      double ss = 0.0;
       for (int dx = -h; dx <= h; dx++)
         for (int dy = -h; dy <= h; dy++) {
           const int32_t v = th[(tx + dx) * T + ty + dy];
           if (v == INT32_MIN) continue;
-          const int64_t dz = (int64_t)v - hc;
-          n++;
-          sx += dx;
-          sy += dy;
-          sxx += dx * dx;
-          syy += dy * dy;
-          sxy += dx * dy;
-          sz += dz;
-          sxz += dx * dz;
-          syz += dy * dz;
+          const double e = (double)((int64_t)v - hc) - (al * dx + be * dy + ga);
+          ss += e * e;
         }
-      // adjugate of M = [[sxx sxy sx] [sxy syy sy] [sx sy n]] (symmetric)
-      const int64_t c00 = (int64_t)syy * n - (int64_t)sy * sy;
-      const int64_t c01 = (int64_t)sy * sx - (int64_t)sxy * n;
-      const int64_t c02 = (int64_t)sxy * sy - (int64_t)syy * sx;
-      const int64_t c11 = (int64_t)sxx * n - (int64_t)sx * sx;
-      const int64_t c12 = (int64_t)sxy * sx - (int64_t)sxx * sy;
-      const int64_t c22 = (int64_t)sxx * syy - (int64_t)sxy * sxy;
-      const int64_t det = (int64_t)sxx * c00 + (int64_t)sxy * c01 + (int64_t)sx * c02;
-      if (n >= 3 && det != 0) {
-        const double inv = 1.0 / (double)det;
-        const double bx = (double)sxz, by = (double)syz, bz = (double)sz;
-        const double al = ((double)c00 * bx + (double)c01 * by + (double)c02 * bz) * inv;
-        const double be = ((double)c01 * bx + (double)c11 * by + (double)c12 * bz) * inv;
-        const double ga = ((double)c02 * bx + (double)c12 * by + (double)c22 * bz) * inv;
-        double ss = 0.0;
-        for (int dx = -h; dx <= h; dx++)
-          for (int dy = -h; dy <= h; dy++) {
-            const int32_t v = th[(tx + dx) * T + ty + dy];
-            if (v == INT32_MIN) continue;
-            const double e = (double)((int64_t)v - hc) - (al * dx + be * dy + ga);
-            ss += e * e;
-          }
-        slope = (float)(sqrt(al * al + be * be) / 65536.0);
-        rough = (float)(ss / (double)n * a.q2m * a.q2m);
-        fl |= 32;
-      }
-    } else {
-      int64_t lo = INT64_MAX, hi = INT64_MIN;
-      int found = 0;
-      // +x / -x cones: slice = tile row tx +- d, y in [ty - d, ty + d]
-      for (int dir = -1; dir <= 1; dir += 2) {
-        for (int d = 1; d <= D; d++) {
-          const int r = tx + dir * d;
-          const int y0 = ty - d, y1 = ty + d;
-          if (rpre[r * (T + 1) + y1 + 1] - rpre[r * (T + 1) + y0] == 0) continue;
-          for (int y = y0; y <= y1; y++) {
-            const int32_t v = th[r * T + y];
-            if (v == INT32_MIN) continue;
-            found++;
-            lo = min(lo, (int64_t)v);
-            hi = max(hi, (int64_t)v);
-          }
-          break;
-        }
-      }
-      // +y / -y cones: slice = tile column ty +- d, x in [tx - d, tx + d]
-      for (int dir = -1; dir <= 1; dir += 2) {
-        for (int d = 1; d <= D; d++) {
-          const int cc = ty + dir * d;
-          const int x0 = tx - d, x1 = tx + d;
-          if (cpre[cc * (T + 1) + x1 + 1] - cpre[cc * (T + 1) + x0] == 0) continue;
-          for (int x = x0; x <= x1; x++) {
-            const int32_t v = th[x * T + cc];
-            if (v == INT32_MIN) continue;
-            found++;
-            lo = min(lo, (int64_t)v);
-            hi = max(hi, (int64_t)v);
-          }
-          break;
-        }
-      }
-      if (found >= 2 && hi - lo > a.tau_q) fl |= 16;
+      slope = (float)(sqrt(al * al + be * be) / 65536.0);
+      rough = (float)(ss / (double)n * a.q2m * a.q2m);
+      fl |= 32;
     }
-    a.slope[c] = slope;
-    a.rough[c] = rough;
-    a.flags[c] = fl;
+  } else {
+    int32_t lo = INT32_MAX, hi = INT32_MIN;
+    int found = 0;
+    // cones 0/1: +x/-x (slices on staged rows), 2/3: +y/-y (staged columns)
+    for (int cone = 0; cone < 4; cone++) {
+      const bool alongx = cone < 2;
+      const int dir = (cone & 1) ? -1 : 1;
+      const int ctr = alongx ? tx : ty;        // coordinate that moves with d
+      const int oth = alongx ? ty : tx;        // centre of the slice span
+      const uint8_t* dist = alongx ? rdist : cdist;
+      const int j = alongx ? py : px;
+      int d = 1;
+      while (d <= D && dist[(ctr + dir * d) * kTile + j] > d) d++;
+      if (d > D) continue;
+      const int line = ctr + dir * d;
+      const int s0 = oth - d, s1 = oth + d;
+      const unsigned long long* L = (alongx ? rmask : cmask) + line * MW;
+      for (int w = s0 >> 6; w <= (s1 >> 6); w++) {
+        unsigned long long b = span_bits(L[w], w, s0, s1);
+        while (b) {
+          const int k = 64 * w + __ffsll((long long)b) - 1;
+          b &= b - 1;
+          const int32_t v = alongx ? th[line * T + k] : th[k * T + line];
+          lo = min(lo, v);
+          hi = max(hi, v);
+          found++;
+        }
+      }
+    }
+    if (found >= 2 && (int64_t)hi - lo > a.tau_q) fl |= 16;
   }
+  a.slope[c] = slope;
+  a.rough[c] = rough;
+  a.flags[c] = fl;
 }
 
-// Lookup-table export, pass 1: occupied voxels per block of 256 columns.
+// Lookup-table export.  Columns are taken in groups of 64 (window-local
+// order); pass 1 counts the occupied voxels of each group, pass 2 scans the
+// group counts, pass 3 writes the table and the data array of one group per
+// block.
+constexpr int kGroup = 64;
+
 __global__ __launch_bounds__(kBlock) void k_lut_count(LutArgs a) {
-  __shared__ int32_t part[kBlock / 64];
   const int nx = a.d.nx, ny = a.d.ny;
   const int c = blockIdx.x * kBlock + threadIdx.x;
   int cnt = 0;
@@ -250,24 +293,18 @@ __global__ __launch_bounds__(kBlock) void k_lut_count(LutArgs a) {
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-  if (__lane_id() == 0) part[threadIdx.x >> 6] = cnt;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int s = 0;
-    for (int w = 0; w < kBlock / 64; w++) s += part[w];
-    a.block_base[blockIdx.x] = s;
-  }
+  const int g = c >> 6;
+  if (__lane_id() == 0 && g * kGroup < nx * ny) a.block_base[g] = cnt;
 }
 
-// Pass 2 (one block): exclusive scan of the block counts; writes M.
+// Pass 2 (one block): exclusive scan of the group counts; writes M.
 __global__ __launch_bounds__(1024) void k_lut_scan(int32_t* base, int nb, int64_t* n_occupied) {
   __shared__ int64_t wsum[16];
   const int t = threadIdx.x;
   const int per = (nb + 1023) / 1024;
-  const int b0 = t * per, b1 = min(b0 + per, nb);
+  const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
   int64_t s = 0;
   for (int b = b0; b < b1; b++) s += base[b];
-  // inclusive scan of s across the block
   const int lane = __lane_id(), w = t >> 6;
   int64_t v = s;
 #pragma unroll
@@ -295,62 +332,69 @@ __global__ __launch_bounds__(1024) void k_lut_scan(int32_t* base, int nb, int64_
   }
 }
 
-// Pass 3: each block writes the lookup table and data array of its 256
-// columns; wave w handles columns w, w+4, ...; lane = window-local z.
-__global__ __launch_bounds__(kBlock) void k_lut_write(LutArgs a) {
-  __shared__ int32_t colbase[kBlock];
+// Pass 3: block = one group of 64 columns.  Wave 0 derives each column's
+// window-local occupancy mask and first rank; then the block walks the
+// group's nz*64 table entries in table order (coalesced reads of passes,
+// coalesced table writes).
+__global__ __launch_bounds__(kBlock) void k_lut_write(LutArgs a, uint32_t nz_magic) {
+  __shared__ unsigned long long slo[kGroup], shi[kGroup];
+  __shared__ int32_t sbase[kGroup];
+  __shared__ int64_t sbaseidx[kGroup];
   const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, W = a.d.W, roz = a.d.ro[2];
   const int C = nx * ny;
-  const int c0 = blockIdx.x * kBlock;
-  {
-    const int c = c0 + threadIdx.x;
+  const int g = blockIdx.x;
+  const int c0 = g * kGroup;
+  const int ncols = min(kGroup, C - c0);
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int c = c0 + lane;
     int cnt = 0;
-    if (c < C) {
+    Mask128 m = {0ull, 0ull};
+    int64_t scol = 0;
+    if (lane < ncols) {
       const int x = c / ny, y = c - x * ny;
-      const int64_t scol =
-          (int64_t)wrap_add(x + a.d.ro[0], nx) * ny + wrap_add(y + a.d.ro[1], ny);
-      cnt = __popcll(a.occ[scol * W]);
-      if (W > 1) cnt += __popcll(a.occ[scol * W + 1]);
+      scol = (int64_t)wrap_add(x + a.d.ro[0], nx) * ny + wrap_add(y + a.d.ro[1], ny);
+      m = local_mask(a.occ, scol, W, nz, roz);
+      cnt = __popcll(m.lo) + __popcll(m.hi);
     }
-    colbase[threadIdx.x] = cnt;
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(incl, o);
+      if (lane >= o) incl += u;
+    }
+    slo[lane] = m.lo;
+    shi[lane] = m.hi;
+    sbase[lane] = a.block_base[g] + incl - cnt;
+    sbaseidx[lane] = scol * nz;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int32_t acc = a.block_base[blockIdx.x];
-    for (int k = 0; k < kBlock; k++) {
-      const int32_t q = colbase[k];
-      colbase[k] = acc;
-      acc += q;
-    }
-  }
-  __syncthreads();
-  const int lane = __lane_id(), wv = threadIdx.x >> 6;
-  for (int k = wv; k < kBlock; k += kBlock / 64) {
-    const int c = c0 + k;
-    if (c >= C) break;
-    const int x = c / ny, y = c - x * ny;
-    const int64_t scol = (int64_t)wrap_add(x + a.d.ro[0], nx) * ny + wrap_add(y + a.d.ro[1], ny);
-    const Mask128 m = local_mask(a.occ, scol, W, nz, roz);
-    const int64_t sbase = scol * nz;
-    const int64_t lbase = (int64_t)c * nz;
-    for (int z = lane; z < nz; z += 64) {
-      const int64_t e = sbase + wrap_add(z + roz, nz);
-      int32_t v;
-      if (test_bit(m, z)) {
-        const int32_t rank = colbase[k] + rank_below(m, z);
-        v = rank;
-        if (rank < a.cap) {
-          map_voxel_t d;
-          d.hits = a.hits[e];
-          d.passes = a.passes[e];
-          d.min_qz = a.minqz[e];
-          a.data[rank] = d;
-        }
-      } else {
-        v = -1 - a.passes[e];
+  const int32_t* __restrict__ passes = a.passes;
+  const int32_t* __restrict__ hits = a.hits;
+  const int32_t* __restrict__ minqz = a.minqz;
+  int32_t* __restrict__ lut = a.lut + (int64_t)c0 * nz;
+  const int total = ncols * nz;
+#pragma unroll 4
+  for (int t = threadIdx.x; t < total; t += kBlock) {
+    const int col = nz == 1 ? t : (int)__umulhi((uint32_t)t, nz_magic);
+    const int z = t - col * nz;
+    const Mask128 m = {slo[col], shi[col]};
+    const int64_t e = sbaseidx[col] + wrap_add(z + roz, nz);
+    int32_t v;
+    if (test_bit(m, z)) {
+      const int32_t rank = sbase[col] + rank_below(m, z);
+      v = rank;
+      if (rank < a.cap) {
+        map_voxel_t d;
+        d.hits = hits[e];
+        d.passes = passes[e];
+        d.min_qz = minqz[e];
+        a.data[rank] = d;
       }
-      a.lut[lbase + z] = v;
+    } else {
+      v = -1 - passes[e];
     }
+    lut[t] = v;
   }
 }
 
@@ -420,7 +464,10 @@ hipError_t launch_column(const ColumnArgs& a, hipStream_t s) {
 hipError_t launch_surface(const SurfaceArgs& a, hipStream_t s) {
   const int H = a.search_d > a.half_fit ? a.search_d : a.half_fit;
   const int T = kTile + 2 * H;
-  const size_t lds = (size_t)T * T * 4 + 2 * (size_t)T * (T + 1) * 2;
+  const int MW = (T + 63) / 64;
+  if (MW > kMaxMaskWords) return hipErrorInvalidValue;
+  const size_t lds = (size_t)((T * T + 1) & ~1) * 4 + 2 * (size_t)T * MW * 8 +
+                     2 * (size_t)T * kTile;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute((const void*)k_surface,
@@ -429,16 +476,19 @@ hipError_t launch_surface(const SurfaceArgs& a, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   dim3 g((a.nx + kTile - 1) / kTile, (a.ny + kTile - 1) / kTile);
-  hipLaunchKernelGGL(k_surface, g, dim3(kBlock), lds, s, a, H);
+  hipLaunchKernelGGL(k_surface, g, dim3(kSurfThreads), lds, s, a, H);
   return hipGetLastError();
 }
 
 hipError_t launch_lut(const LutArgs& a, hipStream_t s) {
   const int C = a.d.nx * a.d.ny;
-  const int nb = (C + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_lut_count, dim3(nb), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_lut_scan, dim3(1), dim3(1024), 0, s, a.block_base, nb, a.n_occupied);
-  hipLaunchKernelGGL(k_lut_write, dim3(nb), dim3(kBlock), 0, s, a);
+  const int ng = (C + kGroup - 1) / kGroup;
+  // t / nz == umulhi(t, ceil(2^32 / nz)) for every t < 2^20 (here t < 64 * 128)
+  const uint32_t magic =
+      a.d.nz > 1 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)a.d.nz - 1) / (uint64_t)a.d.nz) : 0u;
+  hipLaunchKernelGGL(k_lut_count, dim3((C + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_lut_scan, dim3(1), dim3(1024), 0, s, a.block_base, ng, a.n_occupied);
+  hipLaunchKernelGGL(k_lut_write, dim3(ng), dim3(kBlock), 0, s, a, magic);
   return hipGetLastError();
 }
 

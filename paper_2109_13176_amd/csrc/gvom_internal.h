@@ -36,9 +36,21 @@ struct InsertArgs {
   int32_t* passes;
   int32_t* minqz;
   unsigned long long* occ;
-  unsigned long long* stats;   // [n_nonfinite, n_range, n_hits, n_pass, dpass, dhit]
+  unsigned long long* stats;   // [n_nonfinite, n_range, n_hits, n_pass, dpass, dhit,
+                               //  ray-segment count]
   uint32_t* touch;             // distinct-voxel bitmaps [2][V/32] or null
+  unsigned long long* part_rays;   // per ray block: nonfinite, range, hits, distinct hits
+  unsigned long long* part_trace;  // per trace block: passes, distinct passes
+  int4* items;                 // ray segments {Qx, Qy, Qz, segment index}
+  int64_t item_cap;
+  int32_t seg_len;             // dominant-axis voxels per segment
+  int32_t trace_blocks;        // grid of the trace kernel
 };
+
+constexpr int kRayBlock = 1024;   // threads per block of the ray pass
+
+// Upper bound of the ray segments of a scan of n points (items buffer size).
+int64_t segment_capacity(int64_t n, const Dims& d, int32_t seg_len);
 
 struct ColumnArgs {
   Dims d;

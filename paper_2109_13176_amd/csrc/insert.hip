@@ -20,33 +20,34 @@ __device__ __forceinline__ int wave_sum(int v) {
   return v;
 }
 
-// One lane per point.  Each lane transforms its point, records the return in
-// the end voxel, then walks the segment sensor -> point voxel by voxel and
-// adds one pass to every window voxel before the end voxel.
+// ---------------------------------------------------------------------------
+// Pass 1, one lane per point: transform, record the return in its voxel, and
+// cut the ray into segments for the traversal pass.
 //
-// Traversal: along axis a the segment leaves its current cell when it has
-// moved num_a (Q units) at speed |D_a|, i.e. at time num_a / |D_a|.  The axis
-// with the smallest time steps next; times are compared exactly through the
-// pairwise differences E_ab = num_a |D_b| - num_b |D_a| (int64, |.| < 2^56),
-// which change only by constant increments when an axis steps.  When several
-// axes share the smallest time, the axes moving up step first (the shared
-// boundary belongs to the upper cell) and the axes moving down step in the
-// following iteration, so the voxel at that instant is visited.
-//
-// Lanes of a wave step in lock-step; in each step the lanes that pass the
-// same voxel as their left neighbour join its run and the run's first lane
-// adds the run length with one atomic.
+// A ray's voxel path is monotone in every axis.  Along its dominant axis (the
+// axis with the most voxel steps) the path is cut every seg_len voxels:
+// segment j holds the path voxels whose dominant coordinate lies j*seg_len ..
+// (j+1)*seg_len - 1 voxels from the sensor's.  Only segments that start
+// inside the window along the dominant axis are emitted.  A wave reserves
+// room for all its segments with one atomic and writes them segment-major,
+// so that consecutive items are the same segment of neighbouring rays.
+__device__ __forceinline__ int dominant_axis(const int32_t n[3]) {
+  return (n[1] > n[0]) ? (n[2] > n[1] ? 2 : 1) : (n[2] > n[0] ? 2 : 0);
+}
+
 template <bool DISTINCT>
-__global__ __launch_bounds__(kBlock) void k_insert(InsertArgs a) {
-  const int lane = __lane_id();
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kRayBlock) void k_rays(InsertArgs a) {
+  __shared__ unsigned int wcount[kRayBlock / 64][5];
+  __shared__ unsigned long long wbase[kRayBlock / 64];
+  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * kRayBlock + threadIdx.x;
   const bool in = i < a.n;
   int pidx = i;
   if (a.fw > 1 && in) {
     const int b = i / a.azimuths;
     pidx = (i - b * a.azimuths) * a.fw + b;
   }
-  const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
+  const int32_t dims[3] = {a.d.nx, a.d.ny, a.d.nz};
 
   bool nonfinite = false, outrange = false, hit = false, dhit = false, ray = false;
   int32_t q[3] = {0, 0, 0};
@@ -74,56 +75,30 @@ __global__ __launch_bounds__(kBlock) void k_insert(InsertArgs a) {
     }
   }
 
-  // DDA state (meaningful for ray lanes only)
-  int32_t rem[3] = {0, 0, 0}, room[3] = {0, 0, 0}, sg[3] = {0, 0, 0}, sc[3] = {0, 0, 0};
-  int64_t exy = 0, exz = 0, eyz = 0;
-  int64_t kxy = 0, kxz = 0, kyx = 0, kyz = 0, kzx = 0, kzy = 0;
-  int32_t sidx = 0;
+  int nseg = 0;
   if (ray) {
-    const int32_t dims[3] = {nx, ny, nz};
-    int32_t ad[3], num[3];
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-      const int32_t sv = a.S[k] >> 16;
-      const int32_t ev = q[k] >> 16;
-      const int32_t dq = q[k] - a.S[k];
-      sg[k] = dq > 0 ? 1 : (dq < 0 ? -1 : 0);
-      ad[k] = dq < 0 ? -dq : dq;
-      rem[k] = ev > sv ? ev - sv : sv - ev;
-      const int32_t lc = sv - a.O[k];
-      room[k] = sg[k] > 0 ? dims[k] - 1 - lc : lc;
-      num[k] = sg[k] > 0 ? (int32_t)((((int64_t)sv + 1) << 16) - a.S[k])
-                         : (int32_t)((int64_t)a.S[k] - ((int64_t)sv << 16));
-      sc[k] = wrap_add(lc + a.d.ro[k], dims[k]);
-    }
-    exy = (int64_t)num[0] * ad[1] - (int64_t)num[1] * ad[0];
-    exz = (int64_t)num[0] * ad[2] - (int64_t)num[2] * ad[0];
-    eyz = (int64_t)num[1] * ad[2] - (int64_t)num[2] * ad[1];
-    kxy = (int64_t)ad[1] << 16;  // added to E_xy when x steps
-    kxz = (int64_t)ad[2] << 16;
-    kyx = (int64_t)ad[0] << 16;  // subtracted from E_xy when y steps
-    kyz = (int64_t)ad[2] << 16;
-    kzx = (int64_t)ad[0] << 16;
-    kzy = (int64_t)ad[1] << 16;
-    sidx = (sc[0] * ny + sc[1]) * nz + sc[2];
-
-    // the return
-    int32_t l[3];
+    int32_t l[3], n[3];
     bool win = true;
 #pragma unroll
     for (int k = 0; k < 3; k++) {
       l[k] = (q[k] >> 16) - a.O[k];
       win = win && l[k] >= 0 && l[k] < dims[k];
+      const int32_t sv = a.S[k] >> 16, ev = q[k] >> 16;
+      n[k] = ev > sv ? ev - sv : sv - ev;
     }
-    if (win) {
-      const int32_t ex = wrap_add(l[0] + a.d.ro[0], nx);
-      const int32_t ey = wrap_add(l[1] + a.d.ro[1], ny);
-      const int32_t ez = wrap_add(l[2] + a.d.ro[2], nz);
-      const int32_t col = ex * ny + ey;
-      const int32_t e = col * nz + ez;
+    if (win) {  // the return
+      const int32_t ex = wrap_add(l[0] + a.d.ro[0], dims[0]);
+      const int32_t ey = wrap_add(l[1] + a.d.ro[1], dims[1]);
+      const int32_t ez = wrap_add(l[2] + a.d.ro[2], dims[2]);
+      const int32_t col = ex * dims[1] + ey;
+      const int32_t e = col * dims[2] + ez;
       atomicAdd(&a.hits[e], 1);
-      atomicMin(&a.minqz[e], q[2]);
-      atomicOr(&a.occ[(int64_t)col * a.d.W + (ez >> 6)], 1ull << (ez & 63));
+      // min and or only move one way: a plain read that already satisfies
+      // the update makes the atomic unnecessary
+      if (q[2] < a.minqz[e]) atomicMin(&a.minqz[e], q[2]);
+      unsigned long long* ow = &a.occ[(int64_t)col * a.d.W + (ez >> 6)];
+      const unsigned long long ob = 1ull << (ez & 63);
+      if (!(*ow & ob)) atomicOr(ow, ob);
       hit = true;
       if (DISTINCT) {
         const uint32_t bit = 1u << (e & 31);
@@ -131,100 +106,266 @@ __global__ __launch_bounds__(kBlock) void k_insert(InsertArgs a) {
         dhit = !(old & bit);
       }
     }
-  }
-
-  const int64_t V = (int64_t)nx * ny * nz;
-  uint32_t* touch_p = DISTINCT ? a.touch + ((V + 31) >> 5) : nullptr;
-  const int32_t span_x = ny * nz, span_xw = nx * ny * nz, span_yw = ny * nz;
-  bool active = ray && (rem[0] + rem[1] + rem[2] > 0);
-  int n_pass = 0, n_dpass = 0;
-  while (__any(active)) {
-    // ---- aggregated pass of the current voxel
-    const int addr = active ? sidx : -1;
-    const int prev = __shfl_up(addr, 1);
-    const bool head = active && (lane == 0 || prev != addr);
-    const unsigned long long hb = __ballot(head);
-    const unsigned long long ab = __ballot(active);
-    if (head) {
-      const unsigned long long bnd = hb | ~ab;
-      const unsigned long long after = lane == 63 ? 0ull : (bnd >> (lane + 1));
-      const int len = after ? __ffsll((long long)after) : 64 - lane;
-      atomicAdd(&a.passes[addr], len);
-      if (DISTINCT) {
-        const uint32_t bit = 1u << (addr & 31);
-        const uint32_t old = atomicOr(&touch_p[(uint32_t)addr >> 5], bit);
-        n_dpass += !(old & bit);
-      }
-    }
-    if (active) {
-      n_pass++;
-      // ---- choose the axes with the smallest crossing time
-      const bool ax = rem[0] > 0, ay = rem[1] > 0, az = rem[2] > 0;
-      bool mx = ax && (!ay || exy <= 0) && (!az || exz <= 0);
-      bool my = ay && (!ax || exy >= 0) && (!az || eyz <= 0);
-      bool mz = az && (!ax || exz >= 0) && (!ay || eyz >= 0);
-      const bool up = (mx && sg[0] > 0) || (my && sg[1] > 0) || (mz && sg[2] > 0);
-      if (up) {
-        mx = mx && sg[0] > 0;
-        my = my && sg[1] > 0;
-        mz = mz && sg[2] > 0;
-      }
-      bool out = false;
-      if (mx) {
-        rem[0]--;
-        out = out || room[0] == 0;
-        room[0]--;
-        exy += kxy;
-        exz += kxz;
-        sc[0] += sg[0];
-        sidx += sg[0] * span_x;
-        if (sc[0] == nx) { sc[0] = 0; sidx -= span_xw; }
-        if (sc[0] < 0) { sc[0] = nx - 1; sidx += span_xw; }
-      }
-      if (my) {
-        rem[1]--;
-        out = out || room[1] == 0;
-        room[1]--;
-        exy -= kyx;
-        eyz += kyz;
-        sc[1] += sg[1];
-        sidx += sg[1] * nz;
-        if (sc[1] == ny) { sc[1] = 0; sidx -= span_yw; }
-        if (sc[1] < 0) { sc[1] = ny - 1; sidx += span_yw; }
-      }
-      if (mz) {
-        rem[2]--;
-        out = out || room[2] == 0;
-        room[2]--;
-        exz -= kzx;
-        eyz -= kzy;
-        sc[2] += sg[2];
-        sidx += sg[2];
-        if (sc[2] == nz) { sc[2] = 0; sidx -= nz; }
-        if (sc[2] < 0) { sc[2] = nz - 1; sidx += nz; }
-      }
-      active = !out && (rem[0] + rem[1] + rem[2] > 0);
+    if (n[0] + n[1] + n[2] > 0) {
+      const int dom = dominant_axis(n);
+      const int32_t sv = a.S[dom] >> 16;
+      const int32_t lc = sv - a.O[dom];
+      const int32_t room = q[dom] > a.S[dom] ? dims[dom] - 1 - lc : lc;
+      nseg = min(n[dom], room) / a.seg_len + 1;
     }
   }
 
-  // ---- counters: one atomic per wave and counter
+  // reserve and write the segments, segment-major within the wave: one
+  // returning atomic per block, wave bases from the block's prefix
+  int total = nseg;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o);
+  int maxseg = nseg;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) maxseg = max(maxseg, __shfl_xor(maxseg, o));
   const int c0 = __popcll(__ballot(nonfinite));
   const int c1 = __popcll(__ballot(outrange));
   const int c2 = __popcll(__ballot(hit));
-  const int c3 = wave_sum(n_pass);
+  const int c5 = DISTINCT ? __popcll(__ballot(dhit)) : 0;
   if (lane == 0) {
-    if (c0) atomicAdd(&a.stats[0], (unsigned long long)c0);
-    if (c1) atomicAdd(&a.stats[1], (unsigned long long)c1);
-    if (c2) atomicAdd(&a.stats[2], (unsigned long long)c2);
-    if (c3) atomicAdd(&a.stats[3], (unsigned long long)c3);
+    wcount[wv][0] = total;
+    wcount[wv][1] = c0;
+    wcount[wv][2] = c1;
+    wcount[wv][3] = c2;
+    wcount[wv][4] = c5;
   }
-  if (DISTINCT) {
-    const int c4 = wave_sum(n_dpass);
-    const int c5 = __popcll(__ballot(dhit));
-    if (lane == 0) {
-      atomicAdd(&a.stats[4], (unsigned long long)c4);
-      atomicAdd(&a.stats[5], (unsigned long long)c5);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long sum = 0, s0 = 0, s1 = 0, s2 = 0, s5 = 0;
+    for (int w = 0; w < kRayBlock / 64; w++) {
+      wbase[w] = sum;
+      sum += wcount[w][0];
+      s0 += wcount[w][1];
+      s1 += wcount[w][2];
+      s2 += wcount[w][3];
+      s5 += wcount[w][4];
     }
+    const unsigned long long b = sum ? atomicAdd(&a.stats[6], sum) : 0ull;
+    for (int w = 0; w < kRayBlock / 64; w++) wbase[w] += b;
+    unsigned long long* pr = a.part_rays + 4 * (size_t)blockIdx.x;
+    pr[0] = s0;
+    pr[1] = s1;
+    pr[2] = s2;
+    pr[3] = s5;
+  }
+  __syncthreads();
+  unsigned long long off = wbase[wv];
+  for (int j = 0; j < maxseg; j++) {
+    const unsigned long long m = __ballot(nseg > j);
+    if (nseg > j) {
+      const unsigned long long pos =
+          off + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+      if ((int64_t)pos < a.item_cap) a.items[pos] = make_int4(q[0], q[1], q[2], j);
+    }
+    off += __popcll(m);
+  }
+}
+
+// floor(x / d) for d > 0 (|x| < 2^60): double estimate, exact integer fix-up.
+__device__ __forceinline__ int64_t floor_div_pos(int64_t x, int64_t d, bool* exact) {
+  int64_t q = (int64_t)floor((double)x / (double)d);
+  int64_t r = x - q * d;
+  while (r < 0) { q--; r += d; }
+  while (r >= d) { q++; r -= d; }
+  *exact = r == 0;
+  return q;
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2, one lane per ray segment: walk the segment voxel by voxel and add
+// one pass to every window voxel before the ray's end voxel.
+//
+// Start voxel of segment j > 0: the instant the dominant axis enters cell
+// c = c_sensor +- j*seg_len, at exact time t = num / |D_dom|.  Another axis b
+// then lies in cell floor(X_b(t)); if X_b(t) is exactly on a boundary while
+// both b and the dominant axis move down, b leaves its cell at the same
+// instant as the dominant axis (one cell lower).
+//
+// Traversal: along axis a the segment leaves its current cell when it has
+// moved num_a (Q units) at speed |D_a|, i.e. at time num_a / |D_a|.  The axis
+// with the smallest time steps next; times are compared exactly through the
+// pairwise differences E_ab = num_a |D_b| - num_b |D_a| (int64, |.| < 2^56),
+// which change by constant increments when an axis steps.  When several axes
+// share the smallest time, the axes moving up step first (the shared boundary
+// belongs to the upper cell) and the axes moving down step in the next
+// iteration, so the voxel at that instant is visited.
+//
+// Lanes of a wave step in lock-step; the lanes that pass the same voxel as
+// their left neighbour join its run and the run's first lane adds the run
+// length with one atomic.
+template <bool DISTINCT>
+__global__ __launch_bounds__(kBlock) void k_trace(InsertArgs a) {
+  const int lane = __lane_id();
+  const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
+  const int32_t dims[3] = {nx, ny, nz};
+  const int64_t count = min((int64_t)a.stats[6], a.item_cap);
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int64_t V = (int64_t)nx * ny * nz;
+  uint32_t* touch_p = DISTINCT ? a.touch + ((V + 31) >> 5) : nullptr;
+  const int32_t span_x = ny * nz, span_xw = nx * ny * nz, span_yw = ny * nz;
+  int n_pass = 0, n_dpass = 0;
+
+  for (int64_t wbase = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); wbase < count;
+       wbase += stride) {
+    const int64_t it = wbase + lane;
+    bool active = false;
+    int32_t rem[3] = {0, 0, 0}, room[3] = {0, 0, 0}, sg[3] = {0, 0, 0}, sc[3] = {0, 0, 0};
+    int64_t exy = 0, exz = 0, eyz = 0;
+    int64_t kxy = 0, kxz = 0, kyx = 0, kyz = 0, kzx = 0, kzy = 0;
+    int32_t sidx = 0, segleft = 0;
+    bool mdx = false, mdy = false, mdz = false;
+    if (it < count) {
+      const int4 item = a.items[it];
+      const int32_t q[3] = {item.x, item.y, item.z};
+      const int j = item.w;
+      int32_t sv[3], ev[3], n[3], ad[3];
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        sv[k] = a.S[k] >> 16;
+        ev[k] = q[k] >> 16;
+        n[k] = ev[k] > sv[k] ? ev[k] - sv[k] : sv[k] - ev[k];
+        const int32_t dq = q[k] - a.S[k];
+        sg[k] = dq > 0 ? 1 : (dq < 0 ? -1 : 0);
+        ad[k] = dq < 0 ? -dq : dq;
+      }
+      const int dom = dominant_axis(n);
+      int32_t v[3] = {sv[0], sv[1], sv[2]};
+      if (j > 0) {
+        const int32_t c = sv[dom] + sg[dom] * j * a.seg_len;
+        const int64_t num = sg[dom] > 0 ? ((int64_t)c << 16) - a.S[dom]
+                                        : (int64_t)a.S[dom] - (((int64_t)c + 1) << 16);
+        const int64_t den = (int64_t)ad[dom] << 16;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+          if (k == dom) {
+            v[k] = c;
+            continue;
+          }
+          bool exact;
+          const int64_t x = (int64_t)a.S[k] * ad[dom] + num * (sg[k] * (int64_t)ad[k]);
+          int64_t vb = floor_div_pos(x, den, &exact);
+          if (exact && sg[dom] < 0 && sg[k] < 0) vb -= 1;
+          v[k] = (int32_t)vb;
+        }
+      }
+      bool inside = true;
+      int32_t l[3];
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        l[k] = v[k] - a.O[k];
+        inside = inside && l[k] >= 0 && l[k] < dims[k];
+      }
+      if (inside) {
+        int64_t num[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+          rem[k] = ev[k] > v[k] ? ev[k] - v[k] : v[k] - ev[k];
+          room[k] = sg[k] > 0 ? dims[k] - 1 - l[k] : l[k];
+          num[k] = sg[k] > 0 ? (((int64_t)v[k] + 1) << 16) - a.S[k]
+                             : (int64_t)a.S[k] - ((int64_t)v[k] << 16);
+          sc[k] = wrap_add(l[k] + a.d.ro[k], dims[k]);
+        }
+        exy = num[0] * ad[1] - num[1] * ad[0];
+        exz = num[0] * ad[2] - num[2] * ad[0];
+        eyz = num[1] * ad[2] - num[2] * ad[1];
+        kxy = (int64_t)ad[1] << 16;
+        kxz = (int64_t)ad[2] << 16;
+        kyx = (int64_t)ad[0] << 16;
+        kyz = (int64_t)ad[2] << 16;
+        kzx = (int64_t)ad[0] << 16;
+        kzy = (int64_t)ad[1] << 16;
+        sidx = (sc[0] * ny + sc[1]) * nz + sc[2];
+        segleft = a.seg_len - 1;
+        mdx = dom == 0;
+        mdy = dom == 1;
+        mdz = dom == 2;
+        active = rem[0] + rem[1] + rem[2] > 0;
+      }
+    }
+
+    // per-lane constants of the branch-free step
+    const bool px = sg[0] > 0, py = sg[1] > 0, pz = sg[2] > 0;
+    const int32_t ds0 = sg[0] * span_x, ds1 = sg[1] * nz, ds2 = sg[2];
+    const int32_t trig0 = px ? nx : -1, trig1 = py ? ny : -1, trig2 = pz ? nz : -1;
+    const int32_t wv0 = px ? 0 : nx - 1, wv1 = py ? 0 : ny - 1, wv2 = pz ? 0 : nz - 1;
+    const int32_t wc0 = -sg[0] * span_xw, wc1 = -sg[1] * span_yw, wc2 = -sg[2] * nz;
+    while (__any(active)) {
+      // ---- aggregated pass of the current voxel: runs of equal addresses in
+      // neighbouring lanes (left neighbour via a whole-wave DPP shift)
+      const int addr = active ? sidx : -1;
+      const int prev = __builtin_amdgcn_update_dpp(-2, addr, 0x138, 0xf, 0xf, false);
+      const bool head = active && prev != addr;
+      const unsigned long long hb = __ballot(head);
+      const unsigned long long ab = __ballot(active);
+      if (head) {
+        const unsigned long long bnd = hb | ~ab;
+        const unsigned long long after = lane == 63 ? 0ull : (bnd >> (lane + 1));
+        const int len = after ? __ffsll((long long)after) : 64 - lane;
+        atomicAdd(&a.passes[addr], len);
+        if (DISTINCT) {
+          const uint32_t bit = 1u << (addr & 31);
+          const uint32_t old = atomicOr(&touch_p[(uint32_t)addr >> 5], bit);
+          n_dpass += !(old & bit);
+        }
+      }
+      n_pass += active;
+      // ---- the axes with the smallest crossing time (branch-free)
+      const bool ax = rem[0] > 0, ay = rem[1] > 0, az = rem[2] > 0;
+      bool mx = ax & (!ay | (exy <= 0)) & (!az | (exz <= 0));
+      bool my = ay & (!ax | (exy >= 0)) & (!az | (eyz <= 0));
+      bool mz = az & (!ax | (exz >= 0)) & (!ay | (eyz >= 0));
+      const bool up = (mx & px) | (my & py) | (mz & pz);
+      mx = mx & (!up | px);
+      my = my & (!up | py);
+      mz = mz & (!up | pz);
+      const bool domstep = (mx & mdx) | (my & mdy) | (mz & mdz);
+      const bool out = (domstep & (segleft == 0)) | (mx & (room[0] == 0)) |
+                       (my & (room[1] == 0)) | (mz & (room[2] == 0));
+      segleft -= domstep;
+      rem[0] -= mx;
+      rem[1] -= my;
+      rem[2] -= mz;
+      room[0] -= mx;
+      room[1] -= my;
+      room[2] -= mz;
+      exy += (mx ? kxy : 0) - (my ? kyx : 0);
+      exz += (mx ? kxz : 0) - (mz ? kzx : 0);
+      eyz += (my ? kyz : 0) - (mz ? kzy : 0);
+      const int32_t t0 = sc[0] + (mx ? sg[0] : 0);
+      const int32_t t1 = sc[1] + (my ? sg[1] : 0);
+      const int32_t t2 = sc[2] + (mz ? sg[2] : 0);
+      const bool w0 = t0 == trig0, w1 = t1 == trig1, w2 = t2 == trig2;
+      sc[0] = w0 ? wv0 : t0;
+      sc[1] = w1 ? wv1 : t1;
+      sc[2] = w2 ? wv2 : t2;
+      sidx += (mx ? ds0 : 0) + (my ? ds1 : 0) + (mz ? ds2 : 0) + (w0 ? wc0 : 0) +
+              (w1 ? wc1 : 0) + (w2 ? wc2 : 0);
+      active = active & !out & (rem[0] + rem[1] + rem[2] > 0);
+    }
+  }
+
+  // per-block counters, written without atomics (summed by the host)
+  __shared__ int wsum[kBlock / 64][2];
+  const int c3 = wave_sum(n_pass);
+  const int c4 = DISTINCT ? wave_sum(n_dpass) : 0;
+  if (lane == 0) {
+    wsum[threadIdx.x >> 6][0] = c3;
+    wsum[threadIdx.x >> 6][1] = c4;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long p = 0, q = 0;
+    for (int w = 0; w < kBlock / 64; w++) {
+      p += wsum[w][0];
+      q += wsum[w][1];
+    }
+    a.part_trace[2 * blockIdx.x] = p;
+    a.part_trace[2 * blockIdx.x + 1] = q;
   }
 }
 
@@ -306,13 +447,22 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+int64_t segment_capacity(int64_t n, const Dims& d, int32_t seg_len) {
+  int32_t m = d.nx > d.ny ? d.nx : d.ny;
+  if (d.nz > m) m = d.nz;
+  return n * ((m - 1) / seg_len + 1);
+}
+
 hipError_t launch_insert(const InsertArgs& a, bool distinct, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  const int g = (a.n + kBlock - 1) / kBlock;
-  if (distinct)
-    hipLaunchKernelGGL(k_insert<true>, dim3(g), dim3(kBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_insert<false>, dim3(g), dim3(kBlock), 0, s, a);
+  const int g = (a.n + kRayBlock - 1) / kRayBlock;
+  if (distinct) {
+    hipLaunchKernelGGL(k_rays<true>, dim3(g), dim3(kRayBlock), 0, s, a);
+    hipLaunchKernelGGL(k_trace<true>, dim3(a.trace_blocks), dim3(kBlock), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_rays<false>, dim3(g), dim3(kRayBlock), 0, s, a);
+    hipLaunchKernelGGL(k_trace<false>, dim3(a.trace_blocks), dim3(kBlock), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -46,6 +46,10 @@ class map_2d_t(ctypes.Structure):
                 ("flags", ctypes.c_void_p)]
 
 
+class map_tuning_t(ctypes.Structure):
+    _fields_ = [("seg_len", ctypes.c_int32), ("trace_waves_per_cu", ctypes.c_int32)]
+
+
 class map_stats_t(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("n_points", "n_nonfinite", "n_range", "n_hits", "n_pass",
@@ -56,6 +60,7 @@ EXPORTED = [
     "map_params_validate", "map_create", "map_destroy", "map_reset", "map_insert_scan",
     "map_export_2d", "map_export_voxels", "map_import_voxels", "map_get_stats",
     "map_get_origin", "map_sync", "map_status_str", "map_profile_enable", "map_profile_read",
+    "map_set_tuning", "map_get_tuning",
 ]
 PROF_PHASES = ("scroll", "insert", "column", "surface", "lut")
 
@@ -82,6 +87,8 @@ def lib() -> ctypes.CDLL:
         L.map_get_stats.argtypes = [P, ctypes.POINTER(map_stats_t)]
         L.map_get_origin.argtypes = [P, P]
         L.map_sync.argtypes = [P]
+        L.map_set_tuning.argtypes = [P, ctypes.POINTER(map_tuning_t)]
+        L.map_get_tuning.argtypes = [P, ctypes.POINTER(map_tuning_t)]
         L.map_profile_enable.argtypes = [P, I32]
         L.map_profile_read.argtypes = [P, P, P]
         L.map_status_str.argtypes = [I32]
@@ -192,6 +199,16 @@ def map_get_origin(h):
 
 def map_sync(h) -> int:
     return lib().map_sync(h)
+
+
+def map_set_tuning(h, seg_len: int = 0, trace_waves_per_cu: int = 0) -> int:
+    return lib().map_set_tuning(h, ctypes.byref(map_tuning_t(seg_len, trace_waves_per_cu)))
+
+
+def map_get_tuning(h):
+    t = map_tuning_t()
+    s = lib().map_get_tuning(h, ctypes.byref(t))
+    return s, {"seg_len": t.seg_len, "trace_waves_per_cu": t.trace_waves_per_cu}
 
 
 def map_profile_enable(h, enable: bool) -> int:
