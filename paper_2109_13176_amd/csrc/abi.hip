@@ -26,6 +26,7 @@ struct map_t {
   unsigned long long* occ;
   int32_t* hq;
   int32_t* block_base;
+  int32_t* colpre;
   unsigned long long* stats;  // 8 counters
   int32_t* err;
   uint32_t* touch;            // distinct-voxel bitmaps, allocated on first use
@@ -51,7 +52,10 @@ struct map_t {
 
 namespace {
 
+constexpr size_t kStatsBytes = (8 + gvom::kStripes) * 8;
+
 int64_t n_vox(const map_t* m) { return (int64_t)m->p.nx * m->p.ny * m->p.nz; }
+int64_t n_store(const map_t* m) { return m->d.vs; }
 int64_t n_col(const map_t* m) { return (int64_t)m->p.nx * m->p.ny; }
 
 int32_t pos_mod(int64_t a, int32_t n) {
@@ -76,7 +80,7 @@ int32_t dev_status(map_t* m, hipError_t e) {
 
 // Enqueues: every voxel empty, every occupancy word zero.
 hipError_t clear_all(map_t* m) {
-  const int64_t V = n_vox(m);
+  const int64_t V = n_store(m);
   hipError_t e = gvom::launch_fill_i32(m->hits, 0, V, m->stream);
   if (e == hipSuccess) e = gvom::launch_fill_i32(m->passes, 0, V, m->stream);
   if (e == hipSuccess) e = gvom::launch_fill_i32(m->minqz, INT32_MAX, V, m->stream);
@@ -236,7 +240,13 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   m->d.ny = p->ny;
   m->d.nz = p->nz;
   m->d.W = (p->nz + 63) / 64;
-  const int64_t V = n_vox(m), C = n_col(m);
+  m->d.nby = (p->ny + 3) / 4;
+  m->d.vs = (int64_t)((p->nx + 3) / 4) * m->d.nby * p->nz * 16;
+  if (m->d.vs > 2147483647LL) {  // the 4-aligned storage must stay int32-indexable
+    delete m;
+    return MAP_E_INVALID;
+  }
+  const int64_t V = n_store(m), C = n_col(m);
   const int64_t nb = (C + 63) / 64;
   hipError_t e = dmalloc(&m->hits, V * 4);
   if (e == hipSuccess) e = dmalloc(&m->passes, V * 4);
@@ -244,7 +254,8 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   if (e == hipSuccess) e = dmalloc(&m->occ, C * m->d.W * 8);
   if (e == hipSuccess) e = dmalloc(&m->hq, C * 4);
   if (e == hipSuccess) e = dmalloc(&m->block_base, nb * 4);
-  if (e == hipSuccess) e = dmalloc(&m->stats, 8 * 8);
+  if (e == hipSuccess) e = dmalloc(&m->colpre, C * 4);
+  if (e == hipSuccess) e = dmalloc(&m->stats, kStatsBytes);
   if (e == hipSuccess) e = dmalloc(&m->err, 4);
   if (e == hipSuccess) e = dmalloc(&m->part_trace, m->part_trace_cap * 16);
   if (e != hipSuccess) {
@@ -254,7 +265,7 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   }
   initial_origin(m);
   e = clear_all(m);
-  if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, 64, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, kStatsBytes, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -275,6 +286,7 @@ int32_t map_destroy(map_t* m) {
   (void)hipFree(m->occ);
   (void)hipFree(m->hq);
   (void)hipFree(m->block_base);
+  (void)hipFree(m->colpre);
   (void)hipFree(m->stats);
   (void)hipFree(m->err);
   (void)hipFree(m->touch);
@@ -297,7 +309,7 @@ int32_t map_reset(map_t* m) {
   m->last_ray_blocks = 0;
   m->last_trace_blocks = 0;
   hipError_t e = clear_all(m);
-  if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, 64, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, kStatsBytes, m->stream);
   return dev_status(m, e);
 }
 
@@ -315,8 +327,21 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
     S[i] = (int32_t)floorf(u * 65536.0f);
     sv[i] = S[i] >> 16;
   }
-  // segment buffer for the traversal pass (grows before any work is enqueued)
-  const int64_t need = n > 0 ? gvom::segment_capacity(n, m->d, m->seg_len) : 0;
+  // segment buffer for the traversal pass (grows before any work is enqueued):
+  // ray block b writes into the region of stripe b mod kStripes, sized for the
+  // most segments that stripe's points can produce
+  const int64_t ray_blocks = (n + gvom::kRayBlock - 1) / gvom::kRayBlock;
+  const int64_t per_ray = gvom::max_segments(m->d, m->seg_len);
+  int64_t stripe_off[gvom::kStripes], stripe_cap[gvom::kStripes], need = 0;
+  for (int t = 0; t < gvom::kStripes; t++) {
+    const int64_t blocks = ray_blocks > t ? (ray_blocks - t + gvom::kStripes - 1) / gvom::kStripes : 0;
+    int64_t pts = blocks * gvom::kRayBlock;
+    if (blocks && t == (ray_blocks - 1) % gvom::kStripes)
+      pts -= ray_blocks * gvom::kRayBlock - n;  // the last block is partial
+    stripe_off[t] = need;
+    stripe_cap[t] = pts * per_ray;
+    need += stripe_cap[t];
+  }
   if (need > m->item_cap) {
     if (hipStreamSynchronize(m->stream) != hipSuccess) return dev_status(m, hipErrorUnknown);
     (void)hipFree(m->items);
@@ -329,7 +354,6 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
     }
     m->item_cap = need;
   }
-  const int64_t ray_blocks = (n + gvom::kRayBlock - 1) / gvom::kRayBlock;
   if (ray_blocks > m->part_rays_cap) {
     if (hipStreamSynchronize(m->stream) != hipSuccess) return dev_status(m, hipErrorUnknown);
     (void)hipFree(m->part_rays);
@@ -362,9 +386,9 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
   m->last_distinct = distinct;
   m->last_ray_blocks = 0;
   m->last_trace_blocks = 0;
-  if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, 64, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, kStatsBytes, m->stream);
   if (distinct && e == hipSuccess) {
-    const int64_t words = (n_vox(m) + 31) / 32;
+    const int64_t words = (n_store(m) + 31) / 32;
     if (!m->touch) e = dmalloc(&m->touch, words * 2 * 4);
     if (e == hipSuccess) e = hipMemsetAsync(m->touch, 0, words * 2 * 4, m->stream);
   }
@@ -391,12 +415,16 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
     a.stats = m->stats;
     a.touch = m->touch;
     a.items = m->items;
+    for (int t = 0; t < gvom::kStripes; t++) {
+      a.stripe_off[t] = stripe_off[t];
+      a.stripe_cap[t] = stripe_cap[t];
+    }
     a.part_rays = m->part_rays;
     a.part_trace = m->part_trace;
     a.item_cap = m->item_cap;
     a.seg_len = m->seg_len;
     {
-      const int64_t want = (m->item_cap + 255) / 256;
+      const int64_t want = (need + 255) / 256;
       const int64_t lim = (int64_t)m->n_cu * m->trace_wpc / 4;
       a.trace_blocks = (int32_t)(want < lim ? want : lim);
     }
@@ -465,6 +493,7 @@ int32_t map_export_voxels(map_t* m, int32_t* lut_dev, map_voxel_t* data_dev, int
   a.data = data_dev;
   a.cap = cap;
   a.block_base = m->block_base;
+  a.colpre = m->colpre;
   a.n_occupied = n_occupied_dev;
   const int pm = prof_begin(m, MAP_PROF_LUT);
   hipError_t e = gvom::launch_lut(a, m->stream);

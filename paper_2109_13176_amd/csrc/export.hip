@@ -68,8 +68,8 @@ __global__ __launch_bounds__(kBlock) void k_column(ColumnArgs a) {
   int32_t hq = INT32_MIN;
   uint8_t f = 0;
   if (kg >= 0) {
-    const int64_t base = scol * nz;
-    hq = a.minqz[base + wrap_add(kg + a.d.ro[2], nz)];
+    const int64_t base = col_base(a.d, sx, sy);
+    hq = a.minqz[base + (wrap_add(kg + a.d.ro[2], nz) << 4)];
     height = (float)((double)hq * a.res / 65536.0);
     f = 1;
     int64_t sh = 0, sa = 0;
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_column(ColumnArgs a) {
     const int zhi = min(kg + a.n_hi, nz - 1);
     for (int z = zlo; z <= zhi; z++) {
       if (!test_bit(m, z)) continue;
-      const int64_t e = base + wrap_add(z + a.d.ro[2], nz);
+      const int64_t e = base + (wrap_add(z + a.d.ro[2], nz) << 4);
       const int32_t h = a.hits[e];
       sh += h;
       sa += (int64_t)h + a.passes[e];
@@ -186,9 +186,33 @@ __global__ __launch_bounds__(kSurfThreads) void k_surface(SurfaceArgs a, int H) 
   }
   __syncthreads();
 
-  const int px = threadIdx.x / kTile, py = threadIdx.x - px * kTile;
+  // defined pixels (plane fit) and undefined ones (cone search) go to
+  // separate waves: the block's pixels are listed defined-first
+  __shared__ int n_def, n_und;
+  __shared__ int16_t order[kSurfThreads];
+  if (threadIdx.x == 0) {
+    n_def = 0;
+    n_und = 0;
+  }
+  __syncthreads();
+  {
+    const int px = threadIdx.x / kTile, py = threadIdx.x - px * kTile;
+    const int gx = blockIdx.x * kTile + px, gy = blockIdx.y * kTile + py;
+    if (gx < a.nx && gy < a.ny) {
+      if (th[(px + H) * T + py + H] != INT32_MIN)
+        order[atomicAdd(&n_def, 1)] = (int16_t)threadIdx.x;
+      else
+        order[kSurfThreads - 1 - atomicAdd(&n_und, 1)] = (int16_t)threadIdx.x;
+    }
+  }
+  __syncthreads();
+  const int nd = n_def, nu = n_und;
+  int me;
+  if ((int)threadIdx.x < nd) me = order[threadIdx.x];
+  else if ((int)threadIdx.x >= kSurfThreads - nu) me = order[threadIdx.x];
+  else return;
+  const int px = me / kTile, py = me - px * kTile;
   const int gx = blockIdx.x * kTile + px, gy = blockIdx.y * kTile + py;
-  if (gx >= a.nx || gy >= a.ny) return;
   const int h = a.half_fit, D = a.search_d;
   const int tx = px + H, ty = py + H;
   const int32_t hc = th[tx * T + ty];
@@ -275,14 +299,15 @@ __global__ __launch_bounds__(kSurfThreads) void k_surface(SurfaceArgs a, int H) 
   a.flags[c] = fl;
 }
 
-// Lookup-table export.  Columns are taken in groups of 64 (window-local
-// order); pass 1 counts the occupied voxels of each group, pass 2 scans the
-// group counts, pass 3 writes the table and the data array of one group per
-// block.
+// Lookup-table export.  Ranks follow window-local column order: pass 1 gives
+// every local column its occupied-voxel count prefix within its group of 64
+// columns and each group its total, pass 2 scans the group totals, pass 3
+// writes the table and the data array region by region.
 constexpr int kGroup = 64;
 
 __global__ __launch_bounds__(kBlock) void k_lut_count(LutArgs a) {
   const int nx = a.d.nx, ny = a.d.ny;
+  const int lane = __lane_id();
   const int c = blockIdx.x * kBlock + threadIdx.x;
   int cnt = 0;
   if (c < nx * ny) {
@@ -291,10 +316,15 @@ __global__ __launch_bounds__(kBlock) void k_lut_count(LutArgs a) {
     cnt = __popcll(a.occ[scol * a.d.W]);
     if (a.d.W > 1) cnt += __popcll(a.occ[scol * a.d.W + 1]);
   }
+  int incl = cnt;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(incl, o);
+    if (lane >= o) incl += u;
+  }
+  if (c < nx * ny) a.colpre[c] = incl - cnt;
   const int g = c >> 6;
-  if (__lane_id() == 0 && g * kGroup < nx * ny) a.block_base[g] = cnt;
+  if (lane == 63 && g * kGroup < nx * ny) a.block_base[g] = incl;
 }
 
 // Pass 2 (one block): exclusive scan of the group counts; writes M.
@@ -332,69 +362,80 @@ __global__ __launch_bounds__(1024) void k_lut_scan(int32_t* base, int nb, int64_
   }
 }
 
-// Pass 3: block = one group of 64 columns.  Wave 0 derives each column's
-// window-local occupancy mask and first rank; then the block walks the
-// group's nz*64 table entries in table order (coalesced reads of passes,
-// coalesced table writes).
+// Pass 3: block = a storage region of 4 x 16 columns (four 4 x 4 bricks,
+// contiguous in memory).  The passes of the region are read in storage order
+// into LDS, then every column's table entries are written in window-local z
+// order (a transpose through LDS keeps both sides coalesced).
+constexpr int kRegCols = 64;
+
 __global__ __launch_bounds__(kBlock) void k_lut_write(LutArgs a, uint32_t nz_magic) {
-  __shared__ unsigned long long slo[kGroup], shi[kGroup];
-  __shared__ int32_t sbase[kGroup];
-  __shared__ int64_t sbaseidx[kGroup];
+  extern __shared__ int32_t lpass[];  // [64][nz + 1]
+  __shared__ unsigned long long slo[kRegCols], shi[kRegCols];
+  __shared__ int32_t sbase[kRegCols];
+  __shared__ int64_t scb[kRegCols], slut[kRegCols];
   const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, W = a.d.W, roz = a.d.ro[2];
-  const int C = nx * ny;
-  const int g = blockIdx.x;
-  const int c0 = g * kGroup;
-  const int ncols = min(kGroup, C - c0);
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    const int c = c0 + lane;
-    int cnt = 0;
+  const int nzp = nz + 1;
+  const int bxr = blockIdx.x, byr = blockIdx.y;  // brick row, group of 4 bricks
+  if (threadIdx.x < kRegCols) {
+    const int t = threadIdx.x;
+    const int ix = t >> 4, jy = t & 15;
+    const int sx = 4 * bxr + ix, sy = 16 * byr + jy;
     Mask128 m = {0ull, 0ull};
-    int64_t scol = 0;
-    if (lane < ncols) {
-      const int x = c / ny, y = c - x * ny;
-      scol = (int64_t)wrap_add(x + a.d.ro[0], nx) * ny + wrap_add(y + a.d.ro[1], ny);
-      m = local_mask(a.occ, scol, W, nz, roz);
-      cnt = __popcll(m.lo) + __popcll(m.hi);
+    int32_t base = 0;
+    int64_t cb = -1, lrow = 0;
+    if (sx < nx && sy < ny) {
+      const int x = sx - a.d.ro[0] + (sx < a.d.ro[0] ? nx : 0);
+      const int y = sy - a.d.ro[1] + (sy < a.d.ro[1] ? ny : 0);
+      const int c = x * ny + y;
+      m = local_mask(a.occ, (int64_t)sx * ny + sy, W, nz, roz);
+      base = a.block_base[c >> 6] + a.colpre[c];
+      cb = col_base(a.d, sx, sy);
+      lrow = (int64_t)c * nz;
     }
-    int incl = cnt;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int u = __shfl_up(incl, o);
-      if (lane >= o) incl += u;
-    }
-    slo[lane] = m.lo;
-    shi[lane] = m.hi;
-    sbase[lane] = a.block_base[g] + incl - cnt;
-    sbaseidx[lane] = scol * nz;
+    slo[t] = m.lo;
+    shi[t] = m.hi;
+    sbase[t] = base;
+    scb[t] = cb;
+    slut[t] = lrow;
+  }
+  // storage-order read of the region: brick b (0..3), level z, lane16 = 4 iy + ix
+  const int nbricks = min(4, a.d.nby - 4 * byr);
+  const int64_t r0 = col_base(a.d, 4 * bxr, 16 * byr);
+  const int total = nbricks * nz * 16;
+  const int32_t* __restrict__ passes = a.passes;
+#pragma unroll 4
+  for (int k = threadIdx.x; k < total; k += kBlock) {
+    const int bz = k >> 4, l16 = k & 15;
+    const int b = nz == 1 ? bz : (int)__umulhi((uint32_t)bz, nz_magic);
+    const int z = bz - b * nz;
+    const int slot = (l16 & 3) * 16 + 4 * b + (l16 >> 2);
+    lpass[slot * nzp + z] = passes[r0 + k];
   }
   __syncthreads();
-  const int32_t* __restrict__ passes = a.passes;
-  const int32_t* __restrict__ hits = a.hits;
-  const int32_t* __restrict__ minqz = a.minqz;
-  int32_t* __restrict__ lut = a.lut + (int64_t)c0 * nz;
-  const int total = ncols * nz;
-#pragma unroll 4
-  for (int t = threadIdx.x; t < total; t += kBlock) {
-    const int col = nz == 1 ? t : (int)__umulhi((uint32_t)t, nz_magic);
-    const int z = t - col * nz;
-    const Mask128 m = {slo[col], shi[col]};
-    const int64_t e = sbaseidx[col] + wrap_add(z + roz, nz);
-    int32_t v;
-    if (test_bit(m, z)) {
-      const int32_t rank = sbase[col] + rank_below(m, z);
-      v = rank;
-      if (rank < a.cap) {
-        map_voxel_t d;
-        d.hits = hits[e];
-        d.passes = passes[e];
-        d.min_qz = minqz[e];
-        a.data[rank] = d;
+  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+  for (int t = wv; t < kRegCols; t += kBlock / 64) {
+    if (scb[t] < 0) continue;
+    const Mask128 m = {slo[t], shi[t]};
+    int32_t* __restrict__ lut = a.lut + slut[t];
+    for (int z = lane; z < nz; z += 64) {
+      const int zs = wrap_add(z + roz, nz);
+      int32_t v;
+      if (test_bit(m, z)) {
+        const int32_t rank = sbase[t] + rank_below(m, z);
+        v = rank;
+        if (rank < a.cap) {
+          const int64_t e = scb[t] + ((int64_t)zs << 4);
+          map_voxel_t d;
+          d.hits = a.hits[e];
+          d.passes = lpass[t * nzp + zs];
+          d.min_qz = a.minqz[e];
+          a.data[rank] = d;
+        }
+      } else {
+        v = -1 - lpass[t * nzp + zs];
       }
-    } else {
-      v = -1 - passes[e];
+      lut[z] = v;
     }
-    lut[t] = v;
   }
 }
 
@@ -409,7 +450,9 @@ __global__ __launch_bounds__(kBlock) void k_import(Dims d, const int32_t* lut,
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   if (c >= (int64_t)nx * ny) return;
   const int x = (int)(c / ny), y = (int)(c - (int64_t)x * ny);
-  const int64_t scol = (int64_t)wrap_add(x + d.ro[0], nx) * ny + wrap_add(y + d.ro[1], ny);
+  const int sx = wrap_add(x + d.ro[0], nx), sy = wrap_add(y + d.ro[1], ny);
+  const int64_t scol = (int64_t)sx * ny + sy;
+  const int64_t cb = col_base(d, sx, sy);
   unsigned long long w0 = 0, w1 = 0;
   for (int zb = 0; zb < nz; zb += 64) {
     const int z = zb + lane;
@@ -417,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_import(Dims d, const int32_t* lut,
     if (z < nz) {
       const int32_t v = lut[c * nz + z];
       const int sz = wrap_add(z + d.ro[2], nz);
-      const int64_t e = scol * nz + sz;
+      const int64_t e = cb + ((int64_t)sz << 4);
       int32_t h = 0, p = 0, mq = INT32_MAX;
       if (v >= 0) {
         if (v < n_data && data[v].hits >= 1) {
@@ -483,12 +526,14 @@ hipError_t launch_surface(const SurfaceArgs& a, hipStream_t s) {
 hipError_t launch_lut(const LutArgs& a, hipStream_t s) {
   const int C = a.d.nx * a.d.ny;
   const int ng = (C + kGroup - 1) / kGroup;
-  // t / nz == umulhi(t, ceil(2^32 / nz)) for every t < 2^20 (here t < 64 * 128)
+  // b / nz == umulhi(b, ceil(2^32 / nz)) for every b < 2^20 (here b < 4 * 128)
   const uint32_t magic =
       a.d.nz > 1 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)a.d.nz - 1) / (uint64_t)a.d.nz) : 0u;
+  const size_t lds = (size_t)kRegCols * (a.d.nz + 1) * 4;
   hipLaunchKernelGGL(k_lut_count, dim3((C + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_lut_scan, dim3(1), dim3(1024), 0, s, a.block_base, ng, a.n_occupied);
-  hipLaunchKernelGGL(k_lut_write, dim3(ng), dim3(kBlock), 0, s, a, magic);
+  dim3 g((a.d.nx + 3) / 4, (a.d.nby + 3) / 4);
+  hipLaunchKernelGGL(k_lut_write, g, dim3(kBlock), lds, s, a, magic);
   return hipGetLastError();
 }
 

@@ -1,9 +1,13 @@
 // Internal declarations shared by the host code and the kernels of libgvom.
 //
 // Storage layout on the device (per map):
-//   hits, passes, min_qz : int32[nx][ny][nz], z fastest, TOROIDAL: world voxel
-//                          g is stored at (g mod nx, g mod ny, g mod nz), so a
-//                          moving window only clears the slabs it enters.
+//   hits, passes, min_qz : int32 per voxel, TOROIDAL: world voxel g is stored
+//                          at storage coordinate s = (g mod nx, g mod ny,
+//                          g mod nz), so a moving window only clears the slabs
+//                          it enters.  Columns are grouped in 4 x 4 bricks:
+//                          voxel s lives at col_base(sx, sy) + 16 sz, so one
+//                          64-byte line holds one z level of a brick and
+//                          neighbouring columns share lines.
 //   occ                  : uint64[nx*ny][W], W = ceil(nz/64): bit (s mod 64) of
 //                          word s/64 is set iff storage z = s of that column
 //                          holds a return (hits >= 1).
@@ -20,7 +24,16 @@ namespace gvom {
 struct Dims {
   int32_t nx, ny, nz, W;  // W = occupancy words per column
   int32_t ro[3];          // ring offsets
+  int32_t nby;            // bricks along y = ceil(ny / 4)
+  int64_t vs;             // storage voxels = ceil(nx/4) * nby * nz * 16
 };
+
+// Storage index of z = 0 of storage column (sx, sy); z adds 16 per level.
+__host__ __device__ __forceinline__ int32_t col_base(const Dims& d, int32_t sx, int32_t sy) {
+  return ((((sx >> 2) * d.nby + (sy >> 2)) * d.nz) << 4) + ((sy & 3) << 2) + (sx & 3);
+}
+
+constexpr int kStripes = 16;  // independent segment counters of the ray pass
 
 struct InsertArgs {
   const float* xyz;
@@ -36,21 +49,22 @@ struct InsertArgs {
   int32_t* passes;
   int32_t* minqz;
   unsigned long long* occ;
-  unsigned long long* stats;   // [n_nonfinite, n_range, n_hits, n_pass, dpass, dhit,
-                               //  ray-segment count]
+  unsigned long long* stats;   // [8 global counters][kStripes segment counters]
   uint32_t* touch;             // distinct-voxel bitmaps [2][V/32] or null
   unsigned long long* part_rays;   // per ray block: nonfinite, range, hits, distinct hits
   unsigned long long* part_trace;  // per trace block: passes, distinct passes
   int4* items;                 // ray segments {Qx, Qy, Qz, segment index}
   int64_t item_cap;
+  int64_t stripe_off[kStripes];  // item region of each stripe of ray blocks
+  int64_t stripe_cap[kStripes];
   int32_t seg_len;             // dominant-axis voxels per segment
   int32_t trace_blocks;        // grid of the trace kernel
 };
 
 constexpr int kRayBlock = 1024;   // threads per block of the ray pass
 
-// Upper bound of the ray segments of a scan of n points (items buffer size).
-int64_t segment_capacity(int64_t n, const Dims& d, int32_t seg_len);
+// Segments one ray can produce at most.
+int64_t max_segments(const Dims& d, int32_t seg_len);
 
 struct ColumnArgs {
   Dims d;
@@ -88,7 +102,8 @@ struct LutArgs {
   int32_t* lut;
   map_voxel_t* data;
   int64_t cap;
-  int32_t* block_base;    // per 256-column block: exclusive rank base
+  int32_t* block_base;    // per group of 64 window-local columns: exclusive rank base
+  int32_t* colpre;        // per window-local column: exclusive rank within its group
   int64_t* n_occupied;
 };
 

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kRayBlock) void k_rays(InsertArgs a) {
       const int32_t ey = wrap_add(l[1] + a.d.ro[1], dims[1]);
       const int32_t ez = wrap_add(l[2] + a.d.ro[2], dims[2]);
       const int32_t col = ex * dims[1] + ey;
-      const int32_t e = col * dims[2] + ez;
+      const int32_t e = col_base(a.d, ex, ey) + (ez << 4);
       atomicAdd(&a.hits[e], 1);
       // min and or only move one way: a plain read that already satisfies
       // the update makes the atomic unnecessary
@@ -145,8 +145,10 @@ __global__ __launch_bounds__(kRayBlock) void k_rays(InsertArgs a) {
       s2 += wcount[w][3];
       s5 += wcount[w][4];
     }
-    const unsigned long long b = sum ? atomicAdd(&a.stats[6], sum) : 0ull;
-    for (int w = 0; w < kRayBlock / 64; w++) wbase[w] += b;
+    // blocks are spread over kStripes counters, each with its own item region
+    const int st = blockIdx.x % kStripes;
+    const unsigned long long b = sum ? atomicAdd(&a.stats[8 + st], sum) : 0ull;
+    for (int w = 0; w < kRayBlock / 64; w++) wbase[w] += b + a.stripe_off[st];
     unsigned long long* pr = a.part_rays + 4 * (size_t)blockIdx.x;
     pr[0] = s0;
     pr[1] = s1;
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(kRayBlock) void k_rays(InsertArgs a) {
     if (nseg > j) {
       const unsigned long long pos =
           off + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
-      if ((int64_t)pos < a.item_cap) a.items[pos] = make_int4(q[0], q[1], q[2], j);
+      a.items[pos] = make_int4(q[0], q[1], q[2], j);
     }
     off += __popcll(m);
   }
@@ -203,11 +205,16 @@ __global__ __launch_bounds__(kBlock) void k_trace(InsertArgs a) {
   const int lane = __lane_id();
   const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
   const int32_t dims[3] = {nx, ny, nz};
-  const int64_t count = min((int64_t)a.stats[6], a.item_cap);
+  // items of stripe t occupy [stripe_off[t], stripe_off[t] + cnt[t]); the
+  // loop runs over their concatenation
+  int64_t pre[kStripes + 1];
+  pre[0] = 0;
+#pragma unroll
+  for (int t = 0; t < kStripes; t++)
+    pre[t + 1] = pre[t] + min((int64_t)a.stats[8 + t], a.stripe_cap[t]);
+  const int64_t count = pre[kStripes];
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  const int64_t V = (int64_t)nx * ny * nz;
-  uint32_t* touch_p = DISTINCT ? a.touch + ((V + 31) >> 5) : nullptr;
-  const int32_t span_x = ny * nz, span_xw = nx * ny * nz, span_yw = ny * nz;
+  uint32_t* touch_p = DISTINCT ? a.touch + ((a.d.vs + 31) >> 5) : nullptr;
   int n_pass = 0, n_dpass = 0;
 
   for (int64_t wbase = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); wbase < count;
@@ -220,7 +227,10 @@ __global__ __launch_bounds__(kBlock) void k_trace(InsertArgs a) {
     int32_t sidx = 0, segleft = 0;
     bool mdx = false, mdy = false, mdz = false;
     if (it < count) {
-      const int4 item = a.items[it];
+      int t = 0;
+#pragma unroll
+      for (int k = 1; k < kStripes; k++) t += it >= pre[k];
+      const int4 item = a.items[a.stripe_off[t] + (it - pre[t])];
       const int32_t q[3] = {item.x, item.y, item.z};
       const int j = item.w;
       int32_t sv[3], ev[3], n[3], ad[3];
@@ -279,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(InsertArgs a) {
         kyz = (int64_t)ad[2] << 16;
         kzx = (int64_t)ad[0] << 16;
         kzy = (int64_t)ad[1] << 16;
-        sidx = (sc[0] * ny + sc[1]) * nz + sc[2];
+        sidx = col_base(a.d, sc[0], sc[1]) + (sc[2] << 4);
         segleft = a.seg_len - 1;
         mdx = dom == 0;
         mdy = dom == 1;
@@ -290,10 +300,8 @@ __global__ __launch_bounds__(kBlock) void k_trace(InsertArgs a) {
 
     // per-lane constants of the branch-free step
     const bool px = sg[0] > 0, py = sg[1] > 0, pz = sg[2] > 0;
-    const int32_t ds0 = sg[0] * span_x, ds1 = sg[1] * nz, ds2 = sg[2];
     const int32_t trig0 = px ? nx : -1, trig1 = py ? ny : -1, trig2 = pz ? nz : -1;
     const int32_t wv0 = px ? 0 : nx - 1, wv1 = py ? 0 : ny - 1, wv2 = pz ? 0 : nz - 1;
-    const int32_t wc0 = -sg[0] * span_xw, wc1 = -sg[1] * span_yw, wc2 = -sg[2] * nz;
     while (__any(active)) {
       // ---- aggregated pass of the current voxel: runs of equal addresses in
       // neighbouring lanes (left neighbour via a whole-wave DPP shift)
@@ -343,8 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(InsertArgs a) {
       sc[0] = w0 ? wv0 : t0;
       sc[1] = w1 ? wv1 : t1;
       sc[2] = w2 ? wv2 : t2;
-      sidx += (mx ? ds0 : 0) + (my ? ds1 : 0) + (mz ? ds2 : 0) + (w0 ? wc0 : 0) +
-              (w1 ? wc1 : 0) + (w2 ? wc2 : 0);
+      sidx = col_base(a.d, sc[0], sc[1]) + (sc[2] << 4);
       active = active & !out & (rem[0] + rem[1] + rem[2] > 0);
     }
   }
@@ -384,7 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_clear_box(Dims d, int32_t* hits, int
     const uint32_t sx = (x0 + kx) % (uint32_t)d.nx;
     const uint32_t sy = (y0 + ky) % (uint32_t)d.ny;
     const uint32_t sz = (z0 + kz) % (uint32_t)d.nz;
-    const uint32_t e = (sx * d.ny + sy) * d.nz + sz;
+    const uint32_t e = (uint32_t)col_base(d, sx, sy) + (sz << 4);
     hits[e] = 0;
     passes[e] = 0;
     minqz[e] = INT32_MAX;
@@ -447,10 +454,10 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-int64_t segment_capacity(int64_t n, const Dims& d, int32_t seg_len) {
+int64_t max_segments(const Dims& d, int32_t seg_len) {
   int32_t m = d.nx > d.ny ? d.nx : d.ny;
   if (d.nz > m) m = d.nz;
-  return n * ((m - 1) / seg_len + 1);
+  return (m - 1) / seg_len + 1;
 }
 
 hipError_t launch_insert(const InsertArgs& a, bool distinct, hipStream_t s) {
