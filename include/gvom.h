@@ -214,6 +214,50 @@ int32_t map_get_tuning(const map_t* m, map_tuning_t* out);
 int32_t map_profile_enable(map_t* m, int32_t enable);
 int32_t map_profile_read(map_t* m, double ms[MAP_PROF_N], int64_t count[MAP_PROF_N]);
 
+/* ---- batched serving (project extension, not in the paper) ---------------
+ * Many vehicles' maps are stepped together: every stage of every map runs in
+ * one persistent kernel per stage (grids sized to the device, walking the
+ * maps' work from a descriptor table uploaded once per step), and the whole
+ * step is captured once in a HIP graph and replayed. */
+typedef struct map_batch_t map_batch_t;
+
+/* Groups k distinct maps (1..64, created on the current device) for batched
+ * steps enqueued on `stream` (NULL: the batch creates a stream of its own,
+ * since graphs cannot be captured on the null stream).  A map may still be used by the single-map calls
+ * between batch steps, never concurrently with one. */
+int32_t map_batch_create(map_t* const* maps, int32_t k, void* stream, map_batch_t** out);
+int32_t map_batch_destroy(map_batch_t* b);
+
+/* One step: for every map i, the same results as map_insert_scan(maps[i],
+ * xyz_dev[i], n[i], poses + 12*i, flags[i]) followed by map_export_2d(maps[i],
+ * out2d + i) and, when lut_dev != NULL and lut_dev[i] != NULL,
+ * map_export_voxels(maps[i], lut_dev[i], data_dev[i], cap[i],
+ * n_occupied_dev[i], ...).  xyz_dev, n, poses, flags, out2d are arrays of k
+ * (host arrays of device pointers where pointers); MAP_STATS_DISTINCT is not
+ * accepted here.  Every request is checked before any map changes.
+ * Synchronises (the per-map latencies are then available). */
+int32_t map_batch_step(map_batch_t* b, const float* const* xyz_dev, const int64_t* n,
+                       const float* poses, const uint32_t* flags, const map_2d_t* out2d,
+                       int32_t* const* lut_dev, map_voxel_t* const* data_dev,
+                       const int64_t* cap, int64_t* const* n_occupied_dev);
+
+/* Latency of map i in the last step, ms: the device wall-clock time from the
+ * start of the step to the end of map i's last kernel block.  ms[k]. */
+int32_t map_batch_latency(const map_batch_t* b, double* ms);
+
+/* Graph replay on (default) or off (plain stream launches of the same kernels). */
+int32_t map_batch_set_graph(map_batch_t* b, int32_t enable);
+
+/* Autotuner: times every candidate tuning (seg_len 16/32/64 x
+ * trace_waves_per_cu 8/16/32) on this step's inputs with batch steps, applies
+ * the fastest to all maps and appends it to the text cache `cache_path`
+ * (NULL: no cache).  A cached entry for the same device, map shapes and
+ * point-count range is applied without timing.  The maps are left empty
+ * (map_reset) because the timing steps insert the inputs. */
+int32_t map_batch_autotune(map_batch_t* b, const float* const* xyz_dev, const int64_t* n,
+                           const float* poses, const uint32_t* flags, const map_2d_t* out2d,
+                           const char* cache_path, map_tuning_t* chosen);
+
 /* Static text for a status code. */
 const char* map_status_str(int32_t status);
 

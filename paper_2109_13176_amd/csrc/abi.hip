@@ -4,9 +4,13 @@
 // kernel launches on the map's stream.  Nothing here waits on the device
 // except where gvom.h says a call synchronises.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
+#include <stdio.h>
+
 #include <new>
+#include <string>
 #include <vector>
 
 #include "gvom_internal.h"
@@ -96,9 +100,10 @@ void initial_origin(map_t* m) {
   set_ring(m);
 }
 
-// Moves the window to new origin `o` (whole voxels, Sec. III-A): clears the
-// storage slabs that the new window takes over from the old one.
-hipError_t move_window(map_t* m, const int32_t o[3]) {
+// Moves the window to new origin `o` (whole voxels, Sec. III-A) and plans the
+// clears of the storage slabs the new window takes over from the old one.
+// Returns true when the whole window must be cleared.
+bool move_window(map_t* m, const int32_t o[3], gvom::ClearArgs* plan) {
   const int32_t n[3] = {m->p.nx, m->p.ny, m->p.nz};
   int64_t delta[3];
   bool all = false;
@@ -106,53 +111,57 @@ hipError_t move_window(map_t* m, const int32_t o[3]) {
     delta[a] = (int64_t)o[a] - m->origin[a];
     if (delta[a] >= n[a] || -delta[a] >= n[a]) all = true;
   }
+  plan->d = m->d;
+  plan->hits = m->hits;
+  plan->passes = m->passes;
+  plan->minqz = m->minqz;
+  plan->occ = m->occ;
+  plan->nbox = 0;
   m->last_cleared = 0;
-  if (delta[0] == 0 && delta[1] == 0 && delta[2] == 0) return hipSuccess;
+  if (delta[0] == 0 && delta[1] == 0 && delta[2] == 0) return false;
   for (int a = 0; a < 3; a++) m->origin[a] = o[a];
   set_ring(m);
+  plan->d = m->d;
   if (all) {
     m->last_cleared = n_vox(m);
-    return clear_all(m);
+    int32_t* b = plan->box[0];
+    b[0] = 0; b[1] = n[0]; b[2] = 0; b[3] = n[1]; b[4] = 0; b[5] = n[2];
+    plan->keep[0][0] = plan->keep[0][1] = 0ull;
+    plan->nbox = 1;
+    return true;
   }
   int64_t keep = 1;
   for (int a = 0; a < 3; a++) keep *= n[a] - (delta[a] < 0 ? -delta[a] : delta[a]);
   m->last_cleared = n_vox(m) - keep;
-  // storage range of the entering local range along axis a
-  int32_t s0[3], cnt[3];
   for (int a = 0; a < 3; a++) {
-    if (delta[a] > 0) {
-      s0[a] = pos_mod((int64_t)n[a] - delta[a] + m->d.ro[a], n[a]);
-      cnt[a] = (int32_t)delta[a];
-    } else {
-      s0[a] = m->d.ro[a];
-      cnt[a] = (int32_t)-delta[a];
+    if (delta[a] == 0) continue;
+    // storage range of the entering local range along axis a
+    const int32_t s0 = delta[a] > 0 ? pos_mod((int64_t)n[a] - delta[a] + m->d.ro[a], n[a])
+                                    : m->d.ro[a];
+    const int32_t cnt = (int32_t)(delta[a] > 0 ? delta[a] : -delta[a]);
+    int32_t* b = plan->box[plan->nbox];
+    b[0] = 0; b[1] = n[0]; b[2] = 0; b[3] = n[1]; b[4] = 0; b[5] = n[2];
+    b[2 * a] = s0;
+    b[2 * a + 1] = cnt;
+    unsigned long long k0 = 0ull, k1 = 0ull;
+    if (a == 2) {
+      k0 = k1 = ~0ull;
+      for (int j = 0; j < cnt; j++) {
+        const int z = (s0 + j) % n[2];
+        if (z < 64) k0 &= ~(1ull << z); else k1 &= ~(1ull << (z - 64));
+      }
     }
+    plan->keep[plan->nbox][0] = k0;
+    plan->keep[plan->nbox][1] = k1;
+    plan->nbox++;
   }
-  hipError_t e = hipSuccess;
-  if (cnt[0]) {
-    e = gvom::launch_clear_box(m->d, m->hits, m->passes, m->minqz, s0[0], cnt[0], 0, n[1], 0,
-                               n[2], m->stream);
-    if (e == hipSuccess)
-      e = gvom::launch_clear_occ(m->d, m->occ, s0[0], cnt[0], 0, n[1], 0ull, 0ull, m->stream);
-  }
-  if (cnt[1] && e == hipSuccess) {
-    e = gvom::launch_clear_box(m->d, m->hits, m->passes, m->minqz, 0, n[0], s0[1], cnt[1], 0,
-                               n[2], m->stream);
-    if (e == hipSuccess)
-      e = gvom::launch_clear_occ(m->d, m->occ, 0, n[0], s0[1], cnt[1], 0ull, 0ull, m->stream);
-  }
-  if (cnt[2] && e == hipSuccess) {
-    e = gvom::launch_clear_box(m->d, m->hits, m->passes, m->minqz, 0, n[0], 0, n[1], s0[2],
-                               cnt[2], m->stream);
-    unsigned long long k0 = ~0ull, k1 = ~0ull;
-    for (int j = 0; j < cnt[2]; j++) {
-      const int z = (s0[2] + j) % n[2];
-      if (z < 64) k0 &= ~(1ull << z); else k1 &= ~(1ull << (z - 64));
-    }
-    if (e == hipSuccess)
-      e = gvom::launch_clear_occ(m->d, m->occ, 0, n[0], 0, n[1], k0, k1, m->stream);
-  }
-  return e;
+  return false;
+}
+
+hipError_t run_move(map_t* m, const int32_t o[3]) {
+  gvom::ClearArgs plan;
+  if (move_window(m, o, &plan)) return clear_all(m);
+  return gvom::launch_clear(plan, m->stream);
 }
 
 // Records the start event of a profiled phase (no-op when profiling is off).
@@ -313,123 +322,193 @@ int32_t map_reset(map_t* m) {
   return dev_status(m, e);
 }
 
-int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float pose[12],
-                        uint32_t flags) {
+}  // extern "C"
+
+namespace {
+
+// Checks an insert request without changing anything; derives the sensor Q.
+int32_t check_insert(const map_t* m, const float* xyz_dev, int64_t n, const float* pose,
+                     uint32_t flags, int32_t S[3]) {
   if (!m || !pose || n < 0 || n > 2147483647LL || (n > 0 && !xyz_dev)) return MAP_E_INVALID;
   if (flags & 0x0000FFFCu) return MAP_E_INVALID;
   if (m->sticky) return m->sticky;
   for (int i = 0; i < 12; i++)
     if (!isfinite(pose[i])) return MAP_E_POSE;
-  int32_t S[3], sv[3];
   for (int i = 0; i < 3; i++) {
     const float u = pose[4 * i + 3] * m->c.inv_r;
     if (!(fabsf(u) < 32768.0f)) return MAP_E_RANGE;
     S[i] = (int32_t)floorf(u * 65536.0f);
-    sv[i] = S[i] >> 16;
   }
-  // segment buffer for the traversal pass (grows before any work is enqueued):
-  // ray block b writes into the region of stripe b mod kStripes, sized for the
-  // most segments that stripe's points can produce
+  if (!(flags & MAP_RECENTER)) {
+    const int32_t n3[3] = {m->p.nx, m->p.ny, m->p.nz};
+    for (int a = 0; a < 3; a++) {
+      const int64_t l = (int64_t)(S[a] >> 16) - m->origin[a];
+      if (l < 0 || l >= n3[a]) return MAP_E_SENSOR_OUTSIDE;
+    }
+  }
+  return MAP_OK;
+}
+
+// Grows a device buffer (synchronising first); false on allocation failure.
+template <class T>
+bool grow(map_t* m, T** p, int64_t* cap, int64_t need, size_t elem) {
+  if (need <= *cap) return true;
+  if (hipStreamSynchronize(m->stream) != hipSuccess) return false;
+  (void)hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  if (dmalloc(p, (size_t)need * elem) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return false;
+  }
+  *cap = need;
+  return true;
+}
+
+// Second half of an insert (after check_insert): grows the per-scan buffers,
+// moves the window (the slab clears go to `plan`; *full = whole window), and
+// fills the kernel arguments.  Updates the host-side map state.
+int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* pose,
+                       uint32_t flags, const int32_t S[3], gvom::InsertArgs* a,
+                       gvom::ClearArgs* plan, bool* full) {
+  // ray block b writes its segments into the region of stripe b mod kStripes,
+  // sized for the most segments that stripe's points can produce
   const int64_t ray_blocks = (n + gvom::kRayBlock - 1) / gvom::kRayBlock;
   const int64_t per_ray = gvom::max_segments(m->d, m->seg_len);
-  int64_t stripe_off[gvom::kStripes], stripe_cap[gvom::kStripes], need = 0;
+  int64_t need = 0;
   for (int t = 0; t < gvom::kStripes; t++) {
-    const int64_t blocks = ray_blocks > t ? (ray_blocks - t + gvom::kStripes - 1) / gvom::kStripes : 0;
+    const int64_t blocks =
+        ray_blocks > t ? (ray_blocks - t + gvom::kStripes - 1) / gvom::kStripes : 0;
     int64_t pts = blocks * gvom::kRayBlock;
     if (blocks && t == (ray_blocks - 1) % gvom::kStripes)
       pts -= ray_blocks * gvom::kRayBlock - n;  // the last block is partial
-    stripe_off[t] = need;
-    stripe_cap[t] = pts * per_ray;
-    need += stripe_cap[t];
+    a->stripe_off[t] = need;
+    a->stripe_cap[t] = pts * per_ray;
+    need += a->stripe_cap[t];
   }
-  if (need > m->item_cap) {
-    if (hipStreamSynchronize(m->stream) != hipSuccess) return dev_status(m, hipErrorUnknown);
-    (void)hipFree(m->items);
-    m->items = nullptr;
-    m->item_cap = 0;
-    if (dmalloc(&m->items, (size_t)need * sizeof(int4)) != hipSuccess) {
-      (void)hipGetLastError();
-      m->items = nullptr;
-      return MAP_E_OOM;
-    }
-    m->item_cap = need;
-  }
-  if (ray_blocks > m->part_rays_cap) {
-    if (hipStreamSynchronize(m->stream) != hipSuccess) return dev_status(m, hipErrorUnknown);
-    (void)hipFree(m->part_rays);
-    m->part_rays = nullptr;
-    m->part_rays_cap = 0;
-    if (dmalloc(&m->part_rays, (size_t)ray_blocks * 32) != hipSuccess) {
-      (void)hipGetLastError();
-      m->part_rays = nullptr;
-      return MAP_E_OOM;
-    }
-    m->part_rays_cap = ray_blocks;
-  }
-  hipError_t e = hipSuccess;
+  if (!grow(m, &m->items, &m->item_cap, need, sizeof(int4))) return MAP_E_OOM;
+  if (!grow(m, &m->part_rays, &m->part_rays_cap, ray_blocks, 32)) return MAP_E_OOM;
+  *full = false;
+  plan->nbox = 0;
   if (flags & MAP_RECENTER) {
-    const int32_t o[3] = {sv[0] - m->p.nx / 2, sv[1] - m->p.ny / 2,
-                          sv[2] - m->p.sensor_z_voxel};
-    const int pm = prof_begin(m, MAP_PROF_SCROLL);
-    e = move_window(m, o);
-    prof_end(m, pm);
+    const int32_t o[3] = {(S[0] >> 16) - m->p.nx / 2, (S[1] >> 16) - m->p.ny / 2,
+                          (S[2] >> 16) - m->p.sensor_z_voxel};
+    *full = move_window(m, o, plan);
   } else {
-    const int32_t n3[3] = {m->p.nx, m->p.ny, m->p.nz};
-    for (int a = 0; a < 3; a++) {
-      const int64_t l = (int64_t)sv[a] - m->origin[a];
-      if (l < 0 || l >= n3[a]) return MAP_E_SENSOR_OUTSIDE;
-    }
     m->last_cleared = 0;
   }
-  const bool distinct = (flags & MAP_STATS_DISTINCT) != 0;
   m->last_points = n;
+  m->last_distinct = false;
+  m->last_ray_blocks = n > 0 ? ray_blocks : 0;
+  a->xyz = xyz_dev;
+  a->n = (int32_t)n;
+  uint32_t fw = flags >> 16;
+  if (fw < 1 || (n > 0 && n % fw != 0)) fw = 1;
+  a->fw = (int32_t)fw;
+  a->azimuths = (int32_t)(n / fw);
+  for (int i = 0; i < 3; i++) {
+    for (int j = 0; j < 3; j++) a->R[3 * i + j] = pose[4 * i + j];
+    a->t[i] = pose[4 * i + 3];
+    a->S[i] = S[i];
+    a->O[i] = m->origin[i];
+  }
+  a->inv_r = m->c.inv_r;
+  a->d = m->d;
+  a->hits = m->hits;
+  a->passes = m->passes;
+  a->minqz = m->minqz;
+  a->occ = m->occ;
+  a->stats = m->stats;
+  a->touch = m->touch;
+  a->items = m->items;
+  a->part_rays = m->part_rays;
+  a->part_trace = m->part_trace;
+  a->item_cap = m->item_cap;
+  a->seg_len = m->seg_len;
+  const int64_t want = (need + 255) / 256;
+  const int64_t lim = (int64_t)m->n_cu * m->trace_wpc / 4;
+  a->trace_blocks = n > 0 ? (int32_t)(want < lim ? want : lim) : 0;
+  m->last_trace_blocks = a->trace_blocks;
+  return MAP_OK;
+}
+
+void column_args(const map_t* m, const map_2d_t* out, gvom::ColumnArgs* ca) {
+  ca->d = m->d;
+  ca->hits = m->hits;
+  ca->passes = m->passes;
+  ca->minqz = m->minqz;
+  ca->occ = m->occ;
+  ca->res = (double)m->p.res_m;
+  ca->n_lo = m->c.n_lo;
+  ca->n_hi = m->c.n_hi;
+  ca->dens_num = m->p.dens_num;
+  ca->dens_den = m->p.dens_den;
+  ca->height = out->height;
+  ca->density = out->density;
+  ca->flags = out->flags;
+  ca->hq = m->hq;
+}
+
+void surface_args(const map_t* m, const map_2d_t* out, gvom::SurfaceArgs* sa) {
+  sa->nx = m->p.nx;
+  sa->ny = m->p.ny;
+  sa->hq = m->hq;
+  sa->half_fit = m->c.half_fit;
+  sa->search_d = m->c.search_d;
+  sa->tau_q = m->c.tau_neg_q;
+  sa->q2m = (double)m->p.res_m / 65536.0;
+  sa->slope = out->slope;
+  sa->rough = out->rough;
+  sa->flags = out->flags;
+}
+
+void lut_args(const map_t* m, int32_t* lut_dev, map_voxel_t* data_dev, int64_t cap,
+              int64_t* n_occupied_dev, gvom::LutArgs* a) {
+  a->d = m->d;
+  a->hits = m->hits;
+  a->passes = m->passes;
+  a->minqz = m->minqz;
+  a->occ = m->occ;
+  a->lut = lut_dev;
+  a->data = data_dev;
+  a->cap = cap;
+  a->block_base = m->block_base;
+  a->colpre = m->colpre;
+  a->n_occupied = n_occupied_dev;
+}
+
+bool valid_2d(const map_2d_t* out) {
+  return out && out->height && out->slope && out->rough && out->density && out->flags;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float pose[12],
+                        uint32_t flags) {
+  int32_t S[3];
+  int32_t st = check_insert(m, xyz_dev, n, pose, flags, S);
+  if (st) return st;
+  gvom::InsertArgs a;
+  gvom::ClearArgs plan;
+  bool full = false;
+  const int pm0 = prof_begin(m, MAP_PROF_SCROLL);
+  st = prepare_insert(m, xyz_dev, n, pose, flags, S, &a, &plan, &full);
+  if (st) return st;
+  hipError_t e = full ? clear_all(m) : gvom::launch_clear(plan, m->stream);
+  prof_end(m, pm0);
+  const bool distinct = (flags & MAP_STATS_DISTINCT) != 0;
   m->last_distinct = distinct;
-  m->last_ray_blocks = 0;
-  m->last_trace_blocks = 0;
   if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, kStatsBytes, m->stream);
   if (distinct && e == hipSuccess) {
     const int64_t words = (n_store(m) + 31) / 32;
     if (!m->touch) e = dmalloc(&m->touch, words * 2 * 4);
     if (e == hipSuccess) e = hipMemsetAsync(m->touch, 0, words * 2 * 4, m->stream);
+    a.touch = m->touch;
   }
   if (e == hipSuccess && n > 0) {
-    gvom::InsertArgs a;
-    a.xyz = xyz_dev;
-    a.n = (int32_t)n;
-    uint32_t fw = flags >> 16;
-    if (fw < 1 || n % fw != 0) fw = 1;
-    a.fw = (int32_t)fw;
-    a.azimuths = (int32_t)(n / fw);
-    for (int i = 0; i < 3; i++) {
-      for (int j = 0; j < 3; j++) a.R[3 * i + j] = pose[4 * i + j];
-      a.t[i] = pose[4 * i + 3];
-      a.S[i] = S[i];
-      a.O[i] = m->origin[i];
-    }
-    a.inv_r = m->c.inv_r;
-    a.d = m->d;
-    a.hits = m->hits;
-    a.passes = m->passes;
-    a.minqz = m->minqz;
-    a.occ = m->occ;
-    a.stats = m->stats;
-    a.touch = m->touch;
-    a.items = m->items;
-    for (int t = 0; t < gvom::kStripes; t++) {
-      a.stripe_off[t] = stripe_off[t];
-      a.stripe_cap[t] = stripe_cap[t];
-    }
-    a.part_rays = m->part_rays;
-    a.part_trace = m->part_trace;
-    a.item_cap = m->item_cap;
-    a.seg_len = m->seg_len;
-    {
-      const int64_t want = (need + 255) / 256;
-      const int64_t lim = (int64_t)m->n_cu * m->trace_wpc / 4;
-      a.trace_blocks = (int32_t)(want < lim ? want : lim);
-    }
-    m->last_ray_blocks = ray_blocks;
-    m->last_trace_blocks = a.trace_blocks;
     const int pm = prof_begin(m, MAP_PROF_INSERT);
     e = gvom::launch_insert(a, distinct, m->stream);
     prof_end(m, pm);
@@ -438,39 +517,16 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
 }
 
 int32_t map_export_2d(map_t* m, const map_2d_t* out) {
-  if (!m || !out || !out->height || !out->slope || !out->rough || !out->density || !out->flags)
-    return MAP_E_INVALID;
+  if (!m || !valid_2d(out)) return MAP_E_INVALID;
   if (m->sticky) return m->sticky;
   gvom::ColumnArgs ca;
-  ca.d = m->d;
-  ca.hits = m->hits;
-  ca.passes = m->passes;
-  ca.minqz = m->minqz;
-  ca.occ = m->occ;
-  ca.res = (double)m->p.res_m;
-  ca.n_lo = m->c.n_lo;
-  ca.n_hi = m->c.n_hi;
-  ca.dens_num = m->p.dens_num;
-  ca.dens_den = m->p.dens_den;
-  ca.height = out->height;
-  ca.density = out->density;
-  ca.flags = out->flags;
-  ca.hq = m->hq;
+  column_args(m, out, &ca);
   int pm = prof_begin(m, MAP_PROF_COLUMN);
   hipError_t e = gvom::launch_column(ca, m->stream);
   prof_end(m, pm);
   if (e == hipSuccess) {
     gvom::SurfaceArgs sa;
-    sa.nx = m->p.nx;
-    sa.ny = m->p.ny;
-    sa.hq = m->hq;
-    sa.half_fit = m->c.half_fit;
-    sa.search_d = m->c.search_d;
-    sa.tau_q = m->c.tau_neg_q;
-    sa.q2m = (double)m->p.res_m / 65536.0;
-    sa.slope = out->slope;
-    sa.rough = out->rough;
-    sa.flags = out->flags;
+    surface_args(m, out, &sa);
     pm = prof_begin(m, MAP_PROF_SURFACE);
     e = gvom::launch_surface(sa, m->stream);
     prof_end(m, pm);
@@ -484,17 +540,7 @@ int32_t map_export_voxels(map_t* m, int32_t* lut_dev, map_voxel_t* data_dev, int
     return MAP_E_INVALID;
   if (m->sticky) return m->sticky;
   gvom::LutArgs a;
-  a.d = m->d;
-  a.hits = m->hits;
-  a.passes = m->passes;
-  a.minqz = m->minqz;
-  a.occ = m->occ;
-  a.lut = lut_dev;
-  a.data = data_dev;
-  a.cap = cap;
-  a.block_base = m->block_base;
-  a.colpre = m->colpre;
-  a.n_occupied = n_occupied_dev;
+  lut_args(m, lut_dev, data_dev, cap, n_occupied_dev, &a);
   const int pm = prof_begin(m, MAP_PROF_LUT);
   hipError_t e = gvom::launch_lut(a, m->stream);
   prof_end(m, pm);
@@ -615,6 +661,336 @@ int32_t map_profile_read(map_t* m, double ms[MAP_PROF_N], int64_t count[MAP_PROF
     }
   }
   prof_release(m);
+  return MAP_OK;
+}
+
+// ---- batches ---------------------------------------------------------------
+
+}  // extern "C"
+
+struct map_batch_t {
+  int k;
+  map_t* maps[gvom::kMaxBatch];
+  hipStream_t stream;
+  int device, n_cu;
+  gvom::BatchTables* dtab;
+  gvom::BatchTables* htab;  // pinned
+  unsigned long long* dstamps;
+  unsigned long long* hstamps;  // pinned
+  unsigned int* ddone;
+  gvom::BatchGrid grid;
+  bool use_graph, captured;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  bool own_stream;
+  double clock_khz;
+  double last_ms[gvom::kMaxBatch];
+};
+
+namespace {
+
+hipError_t enqueue_batch(map_batch_t* b) {
+  hipError_t e = hipMemcpyAsync(b->dtab, b->htab, sizeof(gvom::BatchTables),
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = gvom::launch_batch_insert(b->dtab, b->grid, b->dstamps, b->ddone, b->stream);
+  if (e == hipSuccess) e = gvom::launch_batch_export(b->dtab, b->grid, b->dstamps, b->ddone, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->hstamps, b->dstamps, (b->k + 1) * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, b->stream);
+  return e;
+}
+
+void batch_fail(map_batch_t* b, hipError_t e = hipSuccess) {
+  if (getenv("GVOM_DEBUG")) fprintf(stderr, "gvom batch: %s\n", hipGetErrorString(e));
+  (void)hipGetLastError();
+  for (int i = 0; i < b->k; i++) b->maps[i]->sticky = MAP_E_DEVICE;
+}
+
+// Fills the step table; the caller has checked every request.
+int32_t batch_prepare(map_batch_t* b, const float* const* xyz_dev, const int64_t* n,
+                      const float* poses, const uint32_t* flags, const map_2d_t* out2d,
+                      int32_t* const* lut_dev, map_voxel_t* const* data_dev, const int64_t* cap,
+                      int64_t* const* n_occupied_dev, const int32_t (*S)[3]) {
+  gvom::BatchTables* t = b->htab;
+  gvom::BatchStep& st = t->st;
+  st.nmaps = b->k;
+  st.pre_rays[0] = st.pre_trace[0] = st.pre_col[0] = st.pre_surf[0] = 0;
+  st.pre_lcount[0] = st.pre_lscan[0] = st.pre_lwrite[0] = 0;
+  const int tile = gvom::surface_tile();
+  for (int i = 0; i < b->k; i++) {
+    map_t* m = b->maps[i];
+    bool full = false;
+    const int32_t s = prepare_insert(m, xyz_dev[i], n[i], poses + 12 * i, flags[i], S[i],
+                                     &t->ins[i], &t->clr[i], &full);
+    if (s) return s;  // allocation failure
+    column_args(m, &out2d[i], &t->col[i]);
+    surface_args(m, &out2d[i], &t->sur[i]);
+    const bool lut = lut_dev && lut_dev[i];
+    if (lut) {
+      lut_args(m, lut_dev[i], data_dev ? data_dev[i] : nullptr, cap ? cap[i] : 0,
+               n_occupied_dev[i], &t->lut[i]);
+    }
+    const int64_t C = (int64_t)m->p.nx * m->p.ny;
+    const int ray_blocks = (int)((n[i] + gvom::kRayBlock - 1) / gvom::kRayBlock);
+    const int tiles_y = (m->p.ny + tile - 1) / tile;
+    const int tiles = ((m->p.nx + tile - 1) / tile) * tiles_y;
+    const int lw_by = (m->d.nby + 3) / 4;
+    const int lw = ((m->p.nx + 3) / 4) * lw_by;
+    st.pre_rays[i + 1] = st.pre_rays[i] + (n[i] > 0 ? ray_blocks : 0);
+    st.pre_trace[i + 1] = st.pre_trace[i] + t->ins[i].trace_blocks;
+    st.pre_col[i + 1] = st.pre_col[i] + (int)((C + 255) / 256);
+    st.pre_surf[i + 1] = st.pre_surf[i] + tiles;
+    st.pre_lcount[i + 1] = st.pre_lcount[i] + (lut ? (int)((C + 255) / 256) : 0);
+    st.pre_lscan[i + 1] = st.pre_lscan[i] + (lut ? 1 : 0);
+    st.pre_lwrite[i + 1] = st.pre_lwrite[i] + (lut ? lw : 0);
+    st.surf_tiles_y[i] = tiles_y;
+    st.surf_H[i] = m->c.search_d > m->c.half_fit ? m->c.search_d : m->c.half_fit;
+    st.lw_by[i] = lw_by;
+    st.lut_groups[i] = (int)((C + 63) / 64);
+    st.nz_magic[i] = gvom::nz_magic(m->p.nz);
+    st.last_is_lut[i] = lut ? 1 : 0;
+    st.last_blocks[i] = lut ? lw : tiles;
+    (void)full;  // a whole-window clear is the plan's single full box
+  }
+  return MAP_OK;
+}
+
+int32_t batch_run(map_batch_t* b) {
+  hipError_t e = hipSuccess;
+  if (b->use_graph) {
+    if (!b->captured) {
+      e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        const hipError_t e1 = enqueue_batch(b);
+        e = hipStreamEndCapture(b->stream, &b->graph);
+        if (e == hipSuccess) e = e1;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        batch_fail(b, e);
+        return MAP_E_DEVICE;
+      }
+      b->captured = true;
+    }
+    e = hipGraphLaunch(b->exec, b->stream);
+  } else {
+    e = enqueue_batch(b);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    batch_fail(b, e);
+    return MAP_E_DEVICE;
+  }
+  for (int i = 0; i < b->k; i++)
+    b->last_ms[i] = (double)(b->hstamps[1 + i] - b->hstamps[0]) / b->clock_khz;
+  return MAP_OK;
+}
+
+int32_t batch_check(map_batch_t* b, const float* const* xyz_dev, const int64_t* n,
+                    const float* poses, const uint32_t* flags, const map_2d_t* out2d,
+                    int32_t* const* lut_dev, const int64_t* cap, int64_t* const* n_occupied_dev,
+                    int32_t (*S)[3]) {
+  if (!b || !xyz_dev || !n || !poses || !flags || !out2d) return MAP_E_INVALID;
+  for (int i = 0; i < b->k; i++) {
+    if (flags[i] & MAP_STATS_DISTINCT) return MAP_E_INVALID;
+    if (!valid_2d(&out2d[i])) return MAP_E_INVALID;
+    if (lut_dev && lut_dev[i] && (!n_occupied_dev || !n_occupied_dev[i] || (cap && cap[i] < 0)))
+      return MAP_E_INVALID;
+    const int32_t s = check_insert(b->maps[i], xyz_dev[i], n[i], poses + 12 * i, flags[i], S[i]);
+    if (s) return s;
+  }
+  for (int i = 0; i < b->k; i++)
+    if (hipStreamSynchronize(b->maps[i]->stream) != hipSuccess) {
+      batch_fail(b);
+      return MAP_E_DEVICE;
+    }
+  return MAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t map_batch_create(map_t* const* maps, int32_t k, void* stream, map_batch_t** out) {
+  if (!out) return MAP_E_INVALID;
+  *out = nullptr;
+  if (!maps || k < 1 || k > gvom::kMaxBatch) return MAP_E_INVALID;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MAP_E_DEVICE;
+  for (int i = 0; i < k; i++) {
+    if (!maps[i] || maps[i]->device != dev || maps[i]->sticky) return MAP_E_INVALID;
+    for (int j = 0; j < i; j++)
+      if (maps[j] == maps[i]) return MAP_E_INVALID;
+  }
+  map_batch_t* b = new (std::nothrow) map_batch_t();
+  if (!b) return MAP_E_OOM;
+  b->k = k;
+  for (int i = 0; i < k; i++) b->maps[i] = maps[i];
+  b->stream = (hipStream_t)stream;
+  if (!b->stream) {  // graphs cannot be captured on the null stream: use an own stream
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return MAP_E_DEVICE;
+    }
+    b->own_stream = true;
+  }
+  b->device = dev;
+  b->n_cu = maps[0]->n_cu;
+  b->use_graph = true;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    khz = 100000;
+  b->clock_khz = khz;
+  size_t surf = 0, lut = 0;
+  for (int i = 0; i < k; i++) {
+    const map_t* m = maps[i];
+    const int H = m->c.search_d > m->c.half_fit ? m->c.search_d : m->c.half_fit;
+    const size_t s1 = gvom::surface_lds(H), s2 = gvom::lut_lds(m->p.nz);
+    surf = s1 > surf ? s1 : surf;
+    lut = s2 > lut ? s2 : lut;
+  }
+  const int cu = b->n_cu;
+  b->grid = gvom::BatchGrid{cu * 4, cu * 2, cu * 8, cu * 4, cu * 2, cu * 4, cu * 4, surf, lut};
+  hipError_t e = hipMalloc((void**)&b->dtab, sizeof(gvom::BatchTables));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->htab, sizeof(gvom::BatchTables), 0);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->dstamps, (gvom::kMaxBatch + 1) * 8);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->hstamps, (gvom::kMaxBatch + 1) * 8, 0);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->ddone, gvom::kMaxBatch * 4);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    map_batch_destroy(b);
+    return MAP_E_OOM;
+  }
+  memset(b->htab, 0, sizeof(gvom::BatchTables));
+  *out = b;
+  return MAP_OK;
+}
+
+int32_t map_batch_destroy(map_batch_t* b) {
+  if (!b) return MAP_OK;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->captured) {
+    (void)hipGraphExecDestroy(b->exec);
+    (void)hipGraphDestroy(b->graph);
+  }
+  (void)hipFree(b->dtab);
+  (void)hipHostFree(b->htab);
+  (void)hipFree(b->dstamps);
+  (void)hipHostFree(b->hstamps);
+  (void)hipFree(b->ddone);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return MAP_OK;
+}
+
+int32_t map_batch_set_graph(map_batch_t* b, int32_t enable) {
+  if (!b) return MAP_E_INVALID;
+  b->use_graph = enable != 0;
+  return MAP_OK;
+}
+
+int32_t map_batch_step(map_batch_t* b, const float* const* xyz_dev, const int64_t* n,
+                       const float* poses, const uint32_t* flags, const map_2d_t* out2d,
+                       int32_t* const* lut_dev, map_voxel_t* const* data_dev,
+                       const int64_t* cap, int64_t* const* n_occupied_dev) {
+  int32_t S[gvom::kMaxBatch][3];
+  int32_t s = batch_check(b, xyz_dev, n, poses, flags, out2d, lut_dev, cap, n_occupied_dev, S);
+  if (s) return s;
+  s = batch_prepare(b, xyz_dev, n, poses, flags, out2d, lut_dev, data_dev, cap, n_occupied_dev, S);
+  if (s) return s;
+  return batch_run(b);
+}
+
+int32_t map_batch_latency(const map_batch_t* b, double* ms) {
+  if (!b || !ms) return MAP_E_INVALID;
+  for (int i = 0; i < b->k; i++) ms[i] = b->last_ms[i];
+  return MAP_OK;
+}
+
+int32_t map_batch_autotune(map_batch_t* b, const float* const* xyz_dev, const int64_t* n,
+                           const float* poses, const uint32_t* flags, const map_2d_t* out2d,
+                           const char* cache_path, map_tuning_t* chosen) {
+  if (!b) return MAP_E_INVALID;
+  int32_t S[gvom::kMaxBatch][3];
+  int32_t s = batch_check(b, xyz_dev, n, poses, flags, out2d, nullptr, nullptr, nullptr, S);
+  if (s) return s;
+  // cache key: device, compute units, map shapes, point-count range
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) return MAP_E_DEVICE;
+  int64_t ntot = 0;
+  for (int i = 0; i < b->k; i++) ntot += n[i];
+  int bucket = 0;
+  for (int64_t v = ntot / b->k; v > 1; v >>= 1) bucket++;
+  std::string key = std::string(prop.gcnArchName) + "/cu" + std::to_string(b->n_cu) + "/n2^" +
+                    std::to_string(bucket);
+  for (int i = 0; i < b->k; i++) {
+    const map_t* m = b->maps[i];
+    key += "/" + std::to_string(m->p.nx) + "x" + std::to_string(m->p.ny) + "x" +
+           std::to_string(m->p.nz);
+  }
+  for (char& c : key)
+    if (c == ' ') c = '_';
+  map_tuning_t best{0, 0};
+  bool cached = false;
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "r")) {
+      char line[8192];
+      while (fgets(line, sizeof(line), f)) {
+        char k2[8000];
+        int a = 0, w = 0;
+        if (sscanf(line, "%7999s %d %d", k2, &a, &w) == 3 && key == k2) {
+          best.seg_len = a;
+          best.trace_waves_per_cu = w;
+          cached = true;
+        }
+      }
+      fclose(f);
+    }
+  }
+  if (!cached) {
+    const int segs[3] = {16, 32, 64}, wpcs[3] = {8, 16, 32};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MAP_E_DEVICE;
+    float best_ms = 1e30f;
+    for (int si = 0; si < 3; si++)
+      for (int wi = 0; wi < 3; wi++) {
+        const map_tuning_t t{segs[si], wpcs[wi]};
+        for (int i = 0; i < b->k; i++) map_set_tuning(b->maps[i], &t);
+        float tot = 0.0f;
+        for (int rep = 0; rep < 3; rep++) {
+          for (int i = 0; i < b->k; i++) map_reset(b->maps[i]);
+          s = batch_check(b, xyz_dev, n, poses, flags, out2d, nullptr, nullptr, nullptr, S);
+          if (!s) s = batch_prepare(b, xyz_dev, n, poses, flags, out2d, nullptr, nullptr, nullptr,
+                                    nullptr, S);
+          if (s) return s;
+          (void)hipEventRecord(e0, b->stream);
+          s = batch_run(b);
+          (void)hipEventRecord(e1, b->stream);
+          (void)hipEventSynchronize(e1);
+          if (s) return s;
+          float ms = 0.0f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0) tot += ms;  // the first run of a setting warms it up
+        }
+        if (tot < best_ms) {
+          best_ms = tot;
+          best = t;
+        }
+      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (cache_path) {
+      if (FILE* f = fopen(cache_path, "a")) {
+        fprintf(f, "%s %d %d\n", key.c_str(), best.seg_len, best.trace_waves_per_cu);
+        fclose(f);
+      }
+    }
+  }
+  for (int i = 0; i < b->k; i++) {
+    map_set_tuning(b->maps[i], &best);
+    map_reset(b->maps[i]);
+  }
+  if (chosen) *chosen = best;
   return MAP_OK;
 }
 

@@ -55,9 +55,9 @@ __device__ __forceinline__ int rank_below(const Mask128& m, int z) {
 // the occupied voxels n_lo..n_hi above the ground voxel; its density is
 // sum(hits) / sum(hits + passes); hard iff that ratio exceeds num/den
 // (compared exactly in integers), soft otherwise.
-__global__ __launch_bounds__(kBlock) void k_column(ColumnArgs a) {
+__device__ __forceinline__ void column_body(const ColumnArgs& a, const int blk) {
   const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
-  const int c = blockIdx.x * kBlock + threadIdx.x;
+  const int c = blk * kBlock + threadIdx.x;
   if (c >= nx * ny) return;
   const int x = c / ny, y = c - x * ny;
   const int sx = wrap_add(x + a.d.ro[0], nx), sy = wrap_add(y + a.d.ro[1], ny);
@@ -95,6 +95,8 @@ __global__ __launch_bounds__(kBlock) void k_column(ColumnArgs a) {
   a.flags[c] = f;
   a.hq[c] = hq;
 }
+
+__global__ __launch_bounds__(kBlock) void k_column(ColumnArgs a) { column_body(a, blockIdx.x); }
 
 // 2D surface maps on tiles of kTile x kTile pixels (one pixel per thread)
 // with a halo of H = max(half_fit, D) pixels staged in LDS.  Defined pixels
@@ -145,7 +147,8 @@ __device__ __forceinline__ int line_distance(const unsigned long long* L, int MW
   return best;
 }
 
-__global__ __launch_bounds__(kSurfThreads) void k_surface(SurfaceArgs a, int H) {
+__device__ __forceinline__ void surface_body(const SurfaceArgs& a, const int H, const int bx,
+                                             const int by) {
   extern __shared__ int32_t lds[];
   const int T = kTile + 2 * H;          // staged tile edge
   const int MW = (T + 63) >> 6;         // mask words per staged row / column
@@ -154,7 +157,7 @@ __global__ __launch_bounds__(kSurfThreads) void k_surface(SurfaceArgs a, int H) 
   unsigned long long* cmask = rmask + T * MW;                            // [T][MW]
   uint8_t* rdist = (uint8_t*)(cmask + T * MW);  // [T][kTile]: row r, tile column j
   uint8_t* cdist = rdist + T * kTile;           // [T][kTile]: column c, tile row i
-  const int gx0 = blockIdx.x * kTile - H, gy0 = blockIdx.y * kTile - H;
+  const int gx0 = bx * kTile - H, gy0 = by * kTile - H;
   for (int i = threadIdx.x; i < T * T; i += kSurfThreads) {
     const int tx = i / T, ty = i - tx * T;
     const int gx = gx0 + tx, gy = gy0 + ty;
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(kSurfThreads) void k_surface(SurfaceArgs a, int H) 
   __syncthreads();
   {
     const int px = threadIdx.x / kTile, py = threadIdx.x - px * kTile;
-    const int gx = blockIdx.x * kTile + px, gy = blockIdx.y * kTile + py;
+    const int gx = bx * kTile + px, gy = by * kTile + py;
     if (gx < a.nx && gy < a.ny) {
       if (th[(px + H) * T + py + H] != INT32_MIN)
         order[atomicAdd(&n_def, 1)] = (int16_t)threadIdx.x;
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(kSurfThreads) void k_surface(SurfaceArgs a, int H) 
   else if ((int)threadIdx.x >= kSurfThreads - nu) me = order[threadIdx.x];
   else return;
   const int px = me / kTile, py = me - px * kTile;
-  const int gx = blockIdx.x * kTile + px, gy = blockIdx.y * kTile + py;
+  const int gx = bx * kTile + px, gy = by * kTile + py;
   const int h = a.half_fit, D = a.search_d;
   const int tx = px + H, ty = py + H;
   const int32_t hc = th[tx * T + ty];
@@ -299,16 +302,20 @@ __global__ __launch_bounds__(kSurfThreads) void k_surface(SurfaceArgs a, int H) 
   a.flags[c] = fl;
 }
 
+__global__ __launch_bounds__(kSurfThreads) void k_surface(SurfaceArgs a, int H) {
+  surface_body(a, H, blockIdx.x, blockIdx.y);
+}
+
 // Lookup-table export.  Ranks follow window-local column order: pass 1 gives
 // every local column its occupied-voxel count prefix within its group of 64
 // columns and each group its total, pass 2 scans the group totals, pass 3
 // writes the table and the data array region by region.
 constexpr int kGroup = 64;
 
-__global__ __launch_bounds__(kBlock) void k_lut_count(LutArgs a) {
+__device__ __forceinline__ void lut_count_body(const LutArgs& a, const int blk) {
   const int nx = a.d.nx, ny = a.d.ny;
   const int lane = __lane_id();
-  const int c = blockIdx.x * kBlock + threadIdx.x;
+  const int c = blk * kBlock + threadIdx.x;
   int cnt = 0;
   if (c < nx * ny) {
     const int x = c / ny, y = c - x * ny;
@@ -327,8 +334,10 @@ __global__ __launch_bounds__(kBlock) void k_lut_count(LutArgs a) {
   if (lane == 63 && g * kGroup < nx * ny) a.block_base[g] = incl;
 }
 
+__global__ __launch_bounds__(kBlock) void k_lut_count(LutArgs a) { lut_count_body(a, blockIdx.x); }
+
 // Pass 2 (one block): exclusive scan of the group counts; writes M.
-__global__ __launch_bounds__(1024) void k_lut_scan(int32_t* base, int nb, int64_t* n_occupied) {
+__device__ __forceinline__ void lut_scan_body(int32_t* base, const int nb, int64_t* n_occupied) {
   __shared__ int64_t wsum[16];
   const int t = threadIdx.x;
   const int per = (nb + 1023) / 1024;
@@ -362,20 +371,24 @@ __global__ __launch_bounds__(1024) void k_lut_scan(int32_t* base, int nb, int64_
   }
 }
 
+__global__ __launch_bounds__(1024) void k_lut_scan(int32_t* base, int nb, int64_t* n_occupied) {
+  lut_scan_body(base, nb, n_occupied);
+}
+
 // Pass 3: block = a storage region of 4 x 16 columns (four 4 x 4 bricks,
 // contiguous in memory).  The passes of the region are read in storage order
 // into LDS, then every column's table entries are written in window-local z
 // order (a transpose through LDS keeps both sides coalesced).
 constexpr int kRegCols = 64;
 
-__global__ __launch_bounds__(kBlock) void k_lut_write(LutArgs a, uint32_t nz_magic) {
+__device__ __forceinline__ void lut_write_body(const LutArgs& a, const uint32_t nz_magic,
+                                               const int bxr, const int byr) {
   extern __shared__ int32_t lpass[];  // [64][nz + 1]
   __shared__ unsigned long long slo[kRegCols], shi[kRegCols];
   __shared__ int32_t sbase[kRegCols];
   __shared__ int64_t scb[kRegCols], slut[kRegCols];
   const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, W = a.d.W, roz = a.d.ro[2];
   const int nzp = nz + 1;
-  const int bxr = blockIdx.x, byr = blockIdx.y;  // brick row, group of 4 bricks
   if (threadIdx.x < kRegCols) {
     const int t = threadIdx.x;
     const int ix = t >> 4, jy = t & 15;
@@ -439,6 +452,10 @@ __global__ __launch_bounds__(kBlock) void k_lut_write(LutArgs a, uint32_t nz_mag
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_lut_write(LutArgs a, uint32_t nz_magic) {
+  lut_write_body(a, nz_magic, blockIdx.x, blockIdx.y);  // brick row, group of 4 bricks
+}
+
 // Import: one wave per window-local column; lane = local z.
 __global__ __launch_bounds__(kBlock) void k_import(Dims d, const int32_t* lut,
                                                    const map_voxel_t* data, int64_t n_data,
@@ -496,12 +513,122 @@ __global__ __launch_bounds__(kBlock) void k_import(Dims d, const int32_t* lut,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched stages (see insert.hip): persistent grids over the virtual blocks of
+// all maps.  The map's last stage stamps its completion time.
+__device__ __forceinline__ int find_map_e(const int32_t* pre, int n, int vb) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= vb) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void stamp_done(const BatchStep& st, int m, unsigned long long* stamps,
+                                           unsigned int* done) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&done[m], 1u) + 1u == (unsigned)st.last_blocks[m]) stamps[1 + m] = wall_clock64();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_column(const BatchTables* __restrict__ t) {
+  const int n = t->st.nmaps;
+  const int total = t->st.pre_col[n];
+  for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    const int m = find_map_e(t->st.pre_col, n, vb);
+    column_body(t->col[m], vb - t->st.pre_col[m]);
+  }
+}
+
+__global__ __launch_bounds__(kSurfThreads) void k_b_surface(const BatchTables* __restrict__ t,
+                                                            unsigned long long* stamps,
+                                                            unsigned int* done) {
+  const int n = t->st.nmaps;
+  const int total = t->st.pre_surf[n];
+  for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    const int m = find_map_e(t->st.pre_surf, n, vb);
+    const int tile = vb - t->st.pre_surf[m];
+    const int ty = t->st.surf_tiles_y[m];
+    surface_body(t->sur[m], t->st.surf_H[m], tile / ty, tile % ty);
+    if (!t->st.last_is_lut[m]) stamp_done(t->st, m, stamps, done);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_lut_count(const BatchTables* __restrict__ t) {
+  const int n = t->st.nmaps;
+  const int total = t->st.pre_lcount[n];
+  for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    const int m = find_map_e(t->st.pre_lcount, n, vb);
+    lut_count_body(t->lut[m], vb - t->st.pre_lcount[m]);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_b_lut_scan(const BatchTables* __restrict__ t) {
+  const int n = t->st.nmaps;
+  const int total = t->st.pre_lscan[n];
+  for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    const int m = find_map_e(t->st.pre_lscan, n, vb);
+    lut_scan_body(t->lut[m].block_base, t->st.lut_groups[m], t->lut[m].n_occupied);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_lut_write(const BatchTables* __restrict__ t,
+                                                        unsigned long long* stamps,
+                                                        unsigned int* done) {
+  const int n = t->st.nmaps;
+  const int total = t->st.pre_lwrite[n];
+  for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    const int m = find_map_e(t->st.pre_lwrite, n, vb);
+    const int b = vb - t->st.pre_lwrite[m];
+    const int by = t->st.lw_by[m];
+    lut_write_body(t->lut[m], t->st.nz_magic[m], b / by, b % by);
+    stamp_done(t->st, m, stamps, done);
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+hipError_t launch_batch_export(const BatchTables* tab, const BatchGrid& g,
+                               unsigned long long* stamps, unsigned int* done, hipStream_t s) {
+  if (g.surf_lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_b_surface,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)g.surf_lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_b_column, dim3(g.col), dim3(kBlock), 0, s, tab);
+  hipLaunchKernelGGL(k_b_surface, dim3(g.surf), dim3(kSurfThreads), g.surf_lds, s, tab, stamps,
+                     done);
+  hipLaunchKernelGGL(k_b_lut_count, dim3(g.lcount), dim3(kBlock), 0, s, tab);
+  hipLaunchKernelGGL(k_b_lut_scan, dim3(g.lcount), dim3(1024), 0, s, tab);
+  hipLaunchKernelGGL(k_b_lut_write, dim3(g.lwrite), dim3(kBlock), g.lut_lds, s, tab, stamps, done);
+  return hipGetLastError();
+}
 
 hipError_t launch_column(const ColumnArgs& a, hipStream_t s) {
   const int C = a.d.nx * a.d.ny;
   hipLaunchKernelGGL(k_column, dim3((C + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
   return hipGetLastError();
+}
+
+int surface_tile() { return kTile; }
+
+size_t surface_lds(int H) {
+  const int T = kTile + 2 * H;
+  const int MW = (T + 63) / 64;
+  return (size_t)((T * T + 1) & ~1) * 4 + 2 * (size_t)T * MW * 8 + 2 * (size_t)T * kTile;
+}
+
+size_t lut_lds(int nz) { return (size_t)kRegCols * (nz + 1) * 4; }
+
+uint32_t nz_magic(int nz) {
+  return nz > 1 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)nz - 1) / (uint64_t)nz) : 0u;
 }
 
 hipError_t launch_surface(const SurfaceArgs& a, hipStream_t s) {

@@ -107,13 +107,69 @@ struct LutArgs {
   int64_t* n_occupied;
 };
 
+struct ClearArgs {
+  Dims d;
+  int32_t* hits;
+  int32_t* passes;
+  int32_t* minqz;
+  unsigned long long* occ;
+  int32_t nbox;
+  int32_t box[3][6];              // x0, cx, y0, cy, z0, cz (storage coordinates)
+  unsigned long long keep[3][2];  // occupancy bits kept in the box's columns
+};
+
+// ---- batches of maps ------------------------------------------------------
+constexpr int kMaxBatch = 64;
+
+// Per-step table of a batch: virtual-block prefixes of every stage (block b of
+// stage S belongs to the map m with pre[m] <= b < pre[m+1]) and per-map
+// launch constants.  Lives in device memory, uploaded once per step.
+struct BatchStep {
+  int32_t nmaps;
+  int32_t pre_rays[kMaxBatch + 1];
+  int32_t pre_trace[kMaxBatch + 1];
+  int32_t pre_col[kMaxBatch + 1];
+  int32_t pre_surf[kMaxBatch + 1];
+  int32_t pre_lcount[kMaxBatch + 1];
+  int32_t pre_lscan[kMaxBatch + 1];
+  int32_t pre_lwrite[kMaxBatch + 1];
+  int32_t surf_tiles_y[kMaxBatch];
+  int32_t surf_H[kMaxBatch];
+  int32_t lw_by[kMaxBatch];
+  int32_t lut_groups[kMaxBatch];
+  uint32_t nz_magic[kMaxBatch];
+  int32_t last_blocks[kMaxBatch];  // blocks of the map's last stage (completion stamp)
+  int32_t last_is_lut[kMaxBatch];
+};
+
+struct BatchTables {
+  BatchStep st;
+  ClearArgs clr[kMaxBatch];
+  InsertArgs ins[kMaxBatch];
+  ColumnArgs col[kMaxBatch];
+  SurfaceArgs sur[kMaxBatch];
+  LutArgs lut[kMaxBatch];
+};
+
+struct BatchGrid {
+  int clear, rays, trace, col, surf, lcount, lwrite;  // persistent grid sizes
+  size_t surf_lds, lut_lds;
+};
+
+// Enqueues one batched step (all stages of all maps) reading `tab` (device).
+// stamps[0] = step start, stamps[1 + m] = completion of map m (wall clock);
+// done[m] counts finished last-stage blocks of map m.
+hipError_t launch_batch_insert(const BatchTables* tab, const BatchGrid& g,
+                               unsigned long long* stamps, unsigned int* done, hipStream_t s);
+hipError_t launch_batch_export(const BatchTables* tab, const BatchGrid& g,
+                               unsigned long long* stamps, unsigned int* done, hipStream_t s);
+int surface_tile();
+size_t surface_lds(int H);
+size_t lut_lds(int nz);
+uint32_t nz_magic(int nz);
+
 // Launchers (all enqueue on `s`, return the launch status).
-hipError_t launch_clear_box(const Dims& d, int32_t* hits, int32_t* passes, int32_t* minqz,
-                            int32_t x0, int32_t cx, int32_t y0, int32_t cy, int32_t z0,
-                            int32_t cz, hipStream_t s);
-hipError_t launch_clear_occ(const Dims& d, unsigned long long* occ, int32_t x0, int32_t cx,
-                            int32_t y0, int32_t cy, unsigned long long keep0,
-                            unsigned long long keep1, hipStream_t s);
+hipError_t launch_clear(const ClearArgs& a, hipStream_t s);
 hipError_t launch_insert(const InsertArgs& a, bool distinct, hipStream_t s);
 hipError_t launch_column(const ColumnArgs& a, hipStream_t s);
 hipError_t launch_surface(const SurfaceArgs& a, hipStream_t s);

@@ -36,11 +36,11 @@ __device__ __forceinline__ int dominant_axis(const int32_t n[3]) {
 }
 
 template <bool DISTINCT>
-__global__ __launch_bounds__(kRayBlock) void k_rays(InsertArgs a) {
+__device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
   __shared__ unsigned int wcount[kRayBlock / 64][5];
   __shared__ unsigned long long wbase[kRayBlock / 64];
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
-  const int i = blockIdx.x * kRayBlock + threadIdx.x;
+  const int i = blk * kRayBlock + threadIdx.x;
   const bool in = i < a.n;
   int pidx = i;
   if (a.fw > 1 && in) {
@@ -146,10 +146,10 @@ __global__ __launch_bounds__(kRayBlock) void k_rays(InsertArgs a) {
       s5 += wcount[w][4];
     }
     // blocks are spread over kStripes counters, each with its own item region
-    const int st = blockIdx.x % kStripes;
+    const int st = blk % kStripes;
     const unsigned long long b = sum ? atomicAdd(&a.stats[8 + st], sum) : 0ull;
     for (int w = 0; w < kRayBlock / 64; w++) wbase[w] += b + a.stripe_off[st];
-    unsigned long long* pr = a.part_rays + 4 * (size_t)blockIdx.x;
+    unsigned long long* pr = a.part_rays + 4 * (size_t)blk;
     pr[0] = s0;
     pr[1] = s1;
     pr[2] = s2;
@@ -166,6 +166,11 @@ __global__ __launch_bounds__(kRayBlock) void k_rays(InsertArgs a) {
     }
     off += __popcll(m);
   }
+}
+
+template <bool DISTINCT>
+__global__ __launch_bounds__(kRayBlock) void k_rays(InsertArgs a) {
+  rays_body<DISTINCT>(a, blockIdx.x);
 }
 
 // floor(x / d) for d > 0 (|x| < 2^60): double estimate, exact integer fix-up.
@@ -201,7 +206,7 @@ __device__ __forceinline__ int64_t floor_div_pos(int64_t x, int64_t d, bool* exa
 // their left neighbour join its run and the run's first lane adds the run
 // length with one atomic.
 template <bool DISTINCT>
-__global__ __launch_bounds__(kBlock) void k_trace(InsertArgs a) {
+__device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, const int nblk) {
   const int lane = __lane_id();
   const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
   const int32_t dims[3] = {nx, ny, nz};
@@ -213,11 +218,11 @@ __global__ __launch_bounds__(kBlock) void k_trace(InsertArgs a) {
   for (int t = 0; t < kStripes; t++)
     pre[t + 1] = pre[t] + min((int64_t)a.stats[8 + t], a.stripe_cap[t]);
   const int64_t count = pre[kStripes];
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int64_t stride = (int64_t)nblk * kBlock;
   uint32_t* touch_p = DISTINCT ? a.touch + ((a.d.vs + 31) >> 5) : nullptr;
   int n_pass = 0, n_dpass = 0;
 
-  for (int64_t wbase = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); wbase < count;
+  for (int64_t wbase = (int64_t)blk * kBlock + (threadIdx.x & ~63); wbase < count;
        wbase += stride) {
     const int64_t it = wbase + lane;
     bool active = false;
@@ -371,45 +376,121 @@ __global__ __launch_bounds__(kBlock) void k_trace(InsertArgs a) {
       p += wsum[w][0];
       q += wsum[w][1];
     }
-    a.part_trace[2 * blockIdx.x] = p;
-    a.part_trace[2 * blockIdx.x + 1] = q;
+    a.part_trace[2 * blk] = p;
+    a.part_trace[2 * blk + 1] = q;
   }
 }
 
-// Resets the storage voxels whose coordinates lie in the box
-// [x0, x0+cx) x [y0, y0+cy) x [z0, z0+cz), each taken modulo the axis size.
-__global__ __launch_bounds__(kBlock) void k_clear_box(Dims d, int32_t* hits, int32_t* passes,
-                                                      int32_t* minqz, int32_t x0, int32_t cx,
-                                                      int32_t y0, int32_t cy, int32_t z0,
-                                                      int32_t cz) {
-  const uint32_t total = (uint32_t)cx * cy * cz;
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
-    const uint32_t kz = i % (uint32_t)cz;
-    const uint32_t t = i / (uint32_t)cz;
-    const uint32_t ky = t % (uint32_t)cy;
-    const uint32_t kx = t / (uint32_t)cy;
-    const uint32_t sx = (x0 + kx) % (uint32_t)d.nx;
-    const uint32_t sy = (y0 + ky) % (uint32_t)d.ny;
-    const uint32_t sz = (z0 + kz) % (uint32_t)d.nz;
-    const uint32_t e = (uint32_t)col_base(d, sx, sy) + (sz << 4);
-    hits[e] = 0;
-    passes[e] = 0;
-    minqz[e] = INT32_MAX;
+template <bool DISTINCT>
+__global__ __launch_bounds__(kBlock) void k_trace(InsertArgs a) {
+  trace_body<DISTINCT>(a, blockIdx.x, gridDim.x);
+}
+
+// Window scroll: box k resets the storage voxels of
+// [x0, x0+cx) x [y0, y0+cy) x [z0, z0+cz) (each coordinate modulo the axis
+// size).  Occupancy: a box spanning all z (an x or y slab) zeroes the words
+// of its columns; a z slab (spanning all columns) clears its bits in every
+// column, where one thread combines all boxes of the column so that no two
+// threads update one word.
+__device__ __forceinline__ void clear_body(const ClearArgs& a, const int64_t first,
+                                           const int64_t stride) {
+  const Dims& d = a.d;
+  bool zslab = false;
+  for (int k = 0; k < a.nbox; k++) {
+    const int32_t* bx = a.box[k];
+    const uint32_t cx = bx[1], cy = bx[3], cz = bx[5];
+    zslab = zslab || (int)cz < d.nz;
+    const uint32_t total = cx * cy * cz;
+    for (int64_t i = first; i < total; i += stride) {
+      const uint32_t kz = (uint32_t)i % cz;
+      const uint32_t t = (uint32_t)i / cz;
+      const uint32_t ky = t % cy;
+      const uint32_t kx = t / cy;
+      const uint32_t sx = (bx[0] + kx) % (uint32_t)d.nx;
+      const uint32_t sy = (bx[2] + ky) % (uint32_t)d.ny;
+      const uint32_t sz = (bx[4] + kz) % (uint32_t)d.nz;
+      const uint32_t e = (uint32_t)col_base(d, sx, sy) + (sz << 4);
+      a.hits[e] = 0;
+      a.passes[e] = 0;
+      a.minqz[e] = INT32_MAX;
+    }
+  }
+  if (!zslab) {
+    for (int k = 0; k < a.nbox; k++) {
+      const int32_t* bx = a.box[k];
+      const uint32_t cx = bx[1], cy = bx[3];
+      for (int64_t i = first; i < (int64_t)cx * cy; i += stride) {
+        const uint32_t sx = (bx[0] + (uint32_t)i / cy) % (uint32_t)d.nx;
+        const uint32_t sy = (bx[2] + (uint32_t)i % cy) % (uint32_t)d.ny;
+        const uint32_t col = sx * d.ny + sy;
+        a.occ[(size_t)col * d.W] = 0;
+        if (d.W > 1) a.occ[(size_t)col * d.W + 1] = 0;
+      }
+    }
+  } else {
+    for (int64_t i = first; i < (int64_t)d.nx * d.ny; i += stride) {
+      const uint32_t sx = (uint32_t)i / d.ny, sy = (uint32_t)i % d.ny;
+      unsigned long long k0 = ~0ull, k1 = ~0ull;
+      for (int k = 0; k < a.nbox; k++) {
+        const int32_t* bx = a.box[k];
+        const uint32_t rx = (sx + d.nx - bx[0]) % (uint32_t)d.nx;
+        const uint32_t ry = (sy + d.ny - bx[2]) % (uint32_t)d.ny;
+        if (rx < (uint32_t)bx[1] && ry < (uint32_t)bx[3]) {
+          k0 &= a.keep[k][0];
+          k1 &= a.keep[k][1];
+        }
+      }
+      a.occ[(size_t)i * d.W] &= k0;
+      if (d.W > 1) a.occ[(size_t)i * d.W + 1] &= k1;
+    }
   }
 }
 
-// occ &= keep for the columns of the box [x0, x0+cx) x [y0, y0+cy) (mod n).
-__global__ __launch_bounds__(kBlock) void k_clear_occ(Dims d, unsigned long long* occ,
-                                                      int32_t x0, int32_t cx, int32_t y0,
-                                                      int32_t cy, unsigned long long keep0,
-                                                      unsigned long long keep1) {
-  const uint32_t total = (uint32_t)cx * cy;
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
-    const uint32_t sx = (x0 + i / (uint32_t)cy) % (uint32_t)d.nx;
-    const uint32_t sy = (y0 + i % (uint32_t)cy) % (uint32_t)d.ny;
-    const uint32_t col = sx * d.ny + sy;
-    occ[(size_t)col * d.W] &= keep0;
-    if (d.W > 1) occ[(size_t)col * d.W + 1] &= keep1;
+__global__ __launch_bounds__(kBlock) void k_clear(ClearArgs a) {
+  clear_body(a, (int64_t)blockIdx.x * kBlock + threadIdx.x, (int64_t)gridDim.x * kBlock);
+}
+
+// ---------------------------------------------------------------------------
+// Batched stages: persistent grids walk the virtual blocks of all maps of a
+// batch; block b of a stage belongs to the map m with pre[m] <= b < pre[m+1].
+__device__ __forceinline__ int find_map(const int32_t* pre, int n, int vb) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= vb) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_clear(const BatchTables* __restrict__ t,
+                                                    unsigned long long* stamps,
+                                                    unsigned int* done) {
+  const int n = t->st.nmaps;
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  if (gid == 0) stamps[0] = wall_clock64();
+  constexpr int kWords = 8 + kStripes;
+  for (int64_t i = gid; i < (int64_t)n * kWords; i += stride) t->ins[i / kWords].stats[i % kWords] = 0;
+  for (int64_t i = gid; i < n; i += stride) done[i] = 0;
+  for (int m = 0; m < n; m++) clear_body(t->clr[m], gid, stride);
+}
+
+__global__ __launch_bounds__(kRayBlock) void k_b_rays(const BatchTables* __restrict__ t) {
+  const int n = t->st.nmaps;
+  const int total = t->st.pre_rays[n];
+  for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    const int m = find_map(t->st.pre_rays, n, vb);
+    rays_body<false>(t->ins[m], vb - t->st.pre_rays[m]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_trace(const BatchTables* __restrict__ t) {
+  const int n = t->st.nmaps;
+  const int total = t->st.pre_trace[n];
+  for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    const int m = find_map(t->st.pre_trace, n, vb);
+    trace_body<false>(t->ins[m], vb - t->st.pre_trace[m], t->ins[m].trace_blocks);
+    __syncthreads();
   }
 }
 
@@ -428,23 +509,22 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
-hipError_t launch_clear_box(const Dims& d, int32_t* hits, int32_t* passes, int32_t* minqz,
-                            int32_t x0, int32_t cx, int32_t y0, int32_t cy, int32_t z0,
-                            int32_t cz, hipStream_t s) {
-  const int64_t total = (int64_t)cx * cy * cz;
+hipError_t launch_clear(const ClearArgs& a, hipStream_t s) {
+  int64_t total = 0;
+  for (int k = 0; k < a.nbox; k++) {
+    const int64_t t = (int64_t)a.box[k][1] * a.box[k][3] * a.box[k][5];
+    total = t > total ? t : total;
+  }
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_clear_box, dim3(grid_for(total)), dim3(kBlock), 0, s, d, hits, passes,
-                     minqz, x0, cx, y0, cy, z0, cz);
+  hipLaunchKernelGGL(k_clear, dim3(grid_for(total)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_clear_occ(const Dims& d, unsigned long long* occ, int32_t x0, int32_t cx,
-                            int32_t y0, int32_t cy, unsigned long long keep0,
-                            unsigned long long keep1, hipStream_t s) {
-  const int64_t total = (int64_t)cx * cy;
-  if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_clear_occ, dim3(grid_for(total)), dim3(kBlock), 0, s, d, occ, x0, cx,
-                     y0, cy, keep0, keep1);
+hipError_t launch_batch_insert(const BatchTables* tab, const BatchGrid& g,
+                               unsigned long long* stamps, unsigned int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_clear, dim3(g.clear), dim3(kBlock), 0, s, tab, stamps, done);
+  hipLaunchKernelGGL(k_b_rays, dim3(g.rays), dim3(kRayBlock), 0, s, tab);
+  hipLaunchKernelGGL(k_b_trace, dim3(g.trace), dim3(kBlock), 0, s, tab);
   return hipGetLastError();
 }
 

@@ -61,6 +61,8 @@ EXPORTED = [
     "map_export_2d", "map_export_voxels", "map_import_voxels", "map_get_stats",
     "map_get_origin", "map_sync", "map_status_str", "map_profile_enable", "map_profile_read",
     "map_set_tuning", "map_get_tuning",
+    "map_batch_create", "map_batch_destroy", "map_batch_step", "map_batch_latency",
+    "map_batch_set_graph", "map_batch_autotune",
 ]
 PROF_PHASES = ("scroll", "insert", "column", "surface", "lut")
 
@@ -89,6 +91,13 @@ def lib() -> ctypes.CDLL:
         L.map_sync.argtypes = [P]
         L.map_set_tuning.argtypes = [P, ctypes.POINTER(map_tuning_t)]
         L.map_get_tuning.argtypes = [P, ctypes.POINTER(map_tuning_t)]
+        L.map_batch_create.argtypes = [P, I32, P, ctypes.POINTER(P)]
+        L.map_batch_destroy.argtypes = [P]
+        L.map_batch_step.argtypes = [P, P, P, P, P, P, P, P, P, P]
+        L.map_batch_latency.argtypes = [P, P]
+        L.map_batch_set_graph.argtypes = [P, I32]
+        L.map_batch_autotune.argtypes = [P, P, P, P, P, P, ctypes.c_char_p,
+                                         ctypes.POINTER(map_tuning_t)]
         L.map_profile_enable.argtypes = [P, I32]
         L.map_profile_read.argtypes = [P, P, P]
         L.map_status_str.argtypes = [I32]
@@ -222,6 +231,116 @@ def map_profile_read(h):
     s = lib().map_profile_read(h, ms.ctypes.data_as(ctypes.c_void_p),
                                cnt.ctypes.data_as(ctypes.c_void_p))
     return s, {p: (float(ms[i]), int(cnt[i])) for i, p in enumerate(PROF_PHASES)}
+
+
+def _ptr_array(ptrs):
+    arr = (ctypes.c_void_p * len(ptrs))(*[p if isinstance(p, int) else (p.value or 0)
+                                           for p in ptrs])
+    return arr
+
+
+class MapBatch:
+    """A batch of VoxelMaps stepped together (map_batch_* calls)."""
+
+    def __init__(self, maps, stream=None):
+        """stream: a torch.cuda.Stream, or None for a stream owned by the batch."""
+        self.maps = list(maps)
+        hs = (ctypes.c_void_p * len(self.maps))(*[m.h.value for m in self.maps])
+        h = ctypes.c_void_p()
+        sp = ctypes.c_void_p(0 if stream is None else stream.cuda_stream)
+        s = lib().map_batch_create(hs, len(self.maps), sp, ctypes.byref(h))
+        if s != MAP_OK:
+            raise RuntimeError(f"map_batch_create: {map_status_str(s)}")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().map_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _inputs(self, xyzs, poses, flags):
+        import torch
+        k = len(self.maps)
+        assert len(xyzs) == k and len(poses) == k and len(flags) == k
+        ptrs, ns = [], []
+        for x in xyzs:
+            if x is None or x.shape[0] == 0:
+                ptrs.append(0)
+                ns.append(0)
+            else:
+                ptrs.append(_dev(x, torch.float32, "xyz").value)
+                ns.append(int(x.shape[0]))
+        xa = _ptr_array(ptrs)
+        na = np.ascontiguousarray(ns, dtype=np.int64)
+        pa = np.ascontiguousarray(np.stack([np.asarray(p, np.float32).reshape(12) for p in poses]))
+        fa = np.ascontiguousarray(flags, dtype=np.uint32)
+        outs = (map_2d_t * k)()
+        for i, m in enumerate(self.maps):
+            o = m.out2d
+            outs[i] = map_2d_t(_dev(o["height"]), _dev(o["slope"]), _dev(o["rough"]),
+                               _dev(o["density"]), _dev(o["flags"]))
+        keep = (xa, na, pa, fa, outs)
+        return keep
+
+    def step(self, xyzs, poses, flags, voxels=None):
+        """voxels: None, or a list of k booleans (export the lookup table of map i)."""
+        k = len(self.maps)
+        xa, na, pa, fa, outs = self._inputs(xyzs, poses, flags)
+        P = ctypes.c_void_p
+        if voxels is None:
+            la = da = ca = oa = None
+        else:
+            lptr, dptr, cap, optr = [], [], [], []
+            for i, m in enumerate(self.maps):
+                if voxels[i]:
+                    V = m.lut.numel()
+                    if m.data is None or m.data.shape[0] != V:
+                        import torch
+                        m.data = torch.empty((V, 3), dtype=torch.int32, device=m.lut.device)
+                    lptr.append(m.lut.data_ptr())
+                    dptr.append(m.data.data_ptr())
+                    cap.append(V)
+                    optr.append(m.n_occ.data_ptr())
+                else:
+                    lptr.append(0)
+                    dptr.append(0)
+                    cap.append(0)
+                    optr.append(0)
+            la, da, oa = _ptr_array(lptr), _ptr_array(dptr), _ptr_array(optr)
+            ca = np.ascontiguousarray(cap, dtype=np.int64)
+        s = lib().map_batch_step(
+            self.h, xa, na.ctypes.data_as(P), pa.ctypes.data_as(P), fa.ctypes.data_as(P),
+            ctypes.cast(outs, P), la, da, None if ca is None else ca.ctypes.data_as(P), oa)
+        if s != MAP_OK:
+            raise RuntimeError(f"map_batch_step: {map_status_str(s)}")
+
+    def latency_ms(self):
+        ms = np.zeros(len(self.maps), np.float64)
+        s = lib().map_batch_latency(self.h, ms.ctypes.data_as(ctypes.c_void_p))
+        if s != MAP_OK:
+            raise RuntimeError(map_status_str(s))
+        return ms
+
+    def set_graph(self, enable: bool):
+        return lib().map_batch_set_graph(self.h, 1 if enable else 0)
+
+    def autotune(self, xyzs, poses, flags, cache_path=None):
+        xa, na, pa, fa, outs = self._inputs(xyzs, poses, flags)
+        P = ctypes.c_void_p
+        t = map_tuning_t()
+        s = lib().map_batch_autotune(self.h, xa, na.ctypes.data_as(P), pa.ctypes.data_as(P),
+                                     fa.ctypes.data_as(P), ctypes.cast(outs, P),
+                                     None if cache_path is None else cache_path.encode(),
+                                     ctypes.byref(t))
+        if s != MAP_OK:
+            raise RuntimeError(f"map_batch_autotune: {map_status_str(s)}")
+        return {"seg_len": t.seg_len, "trace_waves_per_cu": t.trace_waves_per_cu}
 
 
 class VoxelMap:
