@@ -16,6 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gvom_oracle.c")
+_SRC_SGT = os.path.join(_HERE, "sgt_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, E_INVALID, E_POSE, E_SENSOR_OUT, E_RANGE, E_CAPACITY, E_OOM = 0, -1, -2, -3, -4, -5, -6
@@ -25,7 +26,7 @@ RECENTER = 1
 def build() -> str:
     """Compile the oracle with gcc (-O2, no FP contraction, no SIMD flags)."""
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-Wextra", "-fPIC",
-           "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+           "-shared", "-o", _LIB + ".tmp", _SRC, _SRC_SGT, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -80,6 +81,14 @@ def lib():
         L.orc_surface.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_float, ctypes.c_int32, ctypes.c_int64,
                                   P, P, P, P]
+        L.orc_sgt_num_params.argtypes = []
+        L.orc_sgt_num_params.restype = ctypes.c_int64
+        L.orc_sgt_forward.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P]
+        L.orc_sgt_loss_grad.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int32,
+                                        P, P]
+        L.orc_sgt_fill.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P, P]
+        for f in ("orc_sgt_forward", "orc_sgt_loss_grad", "orc_sgt_fill"):
+            getattr(L, f).restype = ctypes.c_int32
         for f in ("orc_derive", "orc_create", "orc_reset", "orc_insert_scan", "orc_export_2d",
                   "orc_export_voxels", "orc_import_voxels", "orc_get_stats", "orc_get_origin",
                   "orc_transform_point", "orc_surface"):
