@@ -258,6 +258,60 @@ int32_t map_batch_autotune(map_batch_t* b, const float* const* xyz_dev, const in
                            const float* poses, const uint32_t* flags, const map_2d_t* out2d,
                            const char* cache_path, map_tuning_t* chosen);
 
+/* ---- learned gap-fill surrogate (project extension, not in the paper) -----
+ * A 5-layer 3x3 convolution network (16 -> 32 -> 32 -> 32 -> 32 -> 2
+ * channels, ReLU, zero padding; bf16 weights and layer inputs, fp32
+ * accumulation, biases fp32) maps 16 per-column features to ground height and
+ * roughness.  It never produces counts or flags: its output only fills
+ * columns the plain method leaves undefined, through sgt_fill.  Images are
+ * [H][W][C] device arrays with H = nx, W = ny of the map, channel fastest.
+ * Parameters (fp32 master copy): per layer W[co][ci][ky][kx] then b[co]. */
+typedef struct sgt_net_t sgt_net_t;
+
+int64_t sgt_num_params(void);  /* 32962 */
+/* Network for H x W images; He-normal weights from `seed`, zero biases,
+ * identity normalisation.  Synchronises. */
+int32_t sgt_create(int32_t H, int32_t W, uint64_t seed, void* stream, sgt_net_t** out);
+int32_t sgt_destroy(sgt_net_t* n);
+int32_t sgt_get_params(sgt_net_t* n, float* params_host);        /* synchronises */
+int32_t sgt_set_params(sgt_net_t* n, const float* params_host);  /* synchronises */
+/* Feature normalisation (x - mean) / std, computed in double and rounded to
+ * float then bf16; mean[16], std[16] host, std > 0. */
+int32_t sgt_set_norm(sgt_net_t* n, const float* mean, const float* std_dev);
+
+/* Per-column features of map m (window-local [nx][ny][16], device): 0 sum of
+ * hits, 1 sum of passes, 2 occupied voxels, 3 occupied fraction, 4 ground
+ * height, 5 lowest return of the highest occupied voxel, 6 mean of the
+ * occupied voxels' lowest returns, 7 height defined, 8 hits / (hits + passes)
+ * of the ground voxel, 9 band density, 10 slope, 11 roughness, 12 slope
+ * defined, 13 horizontal distance from the column centre to sensor_xyz, 14
+ * sensor height above the ground, 15 column thinned (thin_dev[c] != 0; may be
+ * NULL).  Undefined values are 0; a thinned column keeps only 13 and 15.
+ * plain_dev: the map's map_export_2d output.  Heights in metres. */
+int32_t sgt_features(map_t* m, const map_2d_t* plain_dev, const float sensor_xyz[3],
+                     const uint8_t* thin_dev, float* feat_dev);
+/* Removes the data of the window-local columns marked in thin_dev[nx*ny]. */
+int32_t sgt_thin(map_t* m, const uint8_t* thin_dev);
+/* sums[0..15] = per-feature sums, sums[16..31] = sums of squares (host). */
+int32_t sgt_feature_sums(sgt_net_t* n, const float* feat_dev, double* sums_host);
+
+/* out_dev[H][W][2] = network(features). */
+int32_t sgt_forward(sgt_net_t* n, const float* feat_dev, float* out_dev);
+/* Masked L1 loss against label_dev[H][W][2] (NaN = no label) and the gradient
+ * of every parameter (kept for sgt_adam; also copied to grad_host if not
+ * NULL).  The bf16 roundings are treated as the identity in the gradient.
+ * Synchronises. */
+int32_t sgt_loss_grad(sgt_net_t* n, const float* feat_dev, const float* label_dev,
+                      float* loss_host, float* grad_host);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) with the last gradient. */
+int32_t sgt_adam(sgt_net_t* n, float lr);
+/* Filled maps: the plain height / roughness where the plain height is
+ * defined; elsewhere the network's (roughness clamped at 0) when the mean of
+ * |network height - plain height| over the plain-defined columns of the
+ * 11 x 11 window is <= tol_m; otherwise NaN. */
+int32_t sgt_fill(const float* pred_dev, const map_2d_t* plain_dev, int32_t H, int32_t W,
+                 float tol_m, float* height_out, float* rough_out, void* stream);
+
 /* Static text for a status code. */
 const char* map_status_str(int32_t status);
 

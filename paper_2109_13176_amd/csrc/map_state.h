@@ -1,0 +1,45 @@
+// Host-side state of one map (shared by the host sources of libgvom).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "gvom_internal.h"
+
+struct map_t {
+  map_params_t p;
+  map_derived_t c;
+  hipStream_t stream;
+  int device;
+  int32_t origin[3];
+  gvom::Dims d;
+  int32_t* hits;
+  int32_t* passes;
+  int32_t* minqz;
+  unsigned long long* occ;
+  int32_t* hq;
+  int32_t* block_base;
+  int32_t* colpre;
+  unsigned long long* stats;  // 8 counters
+  int32_t* err;
+  uint32_t* touch;            // distinct-voxel bitmaps, allocated on first use
+  int4* items;                // ray segments of the current insert
+  int64_t item_cap;
+  unsigned long long* part_rays;   // per-block counters of the ray pass
+  unsigned long long* part_trace;  // per-block counters of the traversal pass
+  int64_t part_rays_cap, part_trace_cap;
+  int64_t last_ray_blocks, last_trace_blocks;
+  int32_t seg_len;
+  int32_t trace_wpc;
+  int32_t n_cu;
+  int32_t sticky;
+  int64_t last_points, last_cleared;
+  bool last_distinct;
+  bool prof;
+  struct Mark {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+};
+

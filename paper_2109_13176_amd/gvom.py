@@ -63,6 +63,9 @@ EXPORTED = [
     "map_set_tuning", "map_get_tuning",
     "map_batch_create", "map_batch_destroy", "map_batch_step", "map_batch_latency",
     "map_batch_set_graph", "map_batch_autotune",
+    "sgt_num_params", "sgt_create", "sgt_destroy", "sgt_get_params", "sgt_set_params",
+    "sgt_set_norm", "sgt_features", "sgt_thin", "sgt_feature_sums", "sgt_forward",
+    "sgt_loss_grad", "sgt_adam", "sgt_fill",
 ]
 PROF_PHASES = ("scroll", "insert", "column", "surface", "lut")
 
@@ -98,6 +101,19 @@ def lib() -> ctypes.CDLL:
         L.map_batch_set_graph.argtypes = [P, I32]
         L.map_batch_autotune.argtypes = [P, P, P, P, P, P, ctypes.c_char_p,
                                          ctypes.POINTER(map_tuning_t)]
+        L.sgt_num_params.argtypes = []
+        L.sgt_create.argtypes = [I32, I32, ctypes.c_uint64, P, ctypes.POINTER(P)]
+        L.sgt_destroy.argtypes = [P]
+        L.sgt_get_params.argtypes = [P, P]
+        L.sgt_set_params.argtypes = [P, P]
+        L.sgt_set_norm.argtypes = [P, P, P]
+        L.sgt_features.argtypes = [P, ctypes.POINTER(map_2d_t), P, P, P]
+        L.sgt_thin.argtypes = [P, P]
+        L.sgt_feature_sums.argtypes = [P, P, P]
+        L.sgt_forward.argtypes = [P, P, P]
+        L.sgt_loss_grad.argtypes = [P, P, P, P, P]
+        L.sgt_adam.argtypes = [P, ctypes.c_float]
+        L.sgt_fill.argtypes = [P, ctypes.POINTER(map_2d_t), I32, I32, ctypes.c_float, P, P, P]
         L.map_profile_enable.argtypes = [P, I32]
         L.map_profile_read.argtypes = [P, P, P]
         L.map_status_str.argtypes = [I32]
@@ -105,6 +121,7 @@ def lib() -> ctypes.CDLL:
         for f in EXPORTED:
             if f != "map_status_str":
                 getattr(L, f).restype = I32
+        L.sgt_num_params.restype = I64
         _lib = L
     return _lib
 
@@ -404,3 +421,121 @@ class VoxelMap:
 
     def sync(self):
         self._check(map_sync(self.h), "map_sync")
+
+
+def _out2d(out):
+    import torch
+    return map_2d_t(_dev(out["height"], torch.float32), _dev(out["slope"], torch.float32),
+                    _dev(out["rough"], torch.float32), _dev(out["density"], torch.float32),
+                    _dev(out["flags"], torch.uint8))
+
+
+class Surrogate:
+    """The gap-fill network (sgt_* calls) for H x W maps."""
+
+    N_FEAT = 16
+
+    def __init__(self, H: int, W: int, seed: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.H, self.W = H, W
+        h = ctypes.c_void_p()
+        s = lib().sgt_create(H, W, seed, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if s != MAP_OK:
+            raise RuntimeError(f"sgt_create: {map_status_str(s)}")
+        self.h = h
+        self.n_params = int(lib().sgt_num_params())
+
+    def close(self):
+        if self.h:
+            lib().sgt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ok(self, s, what):
+        if s != MAP_OK:
+            raise RuntimeError(f"{what}: {map_status_str(s)}")
+
+    def get_params(self):
+        p = np.zeros(self.n_params, np.float32)
+        self._ok(lib().sgt_get_params(self.h, p.ctypes.data_as(ctypes.c_void_p)), "sgt_get_params")
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.n_params
+        self._ok(lib().sgt_set_params(self.h, p.ctypes.data_as(ctypes.c_void_p)), "sgt_set_params")
+
+    def set_norm(self, mean, std):
+        mean = np.ascontiguousarray(mean, dtype=np.float32)
+        std = np.ascontiguousarray(std, dtype=np.float32)
+        self._ok(lib().sgt_set_norm(self.h, mean.ctypes.data_as(ctypes.c_void_p),
+                                    std.ctypes.data_as(ctypes.c_void_p)), "sgt_set_norm")
+
+    def feature_sums(self, feat):
+        out = np.zeros(32, np.float64)
+        self._ok(lib().sgt_feature_sums(self.h, _dev(feat), out.ctypes.data_as(ctypes.c_void_p)),
+                 "sgt_feature_sums")
+        return out
+
+    def forward(self, feat, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.H, self.W, 2), dtype=torch.float32, device=feat.device)
+        self._ok(lib().sgt_forward(self.h, _dev(feat, torch.float32), _dev(out, torch.float32)),
+                 "sgt_forward")
+        return out
+
+    def loss_grad(self, feat, label, want_grad=False):
+        import torch
+        loss = ctypes.c_float()
+        g = np.zeros(self.n_params, np.float32) if want_grad else None
+        self._ok(lib().sgt_loss_grad(self.h, _dev(feat, torch.float32), _dev(label, torch.float32),
+                                     ctypes.byref(loss),
+                                     None if g is None else g.ctypes.data_as(ctypes.c_void_p)),
+                 "sgt_loss_grad")
+        return float(loss.value), g
+
+    def adam(self, lr: float):
+        self._ok(lib().sgt_adam(self.h, ctypes.c_float(lr)), "sgt_adam")
+
+
+def sgt_features(vmap, plain, sensor_xyz, thin=None, out=None):
+    import torch
+    nx, ny = vmap.params["nx"], vmap.params["ny"]
+    if out is None:
+        out = torch.empty((nx, ny, 16), dtype=torch.float32, device=plain["height"].device)
+    sxyz = np.ascontiguousarray(sensor_xyz, dtype=np.float32).reshape(3)
+    o = _out2d(plain)
+    s = lib().sgt_features(vmap.h, ctypes.byref(o), sxyz.ctypes.data_as(ctypes.c_void_p),
+                           ctypes.c_void_p(0) if thin is None else _dev(thin, torch.uint8),
+                           _dev(out, torch.float32))
+    if s != MAP_OK:
+        raise RuntimeError(f"sgt_features: {map_status_str(s)}")
+    return out
+
+
+def sgt_thin(vmap, thin) -> int:
+    import torch
+    return lib().sgt_thin(vmap.h, _dev(thin, torch.uint8))
+
+
+def sgt_fill(pred, plain, tol_m: float, stream=None):
+    import torch
+    H, W = pred.shape[0], pred.shape[1]
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    h = torch.empty((H, W), dtype=torch.float32, device=pred.device)
+    r = torch.empty((H, W), dtype=torch.float32, device=pred.device)
+    o = _out2d(plain)
+    s = lib().sgt_fill(_dev(pred, torch.float32), ctypes.byref(o), H, W, ctypes.c_float(tol_m),
+                       _dev(h), _dev(r), ctypes.c_void_p(stream.cuda_stream))
+    if s != MAP_OK:
+        raise RuntimeError(f"sgt_fill: {map_status_str(s)}")
+    return h, r

@@ -416,3 +416,50 @@ def small_random_cloud(seed: int, n: int, extent: float, device="cpu"):
     p = rng.uniform(-extent, extent, (n, 3)).astype(np.float32)
     p[rng.uniform(size=n) < 0.05] = np.nan
     return torch.as_tensor(p, device=device)
+
+
+def batch_of_vehicles(n_maps=32, n_steps=10, seed0=400, device="cpu", n_beams=64):
+    """Independent vehicles for batched serving: map i uses scene seed seed0 + i,
+    its scan size N_i is drawn log-uniformly in [20k, 330k] points per step
+    (n_beams x round(N_i / n_beams) azimuths), its grid uniformly from
+    {256 x 256 x 48 at 0.4 m, 512 x 512 x 64 at 0.2 m}; 4.5 m/s, one scan per
+    0.1 s, 100 m range, sigma 0.02 m."""
+    out = []
+    for i in range(n_maps):
+        s_traj, s_noise, s_pick = np.random.SeedSequence(seed0 + i).spawn(3)
+        rp = np.random.default_rng(s_pick)
+        grid = [(256, 256, 48, 0.4), (512, 512, 64, 0.2)][int(rp.integers(0, 2))]
+        base = make_scene(seed0 + i + 1000, 300.0, 0, 0, 0)
+        _, _, path = trajectory(base, np.random.default_rng(s_traj), n_steps, 0.45, 1.5, 0.1,
+                                300.0)
+        sc = make_scene(seed0 + i + 1000, 300.0, 40, 60, 10, keep_clear=(path, 3.0))
+        true, mapper, _ = trajectory(sc, np.random.default_rng(s_traj), n_steps, 0.45, 1.5, 0.1,
+                                     300.0)
+        r_noise = np.random.default_rng(s_noise)
+        scans = []
+        for (R, t) in true:
+            n_pts = float(np.exp(rp.uniform(np.log(20000), np.log(330000))))
+            n_az = max(1, int(round(n_pts / n_beams)))
+            dirs = lidar_dirs(n_beams, -16.6, 16.6, n_az, device)
+            scans.append(simulate_scan(sc, R, t, dirs, 100.0, 0.02, r_noise))
+        out.append(dict(params=params_for(*grid), scans=scans, poses=mapper, firing=n_beams))
+    return out
+
+
+def surrogate_sequence(seed: int, n_scans: int = 20, device="cpu", n_beams=32, n_az=1024):
+    """Gap-fill training / evaluation sequence: n_scans scans of a 32-beam x 1024
+    lidar (50 m, sigma 0.02 m) along a spline at 4.5 m/s (0.45 m per scan) in a
+    150 x 150 m scene with 12 boxes, 20 vegetation clusters and 4 pits;
+    128 x 128 x 32 map at 0.4 m.  Scan 0 is the single-frame input, all scans
+    together give the dense label."""
+    s_traj, s_noise = np.random.SeedSequence(seed).spawn(2)
+    r_noise = np.random.default_rng(s_noise)
+    base = make_scene(seed + 5000, 150.0, 0, 0, 0)
+    _, _, path = trajectory(base, np.random.default_rng(s_traj), n_scans, 0.45, 1.5, 0.1, 150.0)
+    sc = make_scene(seed + 5000, 150.0, 12, 20, 4, keep_clear=(path, 3.0))
+    true, mapper, _ = trajectory(sc, np.random.default_rng(s_traj), n_scans, 0.45, 1.5, 0.1,
+                                 150.0)
+    dirs = lidar_dirs(n_beams, -16.6, 16.6, n_az, device)
+    scans = [simulate_scan(sc, R, t, dirs, 50.0, 0.02, r_noise) for R, t in true]
+    return dict(params=params_for(128, 128, 32, 0.4, 16), scans=scans, poses=mapper,
+                firing=n_beams)

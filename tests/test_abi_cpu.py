@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "gvom.h")
 def declared_functions():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(map_[a-z_0-9]+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*((?:map|sgt)_[a-z_0-9]+)\s*\(", txt, re.M)))
 
 
 @pytest.fixture(scope="module")
