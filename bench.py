@@ -36,9 +36,10 @@ def phase_bytes(params, st, n_occ):
     nx, ny, nz = params["nx"], params["ny"], params["nz"]
     V, C, W = nx * ny * nz, nx * ny, (nz + 63) // 64
     return {
-        # points read; passes read+write per distinct passed voxel; hits and
-        # min height read+write per distinct hit voxel
-        "insert": 12 * st["n_points"] + 8 * st["n_distinct_pass"] + 16 * st["n_distinct_hit"],
+        # points read; hits and min height read+write per distinct hit voxel
+        "rays": 12 * st["n_points"] + 16 * st["n_distinct_hit"],
+        # passes read+write per distinct passed voxel
+        "trace": 8 * st["n_distinct_pass"],
         "scroll": 12 * st["n_cleared"],
         # occupancy word, ground-voxel height, outputs (height, density, flags, Q height)
         "column": C * (8 * W + 4 + 13),

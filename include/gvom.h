@@ -186,31 +186,40 @@ int32_t map_get_origin(const map_t* m, int32_t origin_vox[3]);
 int32_t map_sync(map_t* m);
 
 /* Launch tuning (performance only: results are bit-identical for every
- * setting).  seg_len: dominant-axis voxels per ray segment of the traversal
- * pass, 1..1024 (default 32); trace_waves_per_cu: resident waves per compute
- * unit requested for the traversal grid, 1..32 (default 32).  A field <= 0
- * keeps the current value. */
+ * setting).  traversal: 2 = segmented (rays cut every seg_len dominant-axis
+ * voxels, runs of equal voxels in neighbouring lanes merged, one global
+ * atomic per run; default, and always used by batches), 1 = binned (rays
+ * cut at 16-voxel storage slabs, passes counted per slab tile in LDS, then
+ * added to the map; single-map inserts only, when the window has at most
+ * 16,384 tiles and the scan at most 524,288 points, else segmented).  seg_len: dominant-axis voxels per ray
+ * segment of the segmented traversal, 1..1024 (default 32);
+ * trace_waves_per_cu: resident waves per compute unit requested for the
+ * segmented traversal grid, 1..32 (default 32).  A field <= 0 keeps the
+ * current value. */
 typedef struct {
   int32_t seg_len;
   int32_t trace_waves_per_cu;
+  int32_t traversal;
 } map_tuning_t;
 int32_t map_set_tuning(map_t* m, const map_tuning_t* t);
 int32_t map_get_tuning(const map_t* m, map_tuning_t* out);
 
 /* Optional per-phase timing with HIP events recorded on the map's stream
  * around each kernel group (instrumentation for benchmarks).  Phases:
- * MAP_PROF_SCROLL (window clears), MAP_PROF_INSERT (transform + returns +
- * ray traversal kernel), MAP_PROF_COLUMN (column reduction), MAP_PROF_SURFACE
- * (slope, roughness, negative obstacles), MAP_PROF_LUT (lookup-table export).
+ * MAP_PROF_SCROLL (window clears), MAP_PROF_RAYS (transform, returns and the
+ * ray-segment list), MAP_PROF_TRACE (ray traversal), MAP_PROF_COLUMN (column
+ * reduction), MAP_PROF_SURFACE (slope, roughness, negative obstacles),
+ * MAP_PROF_LUT (lookup-table export).
  * map_profile_read synchronises, adds the elapsed milliseconds and launch
  * counts since the last read into ms[MAP_PROF_N] / count[MAP_PROF_N] (host),
  * and releases the events. */
 #define MAP_PROF_SCROLL  0
-#define MAP_PROF_INSERT  1
-#define MAP_PROF_COLUMN  2
-#define MAP_PROF_SURFACE 3
-#define MAP_PROF_LUT     4
-#define MAP_PROF_N       5
+#define MAP_PROF_RAYS    1
+#define MAP_PROF_TRACE   2
+#define MAP_PROF_COLUMN  3
+#define MAP_PROF_SURFACE 4
+#define MAP_PROF_LUT     5
+#define MAP_PROF_N       6
 int32_t map_profile_enable(map_t* m, int32_t enable);
 int32_t map_profile_read(map_t* m, double ms[MAP_PROF_N], int64_t count[MAP_PROF_N]);
 

@@ -123,12 +123,6 @@ bool move_window(map_t* m, const int32_t o[3], gvom::ClearArgs* plan) {
   return false;
 }
 
-hipError_t run_move(map_t* m, const int32_t o[3]) {
-  gvom::ClearArgs plan;
-  if (move_window(m, o, &plan)) return clear_all(m);
-  return gvom::launch_clear(plan, m->stream);
-}
-
 // Records the start event of a profiled phase (no-op when profiling is off).
 int prof_begin(map_t* m, int phase) {
   if (!m->prof) return -1;
@@ -209,6 +203,7 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   }
   m->seg_len = 32;
   m->trace_wpc = 32;
+  m->traversal = 2;
   m->part_trace_cap = (int64_t)m->n_cu * 32 / 4 + 1;
   m->d.nx = p->nx;
   m->d.ny = p->ny;
@@ -232,6 +227,15 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   if (e == hipSuccess) e = dmalloc(&m->stats, kStatsBytes);
   if (e == hipSuccess) e = dmalloc(&m->err, 4);
   if (e == hipSuccess) e = dmalloc(&m->part_trace, m->part_trace_cap * 16);
+  m->gx = (p->nx + gvom::kBinT - 1) / gvom::kBinT;
+  m->gy = (p->ny + gvom::kBinT - 1) / gvom::kBinT;
+  m->nbins = 4 * m->gx * m->gy + 1;
+  if (m->nbins <= gvom::kMaxBins) {
+    if (e == hipSuccess) e = dmalloc(&m->bin_cnt, (int64_t)m->nbins * 2 * 4);
+    if (e == hipSuccess) e = dmalloc(&m->bin_snap, (int64_t)m->nbins * 4);
+    if (e == hipSuccess) e = dmalloc(&m->uctl, 8);
+    if (e == hipSuccess) e = hipMemsetAsync(m->bin_cnt, 0, (size_t)m->nbins * 2 * 4, m->stream);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     map_destroy(m);
@@ -267,6 +271,11 @@ int32_t map_destroy(map_t* m) {
   (void)hipFree(m->items);
   (void)hipFree(m->part_rays);
   (void)hipFree(m->part_trace);
+  (void)hipFree(m->bin_cnt);
+  (void)hipFree(m->bin_snap);
+  (void)hipFree(m->uctl);
+  (void)hipFree(m->bin_ent);
+  (void)hipFree(m->units);
   delete m;
   return MAP_OK;
 }
@@ -284,6 +293,8 @@ int32_t map_reset(map_t* m) {
   m->last_trace_blocks = 0;
   hipError_t e = clear_all(m);
   if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, kStatsBytes, m->stream);
+  if (e == hipSuccess && m->bin_cnt)
+    e = hipMemsetAsync(m->bin_cnt, 0, (size_t)m->nbins * 2 * 4, m->stream);
   return dev_status(m, e);
 }
 
@@ -336,11 +347,14 @@ bool grow(map_t* m, T** p, int64_t* cap, int64_t need, size_t elem) {
 // fills the kernel arguments.  Updates the host-side map state.
 int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* pose,
                        uint32_t flags, const int32_t S[3], gvom::InsertArgs* a,
-                       gvom::ClearArgs* plan, bool* full) {
+                       gvom::ClearArgs* plan, bool* full, bool allow_binned) {
   // ray block b writes its segments into the region of stripe b mod kStripes,
   // sized for the most segments that stripe's points can produce
   const int64_t ray_blocks = (n + gvom::kRayBlock - 1) / gvom::kRayBlock;
-  const int64_t per_ray = gvom::max_segments(m->d, m->seg_len);
+  const bool binned =
+      allow_binned && m->traversal == 1 && m->bin_cnt && ray_blocks <= gvom::kMaxEnt;
+  const int64_t per_ray =
+      binned ? gvom::max_segments_binned(m->d) : gvom::max_segments(m->d, m->seg_len);
   int64_t need = 0;
   for (int t = 0; t < gvom::kStripes; t++) {
     const int64_t blocks =
@@ -352,8 +366,16 @@ int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* p
     a->stripe_cap[t] = pts * per_ray;
     need += a->stripe_cap[t];
   }
+  if (binned && need > 2147483647LL) return MAP_E_RANGE;  // entries hold int32 offsets
   if (!grow(m, &m->items, &m->item_cap, need, sizeof(int4))) return MAP_E_OOM;
   if (!grow(m, &m->part_rays, &m->part_rays_cap, ray_blocks, 32)) return MAP_E_OOM;
+  if (binned) {
+    if (!grow(m, &m->bin_ent, &m->bin_ent_cap, (int64_t)m->nbins * (ray_blocks > 0 ? ray_blocks : 1),
+              sizeof(int2)))
+      return MAP_E_OOM;
+    if (!grow(m, &m->units, &m->units_cap, need / gvom::kUnit + m->nbins + 1, sizeof(int4)))
+      return MAP_E_OOM;
+  }
   *full = false;
   plan->nbox = 0;
   if (flags & MAP_RECENTER) {
@@ -394,7 +416,26 @@ int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* p
   const int64_t want = (need + 255) / 256;
   const int64_t lim = (int64_t)m->n_cu * m->trace_wpc / 4;
   a->trace_blocks = n > 0 ? (int32_t)(want < lim ? want : lim) : 0;
-  m->last_trace_blocks = a->trace_blocks;
+  a->binned = binned ? 1 : 0;
+  a->gx = m->gx;
+  a->gy = m->gy;
+  a->nb = m->nbins;
+  a->maxblk = (int32_t)(ray_blocks > 0 ? ray_blocks : 1);
+  a->bin_nent = m->bin_cnt;
+  a->bin_tot = m->bin_cnt ? m->bin_cnt + m->nbins : nullptr;
+  a->bin_snap = m->bin_snap;
+  a->bin_ent = m->bin_ent;
+  a->units = m->units;
+  a->uctl = m->uctl;
+  // persistent traversal: as many groups as fit next to each other per CU
+  const int64_t lds = (int64_t)gvom::trace_bin_lds(m->p.nz) + 6 * 1024;
+  int64_t per_cu = (160 * 1024) / lds;
+  if (per_cu < 1) per_cu = 1;
+  int64_t tb = (int64_t)m->n_cu * per_cu;
+  if (tb > m->part_trace_cap) tb = m->part_trace_cap;
+  a->tb_blocks = (int32_t)tb;
+  m->last_trace_blocks = binned ? a->tb_blocks : a->trace_blocks;
+  if (n <= 0) m->last_trace_blocks = 0;
   return MAP_OK;
 }
 
@@ -460,7 +501,7 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
   gvom::ClearArgs plan;
   bool full = false;
   const int pm0 = prof_begin(m, MAP_PROF_SCROLL);
-  st = prepare_insert(m, xyz_dev, n, pose, flags, S, &a, &plan, &full);
+  st = prepare_insert(m, xyz_dev, n, pose, flags, S, &a, &plan, &full, true);
   if (st) return st;
   hipError_t e = full ? clear_all(m) : gvom::launch_clear(plan, m->stream);
   prof_end(m, pm0);
@@ -474,9 +515,14 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
     a.touch = m->touch;
   }
   if (e == hipSuccess && n > 0) {
-    const int pm = prof_begin(m, MAP_PROF_INSERT);
-    e = gvom::launch_insert(a, distinct, m->stream);
+    int pm = prof_begin(m, MAP_PROF_RAYS);
+    e = gvom::launch_rays(a, distinct, m->stream);
     prof_end(m, pm);
+    if (e == hipSuccess) {
+      pm = prof_begin(m, MAP_PROF_TRACE);
+      e = gvom::launch_trace(a, distinct, m->stream);
+      prof_end(m, pm);
+    }
   }
   return dev_status(m, e);
 }
@@ -588,7 +634,7 @@ int32_t map_sync(map_t* m) {
 
 int32_t map_set_tuning(map_t* m, const map_tuning_t* t) {
   if (!m || !t) return MAP_E_INVALID;
-  if (t->seg_len > 1024 || t->trace_waves_per_cu > 32) return MAP_E_INVALID;
+  if (t->seg_len > 1024 || t->trace_waves_per_cu > 32 || t->traversal > 2) return MAP_E_INVALID;
   if (t->seg_len > 0 && t->seg_len != m->seg_len) {
     // the segment buffer is sized for the segment length: regrow on next insert
     if (hipStreamSynchronize(m->stream) != hipSuccess) return dev_status(m, hipErrorUnknown);
@@ -598,6 +644,7 @@ int32_t map_set_tuning(map_t* m, const map_tuning_t* t) {
     m->seg_len = t->seg_len;
   }
   if (t->trace_waves_per_cu > 0) m->trace_wpc = t->trace_waves_per_cu;
+  if (t->traversal > 0) m->traversal = t->traversal;
   return MAP_OK;
 }
 
@@ -605,6 +652,7 @@ int32_t map_get_tuning(const map_t* m, map_tuning_t* out) {
   if (!m || !out) return MAP_E_INVALID;
   out->seg_len = m->seg_len;
   out->trace_waves_per_cu = m->trace_wpc;
+  out->traversal = m->traversal;
   return MAP_OK;
 }
 
@@ -686,7 +734,7 @@ int32_t batch_prepare(map_batch_t* b, const float* const* xyz_dev, const int64_t
     map_t* m = b->maps[i];
     bool full = false;
     const int32_t s = prepare_insert(m, xyz_dev[i], n[i], poses + 12 * i, flags[i], S[i],
-                                     &t->ins[i], &t->clr[i], &full);
+                                     &t->ins[i], &t->clr[i], &full, false);
     if (s) return s;  // allocation failure
     column_args(m, &out2d[i], &t->col[i]);
     surface_args(m, &out2d[i], &t->sur[i]);
@@ -895,7 +943,7 @@ int32_t map_batch_autotune(map_batch_t* b, const float* const* xyz_dev, const in
   }
   for (char& c : key)
     if (c == ' ') c = '_';
-  map_tuning_t best{0, 0};
+  map_tuning_t best{0, 0, 0};
   bool cached = false;
   if (cache_path) {
     if (FILE* f = fopen(cache_path, "r")) {
@@ -919,7 +967,7 @@ int32_t map_batch_autotune(map_batch_t* b, const float* const* xyz_dev, const in
     float best_ms = 1e30f;
     for (int si = 0; si < 3; si++)
       for (int wi = 0; wi < 3; wi++) {
-        const map_tuning_t t{segs[si], wpcs[wi]};
+        const map_tuning_t t{segs[si], wpcs[wi], 0};
         for (int i = 0; i < b->k; i++) map_set_tuning(b->maps[i], &t);
         float tot = 0.0f;
         for (int rep = 0; rep < 3; rep++) {

@@ -35,6 +35,19 @@ __host__ __device__ __forceinline__ int32_t col_base(const Dims& d, int32_t sx, 
 
 constexpr int kStripes = 16;  // independent segment counters of the ray pass
 
+// Binned traversal: slab / tile edge along x and y (storage cells), storage
+// rows of a bin's LDS region along the cross axis, segments per work unit,
+// segment length of z-dominant rays, bin and entry limits, block size.
+constexpr int kBinT = 16;
+constexpr int kBinRows = 2 * kBinT + 4;
+constexpr int kLevelHalves = kBinT * kBinRows;    // 16-bit counters per z level
+constexpr int kLevelWords = kLevelHalves / 2;     // 32-bit LDS words per z level
+constexpr int kUnit = 1024;
+constexpr int kSegG = 32;
+constexpr int kMaxBins = 16385;
+constexpr int kMaxEnt = 512;
+constexpr int kTraceBinThreads = 512;
+
 struct InsertArgs {
   const float* xyz;
   int32_t n;
@@ -59,12 +72,27 @@ struct InsertArgs {
   int64_t stripe_cap[kStripes];
   int32_t seg_len;             // dominant-axis voxels per segment
   int32_t trace_blocks;        // grid of the trace kernel
+  // binned traversal (used when `binned` is set)
+  int32_t binned;
+  int32_t gx, gy;              // slabs along x and along y (ceil(n / kBinT))
+  int32_t nb;                  // bins, the last one holding z-dominant rays
+  int32_t maxblk;              // entry slots per bin (= ray blocks)
+  int32_t* bin_nent;           // [nb] entries per bin (zeroed again by k_binscan)
+  int32_t* bin_tot;            // [nb] segments per bin (zeroed again by k_binscan)
+  int32_t* bin_snap;           // [nb] entries per bin for the traversal
+  int2* bin_ent;               // [nb][maxblk] {first item, count}
+  int4* units;                 // {bin, first segment, segments, 0}
+  int32_t* uctl;               // [0] units, [1] work queue
+  int32_t tb_blocks;           // grid of the binned traversal
 };
 
 constexpr int kRayBlock = 1024;   // threads per block of the ray pass
 
-// Segments one ray can produce at most.
+// Segments one ray can produce at most (segmented / binned traversal).
 int64_t max_segments(const Dims& d, int32_t seg_len);
+int64_t max_segments_binned(const Dims& d);
+size_t rays_bin_lds(int nb);
+size_t trace_bin_lds(int nz);
 
 struct ColumnArgs {
   Dims d;
@@ -170,7 +198,8 @@ uint32_t nz_magic(int nz);
 
 // Launchers (all enqueue on `s`, return the launch status).
 hipError_t launch_clear(const ClearArgs& a, hipStream_t s);
-hipError_t launch_insert(const InsertArgs& a, bool distinct, hipStream_t s);
+hipError_t launch_rays(const InsertArgs& a, bool distinct, hipStream_t s);
+hipError_t launch_trace(const InsertArgs& a, bool distinct, hipStream_t s);
 hipError_t launch_column(const ColumnArgs& a, hipStream_t s);
 hipError_t launch_surface(const SurfaceArgs& a, hipStream_t s);
 hipError_t launch_lut(const LutArgs& a, hipStream_t s);

@@ -31,6 +31,15 @@ struct map_t {
   int64_t last_ray_blocks, last_trace_blocks;
   int32_t seg_len;
   int32_t trace_wpc;
+  int32_t traversal;          // 1: binned when the window allows it, 2: segmented
+  // binned traversal state (allocated when the window gives few enough bins)
+  int32_t gx, gy, nbins;      // slabs along x / y; bins incl. the z-dominant one
+  int32_t* bin_cnt;           // [2 * nbins]: entries, then segments per bin
+  int32_t* bin_snap;          // [nbins]
+  int32_t* uctl;              // [2]
+  int2* bin_ent;              // [nbins][blocks]
+  int4* units;
+  int64_t bin_ent_cap, units_cap;
   int32_t n_cu;
   int32_t sticky;
   int64_t last_points, last_cleared;

@@ -47,7 +47,8 @@ class map_2d_t(ctypes.Structure):
 
 
 class map_tuning_t(ctypes.Structure):
-    _fields_ = [("seg_len", ctypes.c_int32), ("trace_waves_per_cu", ctypes.c_int32)]
+    _fields_ = [("seg_len", ctypes.c_int32), ("trace_waves_per_cu", ctypes.c_int32),
+                ("traversal", ctypes.c_int32)]
 
 
 class map_stats_t(ctypes.Structure):
@@ -67,7 +68,7 @@ EXPORTED = [
     "sgt_set_norm", "sgt_features", "sgt_thin", "sgt_feature_sums", "sgt_forward",
     "sgt_loss_grad", "sgt_adam", "sgt_fill",
 ]
-PROF_PHASES = ("scroll", "insert", "column", "surface", "lut")
+PROF_PHASES = ("scroll", "rays", "trace", "column", "surface", "lut")
 
 _lib = None
 
@@ -227,14 +228,16 @@ def map_sync(h) -> int:
     return lib().map_sync(h)
 
 
-def map_set_tuning(h, seg_len: int = 0, trace_waves_per_cu: int = 0) -> int:
-    return lib().map_set_tuning(h, ctypes.byref(map_tuning_t(seg_len, trace_waves_per_cu)))
+def map_set_tuning(h, seg_len: int = 0, trace_waves_per_cu: int = 0, traversal: int = 0) -> int:
+    return lib().map_set_tuning(h, ctypes.byref(map_tuning_t(seg_len, trace_waves_per_cu,
+                                                             traversal)))
 
 
 def map_get_tuning(h):
     t = map_tuning_t()
     s = lib().map_get_tuning(h, ctypes.byref(t))
-    return s, {"seg_len": t.seg_len, "trace_waves_per_cu": t.trace_waves_per_cu}
+    return s, {"seg_len": t.seg_len, "trace_waves_per_cu": t.trace_waves_per_cu,
+               "traversal": t.traversal}
 
 
 def map_profile_enable(h, enable: bool) -> int:

@@ -25,10 +25,11 @@ def _cloud(rng, n, radius):
     return p.astype(np.float32)
 
 
+@pytest.mark.parametrize("traversal", [1, 2])
 @pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 257, 3001])
-def test_ragged_clouds_tiny_map(n):
+def test_ragged_clouds_tiny_map(n, traversal):
     rng = np.random.default_rng(100 + n)
-    pair = Pair(params(16, 16, 16, 0.5, szv=7))
+    pair = Pair(params(16, 16, 16, 0.5, szv=7), traversal)
     try:
         pose = scenegen.pose12(_rot(0.3, 0.1, -0.2), [0.7, -0.4, 0.25])
         assert pair.insert(_cloud(rng, n, 6.0), pose, 0) == 0
@@ -40,10 +41,11 @@ def test_ragged_clouds_tiny_map(n):
 @pytest.mark.parametrize("dims", [(16, 16, 16, 0.5), (18, 10, 12, 0.25), (40, 26, 7, 0.3),
                                   (32, 32, 64, 0.2), (30, 34, 96, 0.1), (20, 22, 128, 0.15),
                                   (24, 24, 48, 0.4)])
-def test_shapes_and_distinct_counts(dims):
+@pytest.mark.parametrize("traversal", [1, 2])
+def test_shapes_and_distinct_counts(dims, traversal):
     nx, ny, nz, res = dims
     rng = np.random.default_rng(nx * 1000 + nz)
-    pair = Pair(params(nx, ny, nz, res))
+    pair = Pair(params(nx, ny, nz, res), traversal)
     try:
         for k in range(3):
             ang = rng.uniform(-np.pi, np.pi, 3) * np.array([1, 0.3, 0.3])
@@ -55,9 +57,10 @@ def test_shapes_and_distinct_counts(dims):
         pair.close()
 
 
-def test_single_scan_16beam_scene():
+@pytest.mark.parametrize("traversal", [1, 2])
+def test_single_scan_16beam_scene(traversal):
     w = scenegen.single_scan_16beam(seed=1)
-    pair = Pair(w["params"])
+    pair = Pair(w["params"], traversal)
     try:
         assert pair.insert(w["scans"][0], w["poses"][0], 2, firing=16) == 0
         n, g, o = compare_all(pair, distinct=True)
@@ -85,12 +88,13 @@ def test_firing_hint_does_not_change_results():
             assert (o2[k].view(np.uint8) == outs[0][2][k].view(np.uint8)).all(), k
 
 
-def test_moving_window_sequence():
+@pytest.mark.parametrize("traversal", [1, 2])
+def test_moving_window_sequence(traversal):
     """Recentring every scan: scrolls in x, y and z (toroidal wrap), one jump
     larger than the window (full clear), general rotations."""
     rng = np.random.default_rng(7)
     p = params(48, 40, 20, 0.5, szv=8)
-    pair = Pair(p)
+    pair = Pair(p, traversal)
     try:
         pos = np.zeros(3)
         for k in range(14):
@@ -238,3 +242,44 @@ def test_reset_and_repeat_bit_identical():
         assert gvom.map_reset(m.h) == 0
     assert (res[0][0] == res[1][0]).all() and (res[0][1] == res[1][1]).all()
     m.close()
+
+
+def _state(m):
+    lut, data, n_occ, origin = m.export_voxels()
+    out = m.export_2d()
+    torch.cuda.synchronize()
+    return (lut.cpu().numpy().copy(), data[:int(n_occ.item())].cpu().numpy().copy(), origin.copy(),
+            {k: v.cpu().numpy().copy() for k, v in out.items()}, m.stats())
+
+
+@pytest.mark.parametrize("distinct", [False, True])
+def test_traversal_modes_bit_identical(distinct):
+    """The binned traversal (LDS tiles) and the segmented one (global atomics)
+    give the same map bit for bit: four scans of the 64-beam sequence on the
+    512 x 512 x 64 window (recentred each scan, so the storage offsets move),
+    then a cloud of steep rays (z-dominant ones take the global bin)."""
+    from paper_2109_13176_amd import gvom
+    seq = scenegen.sequence_64beam(seed=2, n_scans=4, device="cuda")
+    maps = [gvom.VoxelMap(seq["params"]) for _ in range(2)]
+    for m, mode in zip(maps, (1, 2)):
+        assert gvom.map_set_tuning(m.h, traversal=mode) == 0
+        assert gvom.map_get_tuning(m.h)[1]["traversal"] == mode
+    rng = np.random.default_rng(3)
+    steep = _cloud(rng, 20000, 30.0)
+    steep[:, 2] *= 3.0
+    fl = gvom.MAP_FIRING(64) | (gvom.MAP_STATS_DISTINCT if distinct else 0)
+    try:
+        for k in range(5):
+            xyz = seq["scans"][k] if k < 4 else torch.as_tensor(steep, device="cuda")
+            pose = seq["poses"][k] if k < 4 else seq["poses"][3]
+            for m in maps:
+                m.insert(xyz.contiguous(), pose, fl | gvom.MAP_RECENTER)
+            a, b = _state(maps[0]), _state(maps[1])
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+            assert np.array_equal(a[2], b[2])
+            for key in a[3]:
+                assert np.array_equal(a[3][key].view(np.uint8), b[3][key].view(np.uint8)), key
+            assert a[4] == b[4], (a[4], b[4])
+    finally:
+        for m in maps:
+            m.close()
