@@ -25,6 +25,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "lidar points/sec ingested + map updates/sec (64-beam, 512x512x64) on 1 MI355X"
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_2109_13176_amd", "csrc")
+# sources of the segmented traversal kernel (k_trace) whose counters are committed
+TRACE_SRCS = [os.path.join(CSRC, f) for f in ("insert.hip", "ray_common.h", "gvom_internal.h")]
 
 
 def log(*a):
@@ -49,6 +53,73 @@ def phase_bytes(params, st, n_occ):
         # out, hits + min height of occupied voxels
         "lut": 2 * 8 * C * W + 4 * V + 4 * V + 12 * n_occ + 8 * n_occ,
     }
+
+
+def read_summary(name):
+    """key: value lines of a committed profile summary (None if absent)."""
+    path = os.path.join(PROFILES, name)
+    if not os.path.exists(path):
+        return None
+    out = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            out[k.strip()] = v.strip()
+    return out
+
+
+def source_sha(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the traversal kernel from the committed PMC
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy's counters), or
+    None when the kernel source changed since the counters were taken."""
+    s = read_summary("trace_seq64_traffic.txt")
+    if not s or s.get("kernel sources sha256[:16]") != source_sha(TRACE_SRCS):
+        return None
+    return float(s["hbm bytes per launch"])
+
+
+def calibrate():
+    """Plain copy bandwidth (the scale for FETCH_SIZE / WRITE_SIZE) and the
+    rate of scattered int32 atomic adds, both with torch's own kernels."""
+    import torch
+    n = 128 << 20  # int32 elements: 512 MiB per buffer
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    copy_gbs = 2 * n * 4 / t / 1e9
+    tgt = torch.zeros(64 << 20, dtype=torch.int32, device="cuda")
+    idx = torch.randint(0, tgt.numel(), (16 << 20,), device="cuda")
+    one = torch.ones(idx.numel(), dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        tgt.scatter_add_(0, idx, one)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        tgt.scatter_add_(0, idx, one)
+    e1.record()
+    torch.cuda.synchronize()
+    t2 = e0.elapsed_time(e1) / reps * 1e-3
+    out = {"copy_bytes_per_launch": 2 * n * 4, "copy_GBps": copy_gbs,
+           "scatter_atomics_per_launch": idx.numel(), "scatter_atomics_per_s": idx.numel() / t2}
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(seq, n_scans):
@@ -79,10 +150,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-scans", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traversal", type=int, default=0, choices=[0, 1, 2],
+                    help="ray traversal: 1 binned (LDS tiles), 2 segmented, 0 library default")
+    ap.add_argument("--print-sha", action="store_true",
+                    help="print the hash of the traversal kernel sources, then exit")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="measure a plain copy and scattered atomics (profile scaling), then exit")
     ap.add_argument("--workload", default="seq64", choices=["seq64", "batch32"],
                     help="seq64: the 64-beam 512x512x64 sequence (default); batch32: 32 "
                          "independent maps stepped as one batch")
     args = ap.parse_args()
+    if args.print_sha:
+        print(source_sha(TRACE_SRCS))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(independent maps would shard one per GPU with no exchange).", file=sys.stderr)
@@ -94,6 +174,8 @@ def main():
     from synth import scenegen
 
     torch.cuda.set_device(0)
+    if args.calibrate:
+        return calibrate()
     if args.workload == "batch32":
         return bench_batch(args)
     W, K = args.warmup, args.steps
@@ -107,6 +189,8 @@ def main():
 
     # untimed pre-pass on a shadow map: distinct voxels touched per scan
     shadow = gvom.VoxelMap(params)
+    if args.traversal:
+        gvom.map_set_tuning(shadow.h, traversal=args.traversal)
     dstats = []
     for k in range(W + K):
         shadow.insert(scans[k], poses[k], flags | gvom.MAP_STATS_DISTINCT)
@@ -116,6 +200,8 @@ def main():
     del shadow
 
     m = gvom.VoxelMap(params)
+    if args.traversal:
+        gvom.map_set_tuning(m.h, traversal=args.traversal)
     gvom.map_profile_enable(m.h, True)
 
     def step(k):
@@ -155,7 +241,17 @@ def main():
     dom = max(phases, key=lambda p: phases[p]["avg_ms"] * phases[p]["launches"])
     roof = {"kernel": dom, "bound": "hbm", "achieved": phases[dom]["gbps"],
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": phases[dom]["gbps"] / HBM_PEAK_GBS, "traffic": None}
+            "frac": phases[dom]["gbps"] / HBM_PEAK_GBS,
+            "traffic": measured_traffic() if dom == "trace" and args.traversal != 1 else None}
+    if dom == "trace":
+        # co-reported: global pass updates per second against the measured
+        # rate of scattered int32 atomics (torch scatter_add on this GPU)
+        upd = avg["n_pass_updates"] / (phases["trace"]["avg_ms"] * 1e-3)
+        cal = read_summary("calibration_mi355x.txt")
+        peak = float(cal["scatter atomics per s"]) if cal else None
+        roof["atomics"] = {"achieved": upd, "peak": peak, "unit": "updates/s",
+                           "frac": upd / peak if peak else None,
+                           "updates_per_launch": avg["n_pass_updates"]}
 
     out = {
         "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": K,
@@ -170,7 +266,8 @@ def main():
         "phases": phases,
         "per_scan": {"pass_incidences": avg["n_pass"], "distinct_passed": avg["n_distinct_pass"],
                      "distinct_hit": avg["n_distinct_hit"], "hits": avg["n_hits"],
-                     "occupied_voxels_final": n_occ, "cleared": avg["n_cleared"]},
+                     "occupied_voxels_final": n_occ, "cleared": avg["n_cleared"],
+                     "pass_updates": avg["n_pass_updates"]},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

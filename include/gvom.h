@@ -116,6 +116,9 @@ typedef struct {
   int64_t n_distinct_pass;  /* distinct voxels passed (-1 without MAP_STATS_DISTINCT) */
   int64_t n_distinct_hit;   /* distinct voxels hit   (-1 without MAP_STATS_DISTINCT) */
   int64_t n_cleared;        /* window voxels reset by the recentring              */
+  int64_t n_pass_updates;   /* global-memory pass updates the traversal issued
+                               (diagnostic: depends on the work order, so it is
+                               not reproducible from run to run)                  */
 } map_stats_t;
 
 typedef struct map_t map_t;  /* opaque */

@@ -226,15 +226,14 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   if (e == hipSuccess) e = dmalloc(&m->colpre, C * 4);
   if (e == hipSuccess) e = dmalloc(&m->stats, kStatsBytes);
   if (e == hipSuccess) e = dmalloc(&m->err, 4);
-  if (e == hipSuccess) e = dmalloc(&m->part_trace, m->part_trace_cap * 16);
+  if (e == hipSuccess) e = dmalloc(&m->part_trace, m->part_trace_cap * 32);
   m->gx = (p->nx + gvom::kBinT - 1) / gvom::kBinT;
   m->gy = (p->ny + gvom::kBinT - 1) / gvom::kBinT;
   m->nbins = 4 * m->gx * m->gy + 1;
   if (m->nbins <= gvom::kMaxBins) {
-    if (e == hipSuccess) e = dmalloc(&m->bin_cnt, (int64_t)m->nbins * 2 * 4);
-    if (e == hipSuccess) e = dmalloc(&m->bin_snap, (int64_t)m->nbins * 4);
+    if (e == hipSuccess) e = dmalloc(&m->bin_cnt, (int64_t)m->nbins * 4);
     if (e == hipSuccess) e = dmalloc(&m->uctl, 8);
-    if (e == hipSuccess) e = hipMemsetAsync(m->bin_cnt, 0, (size_t)m->nbins * 2 * 4, m->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(m->bin_cnt, 0, (size_t)m->nbins * 4, m->stream);
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -272,7 +271,6 @@ int32_t map_destroy(map_t* m) {
   (void)hipFree(m->part_rays);
   (void)hipFree(m->part_trace);
   (void)hipFree(m->bin_cnt);
-  (void)hipFree(m->bin_snap);
   (void)hipFree(m->uctl);
   (void)hipFree(m->bin_ent);
   (void)hipFree(m->units);
@@ -294,7 +292,7 @@ int32_t map_reset(map_t* m) {
   hipError_t e = clear_all(m);
   if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, kStatsBytes, m->stream);
   if (e == hipSuccess && m->bin_cnt)
-    e = hipMemsetAsync(m->bin_cnt, 0, (size_t)m->nbins * 2 * 4, m->stream);
+    e = hipMemsetAsync(m->bin_cnt, 0, (size_t)m->nbins * 4, m->stream);
   return dev_status(m, e);
 }
 
@@ -350,18 +348,20 @@ int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* p
                        gvom::ClearArgs* plan, bool* full, bool allow_binned) {
   // ray block b writes its segments into the region of stripe b mod kStripes,
   // sized for the most segments that stripe's points can produce
-  const int64_t ray_blocks = (n + gvom::kRayBlock - 1) / gvom::kRayBlock;
+  const int64_t bin_blocks = (n + gvom::kRayBinBlock - 1) / gvom::kRayBinBlock;
   const bool binned =
-      allow_binned && m->traversal == 1 && m->bin_cnt && ray_blocks <= gvom::kMaxEnt;
+      allow_binned && m->traversal == 1 && m->bin_cnt && bin_blocks <= gvom::kMaxEnt;
+  const int64_t rb = binned ? gvom::kRayBinBlock : gvom::kRayBlock;  // threads per ray block
+  const int64_t ray_blocks = (n + rb - 1) / rb;
   const int64_t per_ray =
       binned ? gvom::max_segments_binned(m->d) : gvom::max_segments(m->d, m->seg_len);
   int64_t need = 0;
   for (int t = 0; t < gvom::kStripes; t++) {
     const int64_t blocks =
         ray_blocks > t ? (ray_blocks - t + gvom::kStripes - 1) / gvom::kStripes : 0;
-    int64_t pts = blocks * gvom::kRayBlock;
+    int64_t pts = blocks * rb;
     if (blocks && t == (ray_blocks - 1) % gvom::kStripes)
-      pts -= ray_blocks * gvom::kRayBlock - n;  // the last block is partial
+      pts -= ray_blocks * rb - n;  // the last block is partial
     a->stripe_off[t] = need;
     a->stripe_cap[t] = pts * per_ray;
     need += a->stripe_cap[t];
@@ -421,9 +421,7 @@ int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* p
   a->gy = m->gy;
   a->nb = m->nbins;
   a->maxblk = (int32_t)(ray_blocks > 0 ? ray_blocks : 1);
-  a->bin_nent = m->bin_cnt;
-  a->bin_tot = m->bin_cnt ? m->bin_cnt + m->nbins : nullptr;
-  a->bin_snap = m->bin_snap;
+  a->bin_tot = m->bin_cnt;
   a->bin_ent = m->bin_ent;
   a->units = m->units;
   a->uctl = m->uctl;
@@ -588,17 +586,17 @@ int32_t map_get_stats(map_t* m, map_stats_t* out) {
   if (!m || !out) return MAP_E_INVALID;
   if (m->sticky) return m->sticky;
   std::vector<unsigned long long> pr((size_t)m->last_ray_blocks * 4 + 1),
-      pt((size_t)m->last_trace_blocks * 2 + 1);
+      pt((size_t)m->last_trace_blocks * 4 + 1);
   hipError_t e = hipSuccess;
   if (m->last_ray_blocks)
     e = hipMemcpyAsync(pr.data(), m->part_rays, m->last_ray_blocks * 32, hipMemcpyDeviceToHost,
                        m->stream);
   if (e == hipSuccess && m->last_trace_blocks)
-    e = hipMemcpyAsync(pt.data(), m->part_trace, m->last_trace_blocks * 16,
+    e = hipMemcpyAsync(pt.data(), m->part_trace, m->last_trace_blocks * 32,
                        hipMemcpyDeviceToHost, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) return dev_status(m, e);
-  int64_t c[6] = {0, 0, 0, 0, 0, 0};
+  int64_t c[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int64_t b = 0; b < m->last_ray_blocks; b++) {
     c[0] += (int64_t)pr[4 * b + 0];
     c[1] += (int64_t)pr[4 * b + 1];
@@ -606,8 +604,9 @@ int32_t map_get_stats(map_t* m, map_stats_t* out) {
     c[5] += (int64_t)pr[4 * b + 3];
   }
   for (int64_t b = 0; b < m->last_trace_blocks; b++) {
-    c[3] += (int64_t)pt[2 * b + 0];
-    c[4] += (int64_t)pt[2 * b + 1];
+    c[3] += (int64_t)pt[4 * b + 0];
+    c[4] += (int64_t)pt[4 * b + 1];
+    c[6] += (int64_t)pt[4 * b + 2];
   }
   out->n_points = m->last_points;
   out->n_nonfinite = c[0];
@@ -617,6 +616,7 @@ int32_t map_get_stats(map_t* m, map_stats_t* out) {
   out->n_distinct_pass = m->last_distinct ? c[4] : -1;
   out->n_distinct_hit = m->last_distinct ? c[5] : -1;
   out->n_cleared = m->last_cleared;
+  out->n_pass_updates = c[6];
   return MAP_OK;
 }
 

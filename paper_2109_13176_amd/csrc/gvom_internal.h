@@ -47,6 +47,7 @@ constexpr int kSegG = 32;
 constexpr int kMaxBins = 16385;
 constexpr int kMaxEnt = 512;
 constexpr int kTraceBinThreads = 512;
+constexpr int kRayBinBlock = 512;  // threads per block of the binned ray pass
 
 struct InsertArgs {
   const float* xyz;
@@ -65,7 +66,7 @@ struct InsertArgs {
   unsigned long long* stats;   // [8 global counters][kStripes segment counters]
   uint32_t* touch;             // distinct-voxel bitmaps [2][V/32] or null
   unsigned long long* part_rays;   // per ray block: nonfinite, range, hits, distinct hits
-  unsigned long long* part_trace;  // per trace block: passes, distinct passes
+  unsigned long long* part_trace;  // per trace block: passes, distinct passes, updates, 0
   int4* items;                 // ray segments {Qx, Qy, Qz, segment index}
   int64_t item_cap;
   int64_t stripe_off[kStripes];  // item region of each stripe of ray blocks
@@ -76,13 +77,11 @@ struct InsertArgs {
   int32_t binned;
   int32_t gx, gy;              // slabs along x and along y (ceil(n / kBinT))
   int32_t nb;                  // bins, the last one holding z-dominant rays
-  int32_t maxblk;              // entry slots per bin (= ray blocks)
-  int32_t* bin_nent;           // [nb] entries per bin (zeroed again by k_binscan)
+  int32_t maxblk;              // ray blocks: entry slots per bin
   int32_t* bin_tot;            // [nb] segments per bin (zeroed again by k_binscan)
-  int32_t* bin_snap;           // [nb] entries per bin for the traversal
-  int2* bin_ent;               // [nb][maxblk] {first item, count}
+  int2* bin_ent;               // [nb][maxblk] {first item, count} of ray block b
   int4* units;                 // {bin, first segment, segments, 0}
-  int32_t* uctl;               // [0] units, [1] work queue
+  int32_t* uctl;               // [0] units
   int32_t tb_blocks;           // grid of the binned traversal
 };
 
@@ -200,6 +199,8 @@ uint32_t nz_magic(int nz);
 hipError_t launch_clear(const ClearArgs& a, hipStream_t s);
 hipError_t launch_rays(const InsertArgs& a, bool distinct, hipStream_t s);
 hipError_t launch_trace(const InsertArgs& a, bool distinct, hipStream_t s);
+hipError_t launch_rays_bin(const InsertArgs& a, bool distinct, hipStream_t s);
+hipError_t launch_trace_bin(const InsertArgs& a, bool distinct, hipStream_t s);
 hipError_t launch_column(const ColumnArgs& a, hipStream_t s);
 hipError_t launch_surface(const SurfaceArgs& a, hipStream_t s);
 hipError_t launch_lut(const LutArgs& a, hipStream_t s);

@@ -34,9 +34,8 @@ struct map_t {
   int32_t traversal;          // 1: binned when the window allows it, 2: segmented
   // binned traversal state (allocated when the window gives few enough bins)
   int32_t gx, gy, nbins;      // slabs along x / y; bins incl. the z-dominant one
-  int32_t* bin_cnt;           // [2 * nbins]: entries, then segments per bin
-  int32_t* bin_snap;          // [nbins]
-  int32_t* uctl;              // [2]
+  int32_t* bin_cnt;           // [nbins] segments per bin
+  int32_t* uctl;              // [1] work units
   int2* bin_ent;              // [nbins][blocks]
   int4* units;
   int64_t bin_ent_cap, units_cap;

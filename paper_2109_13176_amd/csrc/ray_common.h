@@ -1,0 +1,204 @@
+// Device helpers shared by the ray passes (segmented and binned): point
+// transform and return, dominant axis, exact segment entry voxel and the
+// exact integer voxel walk (Sec. III-C of arXiv 2109.13176).
+#pragma once
+#include <math.h>
+
+#include "gvom_internal.h"
+
+namespace gvom {
+namespace {
+
+__device__ __forceinline__ int32_t wrap_add(int32_t s, int32_t n) { return s >= n ? s - n : s; }
+
+// Sums an int over the 64 lanes of the wave.
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ int32_t mod_pos(int32_t v, int32_t n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+__device__ __forceinline__ int dominant_axis(const int32_t n[3]) {
+  return (n[1] > n[0]) ? (n[2] > n[1] ? 2 : 1) : (n[2] > n[0] ? 2 : 0);
+}
+
+// Transform of point i (in firing order) and its return: q = Q16 world
+// coordinates; records the hit when the return lies in the window.  Returns
+// true when the ray can be traversed.
+struct PointFlags {
+  bool nonfinite = false, outrange = false, hit = false, dhit = false;
+};
+
+template <bool DISTINCT>
+__device__ __forceinline__ bool point_pass(const InsertArgs& a, const int i, int32_t q[3],
+                                           PointFlags& f) {
+  q[0] = q[1] = q[2] = 0;
+  if (i >= a.n) return false;
+  int pidx = i;
+  if (a.fw > 1) {
+    const int b = i / a.azimuths;
+    pidx = (i - b * a.azimuths) * a.fw + b;
+  }
+  const int32_t dims[3] = {a.d.nx, a.d.ny, a.d.nz};
+  const float p0 = a.xyz[3 * pidx + 0];
+  const float p1 = a.xyz[3 * pidx + 1];
+  const float p2 = a.xyz[3 * pidx + 2];
+  if (!(isfinite(p0) && isfinite(p1) && isfinite(p2))) {
+    f.nonfinite = true;
+    return false;
+  }
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    float w = __builtin_fmaf(a.R[3 * k + 0], p0, a.t[k]);
+    w = __builtin_fmaf(a.R[3 * k + 1], p1, w);
+    w = __builtin_fmaf(a.R[3 * k + 2], p2, w);
+    const float u = w * a.inv_r;
+    const bool okk = isfinite(w) && fabsf(u) < 32768.0f;
+    q[k] = okk ? (int32_t)floorf(u * 65536.0f) : 0;
+    ok = ok && okk;
+    const int64_t dd = (int64_t)q[k] - a.S[k];
+    ok = ok && dd < (1 << 27) && -dd < (1 << 27);
+  }
+  if (!ok) {
+    f.outrange = true;
+    return false;
+  }
+  int32_t l[3];
+  bool win = true;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    l[k] = (q[k] >> 16) - a.O[k];
+    win = win && l[k] >= 0 && l[k] < dims[k];
+  }
+  if (win) {  // the return
+    const int32_t ex = wrap_add(l[0] + a.d.ro[0], dims[0]);
+    const int32_t ey = wrap_add(l[1] + a.d.ro[1], dims[1]);
+    const int32_t ez = wrap_add(l[2] + a.d.ro[2], dims[2]);
+    const int32_t col = ex * dims[1] + ey;
+    const int32_t e = col_base(a.d, ex, ey) + (ez << 4);
+    atomicAdd(&a.hits[e], 1);
+    // min and or only move one way: a plain read that already satisfies
+    // the update makes the atomic unnecessary
+    if (q[2] < a.minqz[e]) atomicMin(&a.minqz[e], q[2]);
+    unsigned long long* ow = &a.occ[(int64_t)col * a.d.W + (ez >> 6)];
+    const unsigned long long ob = 1ull << (ez & 63);
+    if (!(*ow & ob)) atomicOr(ow, ob);
+    f.hit = true;
+    if (DISTINCT) {
+      const uint32_t bit = 1u << (e & 31);
+      const uint32_t old = atomicOr(&a.touch[(uint32_t)e >> 5], bit);
+      f.dhit = !(old & bit);
+    }
+  }
+  return true;
+}
+
+// floor(x / d) for d > 0 (|x| < 2^60): double estimate, exact integer fix-up.
+__device__ __forceinline__ int64_t floor_div_pos(int64_t x, int64_t d, bool* exact) {
+  int64_t q = (int64_t)floor((double)x / (double)d);
+  int64_t r = x - q * d;
+  while (r < 0) { q--; r += d; }
+  while (r >= d) { q++; r -= d; }
+  *exact = r == 0;
+  return q;
+}
+
+// Voxel at which the ray S -> q enters world cell c along axis dm (c is not
+// the sensor's cell): see the traversal pass below for the tie rule.
+__device__ __forceinline__ void entry_voxel(const int32_t S[3], const int32_t sg[3],
+                                            const int32_t ad[3], const int dm, const int32_t c,
+                                            int32_t v[3]) {
+  const int64_t num = sg[dm] > 0 ? ((int64_t)c << 16) - S[dm] : (int64_t)S[dm] - (((int64_t)c + 1) << 16);
+  const int64_t den = (int64_t)ad[dm] << 16;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    if (k == dm) {
+      v[k] = c;
+      continue;
+    }
+    bool exact;
+    const int64_t x = (int64_t)S[k] * ad[dm] + num * (sg[k] * (int64_t)ad[k]);
+    int64_t vb = floor_div_pos(x, den, &exact);
+    if (exact && sg[dm] < 0 && sg[k] < 0) vb -= 1;
+    v[k] = (int32_t)vb;
+  }
+}
+
+// Exact traversal state of one segment: remaining steps to the end voxel and
+// to the window edge per axis, and the crossing-time differences.
+//
+// E_ab = num_a |D_b| - num_b |D_a| (num = distance from the sensor to the
+// next boundary along the axis, Q units) decides which axis crosses first.
+// It only changes by multiples of 2^16 (|D| << 16 per step), so its low 16
+// bits are fixed and f = floor(E / 2^16) carries the rest: E >= 0 iff
+// f >= 0, and E <= 0 iff f <= c with c = -1 when the low bits are not zero,
+// else 0.  While both axes still move, the next crossings lie within one
+// cell of the current point, so |E| <= 2^16 max(|D_a|, |D_b|) < 2^43 and f
+// fits in 32 bits (|D| < 2^27); f of a finished axis is never consulted.
+struct Walk {
+  int32_t rem[3], room[3], sg[3], ad[3];
+  int32_t fxy, fxz, fyz;
+  int32_t cxy, cxz, cyz;
+};
+
+__device__ __forceinline__ void split_e(int64_t e, int32_t& f, int32_t& c) {
+  f = (int32_t)(e >> 16);
+  c = (e & 0xFFFF) ? -1 : 0;
+}
+
+// Starts the walk at world voxel v (inside the window, local l).
+__device__ __forceinline__ void walk_init(const InsertArgs& a, const int32_t q[3],
+                                          const int32_t v[3], const int32_t l[3], Walk& w) {
+  const int32_t dims[3] = {a.d.nx, a.d.ny, a.d.nz};
+  int64_t num[3];
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    const int32_t ev = q[k] >> 16;
+    const int32_t dq = q[k] - a.S[k];
+    w.sg[k] = dq > 0 ? 1 : (dq < 0 ? -1 : 0);
+    w.ad[k] = dq < 0 ? -dq : dq;
+    w.rem[k] = ev > v[k] ? ev - v[k] : v[k] - ev;
+    w.room[k] = w.sg[k] > 0 ? dims[k] - 1 - l[k] : l[k];
+    num[k] = w.sg[k] > 0 ? (((int64_t)v[k] + 1) << 16) - a.S[k] : (int64_t)a.S[k] - ((int64_t)v[k] << 16);
+  }
+  split_e(num[0] * w.ad[1] - num[1] * w.ad[0], w.fxy, w.cxy);
+  split_e(num[0] * w.ad[2] - num[2] * w.ad[0], w.fxz, w.cxz);
+  split_e(num[1] * w.ad[2] - num[2] * w.ad[1], w.fyz, w.cyz);
+}
+
+// One step: the axes with the smallest crossing time move; when several
+// share it, the axes moving up step first (the shared boundary belongs to
+// the upper cell) and the axes moving down in the next step.  Sets mx/my/mz
+// and returns whether a moving axis left the window.
+__device__ __forceinline__ bool walk_step(Walk& w, bool& mx, bool& my, bool& mz) {
+  const bool ax = w.rem[0] > 0, ay = w.rem[1] > 0, az = w.rem[2] > 0;
+  const bool px = w.sg[0] > 0, py = w.sg[1] > 0, pz = w.sg[2] > 0;
+  mx = ax & (!ay | (w.fxy <= w.cxy)) & (!az | (w.fxz <= w.cxz));
+  my = ay & (!ax | (w.fxy >= 0)) & (!az | (w.fyz <= w.cyz));
+  mz = az & (!ax | (w.fxz >= 0)) & (!ay | (w.fyz >= 0));
+  const bool up = (mx & px) | (my & py) | (mz & pz);
+  mx = mx & (!up | px);
+  my = my & (!up | py);
+  mz = mz & (!up | pz);
+  const bool out = (mx & (w.room[0] == 0)) | (my & (w.room[1] == 0)) | (mz & (w.room[2] == 0));
+  w.rem[0] -= mx;
+  w.rem[1] -= my;
+  w.rem[2] -= mz;
+  w.room[0] -= mx;
+  w.room[1] -= my;
+  w.room[2] -= mz;
+  // wrapping unsigned adds: f of an axis that no longer moves may drift
+  w.fxy = (int32_t)((uint32_t)w.fxy + (mx ? (uint32_t)w.ad[1] : 0u) - (my ? (uint32_t)w.ad[0] : 0u));
+  w.fxz = (int32_t)((uint32_t)w.fxz + (mx ? (uint32_t)w.ad[2] : 0u) - (mz ? (uint32_t)w.ad[0] : 0u));
+  w.fyz = (int32_t)((uint32_t)w.fyz + (my ? (uint32_t)w.ad[2] : 0u) - (mz ? (uint32_t)w.ad[1] : 0u));
+  return out;
+}
+
+}  // namespace
+}  // namespace gvom

@@ -54,7 +54,7 @@ class map_tuning_t(ctypes.Structure):
 class map_stats_t(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("n_points", "n_nonfinite", "n_range", "n_hits", "n_pass",
-                 "n_distinct_pass", "n_distinct_hit", "n_cleared")]
+                 "n_distinct_pass", "n_distinct_hit", "n_cleared", "n_pass_updates")]
 
 
 EXPORTED = [

@@ -83,6 +83,7 @@ def test_batch_equals_single_maps(graph):
                 for k in a[3]:
                     assert (a[3][k].view(np.uint8) == b[3][k].view(np.uint8)).all(), (s, i, k)
                 sa, sb = bmaps[i].stats(), smaps[i].stats()
+                sa.pop("n_pass_updates"), sb.pop("n_pass_updates")  # work-order dependent
                 assert sa == sb, (sa, sb)
     finally:
         batch.close()
