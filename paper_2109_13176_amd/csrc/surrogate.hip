@@ -436,13 +436,27 @@ __global__ __launch_bounds__(256) void k_bwd_weight(const float* __restrict__ dz
   }
 }
 
-// grad[o] = scale * sum over blocks of part[b][o] (fixed order: deterministic)
+// Two-stage fixed-order (deterministic) reduction of the weight-gradient
+// partials: stage 1 sums groups of kRedGroup consecutive tiles per parameter
+// (grid.y = group), stage 2 sums the groups and scales by 1 / count.
+constexpr int kRedGroup = 32;
+
 __global__ __launch_bounds__(256) void k_reduce_parts(const float* part, int nb, int64_t np,
-                                                      const double* scal, float* grad) {
+                                                      double* mid) {
+  const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (o >= np) return;
+  const int b0 = blockIdx.y * kRedGroup, b1 = min(nb, b0 + kRedGroup);
+  double s = 0.0;
+  for (int b = b0; b < b1; b++) s += part[(int64_t)b * np + o];
+  mid[(int64_t)blockIdx.y * np + o] = s;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_mid(const double* mid, int ng, int64_t np,
+                                                    const double* scal, float* grad) {
   const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (o >= np) return;
   double s = 0.0;
-  for (int b = 0; b < nb; b++) s += part[(int64_t)b * np + o];
+  for (int g = 0; g < ng; g++) s += mid[(int64_t)g * np + o];
   grad[o] = (float)(s * scal[1]);
 }
 
@@ -524,7 +538,8 @@ struct sgt_net_t {
   uint16_t* act[kNL];  // input of each layer (bf16)
   float* out;
   float *dz0, *dz1;    // fp32 gradient images (up to 32 channels)
-  float* part;         // weight-gradient partials
+  float* part;         // weight-gradient partials, one per 16 x 16 tile
+  double* mid;         // partials summed over groups of kRedGroup tiles
   int part_blocks;
   double* lpart;
   double* scal;
@@ -616,6 +631,7 @@ int32_t sgt_create(int32_t H, int32_t W, uint64_t seed, void* stream, sgt_net_t*
   al((void**)&n->dz0, P * 32 * 4);
   al((void**)&n->dz1, P * 32 * 4);
   al((void**)&n->part, (size_t)n->part_blocks * maxlp * 4);
+  al((void**)&n->mid, (size_t)((n->part_blocks + kRedGroup - 1) / kRedGroup) * maxlp * 8);
   al((void**)&n->lpart, (size_t)4096 * 2 * 8);
   al((void**)&n->scal, 16);
   al((void**)&n->mean, kFeat * 4);
@@ -653,8 +669,8 @@ int32_t sgt_create(int32_t H, int32_t W, uint64_t seed, void* stream, sgt_net_t*
 int32_t sgt_destroy(sgt_net_t* n) {
   if (!n) return MAP_OK;
   (void)hipStreamSynchronize(n->stream);
-  void* ps[] = {n->master, n->m, n->v, n->grad, n->out, n->dz0, n->dz1, n->part, n->lpart,
-                n->scal, n->mean, n->stdv};
+  void* ps[] = {n->master, n->m, n->v, n->grad, n->out, n->dz0, n->dz1, n->part, n->mid,
+                n->lpart, n->scal, n->mean, n->stdv};
   for (void* p : ps) (void)hipFree(p);
   for (int l = 0; l < kNL; l++) {
     (void)hipFree(n->wbf[l]);
@@ -782,8 +798,11 @@ int32_t sgt_loss_grad(sgt_net_t* n, const float* feat_dev, const float* label_de
       hipLaunchKernelGGL((k_bwd_weight<16, 32>), g16, dim3(256), 0, n->stream, dz, n->act[l], n->part, H, W);
     else
       hipLaunchKernelGGL((k_bwd_weight<32, 32>), g16, dim3(256), 0, n->stream, dz, n->act[l], n->part, H, W);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for(lp)), dim3(256), 0, n->stream, n->part,
-                       n->part_blocks, lp, n->scal, n->grad + n->off[l]);
+    const int ng = (n->part_blocks + kRedGroup - 1) / kRedGroup;
+    hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for(lp), ng), dim3(256), 0, n->stream, n->part,
+                       n->part_blocks, lp, n->mid);
+    hipLaunchKernelGGL(k_reduce_mid, dim3(blocks_for(lp)), dim3(256), 0, n->stream, n->mid, ng, lp,
+                       n->scal, n->grad + n->off[l]);
     if (l == 0) break;
     if (l == 4)
       hipLaunchKernelGGL((k_bwd_data<32, 2>), g16, dim3(256), 0, n->stream, dz, n->wbf[l], n->act[l], dp, H, W);
