@@ -186,49 +186,70 @@ __global__ __launch_bounds__(256) void k_normalize(const float* feat, int64_t n,
 }
 
 // ------------------------------------------------------------ forward conv
-// Hidden layers on matrix cores: out[co][pixel] = W[co][k] x patch[k][pixel]
-// with k = (tap, ci), v_mfma_f32_16x16x16 bf16 tiles (fp32 accumulation).
-// Block = 4 rows x 64 pixels (one wave per row), input tile with a one-pixel
-// halo and the layer's weights staged in LDS.  Operand lanes: A row = lane%16
-// (output channel), B column = lane%16 (pixel), both with k = 4*(lane/16)+e;
-// result lane holds column lane%16, rows 4*(lane/16)+e.
-constexpr int kTR = 4, kTC = 64;
+// Convolutions on matrix cores: out[co][pixel] = W[co][k] x patch[k][pixel]
+// with k = (tap, ci), fp32 accumulation.  Block = TR rows x 64 pixels (one
+// wave per row), input tile with a one-pixel halo and the layer's weights
+// staged in LDS with a padded pixel / weight-row stride (kPad bf16), which
+// spreads a wave's 8- and 16-byte reads over distinct banks.  Operand lanes:
+// A row = lane % 16 (output channel), B column = lane % 16 (pixel), both
+// with k = KL * (lane / 16) + e; result lane holds column lane % 16, rows
+// 4 * (lane / 16) + e.
+//   CIN = 16: v_mfma_f32_16x16x16_bf16 (KL = 4), one instruction per tap;
+//   CIN = 32: v_mfma_f32_16x16x32_bf16 (KL = 8), one instruction per tap.
+constexpr int kTC = 64, kPad = 8;
 
-template <int CIN>
-__global__ __launch_bounds__(256) void k_conv_mfma(const uint16_t* __restrict__ x,
-                                                   const uint16_t* __restrict__ w,
-                                                   const float* __restrict__ bias,
-                                                   uint16_t* __restrict__ y, int H, int W) {
-  __shared__ __attribute__((aligned(16))) uint16_t sx[(kTR + 2) * (kTC + 2) * CIN];
-  __shared__ __attribute__((aligned(16))) uint16_t sw[32 * 9 * CIN];
-  const int r0 = blockIdx.y * kTR, c0 = blockIdx.x * kTC;
-  constexpr int Q = CIN / 4;  // 4-channel (8-byte) groups per pixel
-  for (int i = threadIdx.x; i < (kTR + 2) * (kTC + 2) * Q; i += 256) {
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+template <int CIN, int TR>
+__global__ __launch_bounds__(TR * 64) void k_conv_mfma(const uint16_t* __restrict__ x,
+                                                       const uint16_t* __restrict__ w,
+                                                       const float* __restrict__ bias,
+                                                       uint16_t* __restrict__ y, int H, int W) {
+  constexpr int PS = CIN + kPad;  // LDS stride of a pixel and of a weight row
+  constexpr int NT = TR * 64;
+  __shared__ __attribute__((aligned(16))) uint16_t sx[(TR + 2) * (kTC + 2) * PS];
+  __shared__ __attribute__((aligned(16))) uint16_t sw[32 * 9 * PS];
+  const int r0 = blockIdx.y * TR, c0 = blockIdx.x * kTC;
+  constexpr int Q = CIN / 8;  // 16-byte groups per pixel
+  for (int i = threadIdx.x; i < (TR + 2) * (kTC + 2) * Q; i += NT) {
     const int pix = i / Q, cq = i - pix * Q;
     const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
     const int gr = r0 + tr - 1, gc = c0 + tc - 1;
-    uint2 v = make_uint2(0u, 0u);
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
     if (gr >= 0 && gr < H && gc >= 0 && gc < W)
-      v = *(const uint2*)(x + ((int64_t)gr * W + gc) * CIN + cq * 4);
-    *(uint2*)(sx + pix * CIN + cq * 4) = v;
+      v = *(const uint4*)(x + ((int64_t)gr * W + gc) * CIN + cq * 8);
+    *(uint4*)(sx + pix * PS + cq * 8) = v;
   }
-  for (int i = threadIdx.x; i < 32 * 9 * Q; i += 256) *(uint2*)(sw + i * 4) = *(const uint2*)(w + i * 4);
+  for (int i = threadIdx.x; i < 32 * 9 * Q; i += NT) {
+    const int row = i / Q, cq = i - row * Q;
+    *(uint4*)(sw + row * PS + cq * 8) = *(const uint4*)(w + row * CIN + cq * 8);
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   v4f acc[2][4];
   for (int m = 0; m < 2; m++)
     for (int n = 0; n < 4; n++) acc[m][n] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
   for (int tap = 0; tap < 9; tap++) {
     const int dy = tap / 3, dx = tap - dy * 3;
-    for (int cb = 0; cb < CIN; cb += 16) {
-      const int ci = cb + 4 * lk;
-      const v4s a0 = *(const v4s*)(sw + ((lr)*9 + tap) * CIN + ci);
-      const v4s a1 = *(const v4s*)(sw + ((16 + lr) * 9 + tap) * CIN + ci);
+    if constexpr (CIN == 32) {
+      const v8bf a0 = *(const v8bf*)(sw + (lr * 9 + tap) * PS + 8 * lk);
+      const v8bf a1 = *(const v8bf*)(sw + ((16 + lr) * 9 + tap) * PS + 8 * lk);
 #pragma unroll
       for (int nt = 0; nt < 4; nt++) {
         const int pc = nt * 16 + lr;
-        const v4s b = *(const v4s*)(sx + ((wv + dy) * (kTC + 2) + pc + dx) * CIN + ci);
+        const v8bf b = *(const v8bf*)(sx + ((wv + dy) * (kTC + 2) + pc + dx) * PS + 8 * lk);
+        acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc[0][nt], 0, 0, 0);
+        acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc[1][nt], 0, 0, 0);
+      }
+    } else {
+      const v4s a0 = *(const v4s*)(sw + (lr * 9 + tap) * PS + 4 * lk);
+      const v4s a1 = *(const v4s*)(sw + ((16 + lr) * 9 + tap) * PS + 4 * lk);
+#pragma unroll
+      for (int nt = 0; nt < 4; nt++) {
+        const int pc = nt * 16 + lr;
+        const v4s b = *(const v4s*)(sx + ((wv + dy) * (kTC + 2) + pc + dx) * PS + 4 * lk);
         acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b, acc[0][nt], 0, 0, 0);
         acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b, acc[1][nt], 0, 0, 0);
       }
@@ -572,12 +593,12 @@ hipError_t forward_all(sgt_net_t* n, const float* feat) {
   const int64_t P = (int64_t)H * W;
   hipLaunchKernelGGL(k_normalize, dim3(blocks_for(P * kFeat) < 65536 ? blocks_for(P * kFeat) : 65536),
                      dim3(256), 0, n->stream, feat, P * kFeat, n->mean, n->stdv, n->act[0]);
-  dim3 g((W + kTC - 1) / kTC, (H + kTR - 1) / kTR);
-  hipLaunchKernelGGL(k_conv_mfma<16>, g, dim3(256), 0, n->stream, n->act[0], n->wbf[0], n->bias[0],
-                     n->act[1], H, W);
+  dim3 g4((W + kTC - 1) / kTC, (H + 3) / 4), g8((W + kTC - 1) / kTC, (H + 7) / 8);
+  hipLaunchKernelGGL((k_conv_mfma<16, 4>), g4, dim3(256), 0, n->stream, n->act[0], n->wbf[0],
+                     n->bias[0], n->act[1], H, W);
   for (int l = 1; l < 4; l++)
-    hipLaunchKernelGGL(k_conv_mfma<32>, g, dim3(256), 0, n->stream, n->act[l], n->wbf[l], n->bias[l],
-                       n->act[l + 1], H, W);
+    hipLaunchKernelGGL((k_conv_mfma<32, 8>), g8, dim3(512), 0, n->stream, n->act[l], n->wbf[l],
+                       n->bias[l], n->act[l + 1], H, W);
   hipLaunchKernelGGL(k_conv_out, dim3(blocks_for(P)), dim3(256), 0, n->stream, n->act[4], n->wbf[4],
                      n->bias[4], n->out, H, W);
   return hipGetLastError();
