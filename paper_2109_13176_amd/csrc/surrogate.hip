@@ -176,15 +176,6 @@ __global__ __launch_bounds__(256) void k_feat_sums(const float* feat, int64_t P,
   }
 }
 
-// Normalised network input: bf16((float)((f - mean) / std)).
-__global__ __launch_bounds__(256) void k_normalize(const float* feat, int64_t n, const float* mean,
-                                                   const float* stdv, uint16_t* x) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const int k = (int)(i % kFeat);
-    x[i] = to_bf16((float)(((double)feat[i] - (double)mean[k]) / (double)stdv[k]));
-  }
-}
-
 // ------------------------------------------------------------ forward conv
 // Convolutions on matrix cores: out[co][pixel] = W[co][k] x patch[k][pixel]
 // with k = (tap, ci), fp32 accumulation.  Block = TR rows x 64 pixels (one
@@ -200,24 +191,48 @@ constexpr int kTC = 64, kPad = 8;
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-template <int CIN, int TR>
-__global__ __launch_bounds__(TR * 64) void k_conv_mfma(const uint16_t* __restrict__ x,
+// NORM (first layer): x holds the raw fp32 features; each is normalised as
+// bf16((float)((f - mean) / std)) (double arithmetic) while staged, and the
+// block's own pixels are also written to xn, the layer input the backward
+// pass reads.
+template <int CIN, int TR, bool NORM>
+__global__ __launch_bounds__(TR * 64) void k_conv_mfma(const void* __restrict__ xin,
                                                        const uint16_t* __restrict__ w,
                                                        const float* __restrict__ bias,
-                                                       uint16_t* __restrict__ y, int H, int W) {
+                                                       uint16_t* __restrict__ y, int H, int W,
+                                                       const float* __restrict__ mean,
+                                                       const float* __restrict__ stdv,
+                                                       uint16_t* __restrict__ xn) {
   constexpr int PS = CIN + kPad;  // LDS stride of a pixel and of a weight row
   constexpr int NT = TR * 64;
   __shared__ __attribute__((aligned(16))) uint16_t sx[(TR + 2) * (kTC + 2) * PS];
   __shared__ __attribute__((aligned(16))) uint16_t sw[32 * 9 * PS];
   const int r0 = blockIdx.y * TR, c0 = blockIdx.x * kTC;
-  constexpr int Q = CIN / 8;  // 16-byte groups per pixel
+  constexpr int Q = CIN / 8;  // 8-channel groups per pixel
   for (int i = threadIdx.x; i < (TR + 2) * (kTC + 2) * Q; i += NT) {
     const int pix = i / Q, cq = i - pix * Q;
     const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
     const int gr = r0 + tr - 1, gc = c0 + tc - 1;
     uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (gr >= 0 && gr < H && gc >= 0 && gc < W)
-      v = *(const uint4*)(x + ((int64_t)gr * W + gc) * CIN + cq * 8);
+    if (gr >= 0 && gr < H && gc >= 0 && gc < W) {
+      const int64_t e = ((int64_t)gr * W + gc) * CIN + cq * 8;
+      if constexpr (NORM) {
+        const float* f = (const float*)xin + e;
+        uint16_t b[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+          const int ch = cq * 8 + k;
+          b[k] = to_bf16((float)(((double)f[k] - (double)mean[ch]) / (double)stdv[ch]));
+        }
+        v.x = (uint32_t)b[0] | ((uint32_t)b[1] << 16);
+        v.y = (uint32_t)b[2] | ((uint32_t)b[3] << 16);
+        v.z = (uint32_t)b[4] | ((uint32_t)b[5] << 16);
+        v.w = (uint32_t)b[6] | ((uint32_t)b[7] << 16);
+        if (tr >= 1 && tr <= TR && tc >= 1 && tc <= kTC) *(uint4*)(xn + e) = v;
+      } else {
+        v = *(const uint4*)((const uint16_t*)xin + e);
+      }
+    }
     *(uint4*)(sx + pix * PS + cq * 8) = v;
   }
   for (int i = threadIdx.x; i < 32 * 9 * Q; i += NT) {
@@ -277,31 +292,47 @@ __global__ __launch_bounds__(TR * 64) void k_conv_mfma(const uint16_t* __restric
     }
 }
 
-// Output layer (32 -> 2, no ReLU): fp32 accumulation of bf16 products.
-__global__ __launch_bounds__(256) void k_conv_out(const uint16_t* __restrict__ x,
+// Output layer (32 -> 2, no ReLU): fp32 accumulation of bf16 products, tap
+// by tap and channel by channel.  Block = 8 rows x 64 pixels, one thread per
+// pixel, the input tile with its halo staged in LDS.
+__global__ __launch_bounds__(512) void k_conv_out(const uint16_t* __restrict__ x,
                                                   const uint16_t* __restrict__ w,
                                                   const float* __restrict__ bias,
                                                   float* __restrict__ out, int H, int W) {
+  constexpr int TR = 8, PS = 32 + kPad;
+  __shared__ __attribute__((aligned(16))) uint16_t sx[(TR + 2) * (kTC + 2) * PS];
   __shared__ float sw[2 * 9 * 32];
-  for (int i = threadIdx.x; i < 2 * 9 * 32; i += 256) sw[i] = from_bf16(w[i]);
+  const int r0 = blockIdx.y * TR, c0 = blockIdx.x * kTC;
+  for (int i = threadIdx.x; i < 2 * 9 * 32; i += 512) sw[i] = from_bf16(w[i]);
+  for (int i = threadIdx.x; i < (TR + 2) * (kTC + 2) * 4; i += 512) {
+    const int pix = i >> 2, cq = i & 3;
+    const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
+    const int gr = r0 + tr - 1, gc = c0 + tc - 1;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (gr >= 0 && gr < H && gc >= 0 && gc < W)
+      v = *(const uint4*)(x + ((int64_t)gr * W + gc) * 32 + cq * 8);
+    *(uint4*)(sx + pix * PS + cq * 8) = v;
+  }
   __syncthreads();
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= (int64_t)H * W) return;
-  const int r = (int)(p / W), c = (int)(p - (int64_t)r * W);
+  const int tr = threadIdx.x >> 6, tc = threadIdx.x & 63;
+  const int r = r0 + tr, c = c0 + tc;
+  if (r >= H || c >= W) return;
   float s0 = bias[0], s1 = bias[1];
   for (int tap = 0; tap < 9; tap++) {
     const int rr = r + tap / 3 - 1, cc = c + tap % 3 - 1;
     if (rr < 0 || rr >= H || cc < 0 || cc >= W) continue;
-    const uint16_t* xp = x + ((int64_t)rr * W + cc) * 32;
+    const uint16_t* xp = sx + ((tr + tap / 3) * (kTC + 2) + tc + tap % 3) * PS;
+#pragma unroll
     for (int ci = 0; ci < 32; ci++) {
       const float v = from_bf16(xp[ci]);
       s0 = __builtin_fmaf(sw[(0 * 9 + tap) * 32 + ci], v, s0);
       s1 = __builtin_fmaf(sw[(1 * 9 + tap) * 32 + ci], v, s1);
     }
   }
-  out[p * 2] = s0;
-  out[p * 2 + 1] = s1;
+  out[((int64_t)r * W + c) * 2] = s0;
+  out[((int64_t)r * W + c) * 2 + 1] = s1;
 }
+
 
 // ------------------------------------------------------------------ loss
 // dz = sign(pred - label) on defined label entries (the 1/count scale is
@@ -590,17 +621,15 @@ int32_t st_of(hipError_t e) {
 
 hipError_t forward_all(sgt_net_t* n, const float* feat) {
   const int H = n->H, W = n->W;
-  const int64_t P = (int64_t)H * W;
-  hipLaunchKernelGGL(k_normalize, dim3(blocks_for(P * kFeat) < 65536 ? blocks_for(P * kFeat) : 65536),
-                     dim3(256), 0, n->stream, feat, P * kFeat, n->mean, n->stdv, n->act[0]);
   dim3 g4((W + kTC - 1) / kTC, (H + 3) / 4), g8((W + kTC - 1) / kTC, (H + 7) / 8);
-  hipLaunchKernelGGL((k_conv_mfma<16, 4>), g4, dim3(256), 0, n->stream, n->act[0], n->wbf[0],
-                     n->bias[0], n->act[1], H, W);
+  hipLaunchKernelGGL((k_conv_mfma<16, 4, true>), g4, dim3(256), 0, n->stream, (const void*)feat,
+                     n->wbf[0], n->bias[0], n->act[1], H, W, n->mean, n->stdv, n->act[0]);
   for (int l = 1; l < 4; l++)
-    hipLaunchKernelGGL((k_conv_mfma<32, 8>), g8, dim3(512), 0, n->stream, n->act[l], n->wbf[l],
-                       n->bias[l], n->act[l + 1], H, W);
-  hipLaunchKernelGGL(k_conv_out, dim3(blocks_for(P)), dim3(256), 0, n->stream, n->act[4], n->wbf[4],
-                     n->bias[4], n->out, H, W);
+    hipLaunchKernelGGL((k_conv_mfma<32, 8, false>), g8, dim3(512), 0, n->stream,
+                       (const void*)n->act[l], n->wbf[l], n->bias[l], n->act[l + 1], H, W,
+                       (const float*)nullptr, (const float*)nullptr, (uint16_t*)nullptr);
+  hipLaunchKernelGGL(k_conv_out, g8, dim3(512), 0, n->stream, n->act[4], n->wbf[4], n->bias[4],
+                     n->out, H, W);
   return hipGetLastError();
 }
 
