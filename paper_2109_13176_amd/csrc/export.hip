@@ -377,18 +377,22 @@ __global__ __launch_bounds__(1024) void k_lut_scan(int32_t* base, int nb, int64_
 
 // Pass 3: block = a storage region of 4 x 16 columns (four 4 x 4 bricks,
 // contiguous in memory).  The passes of the region are read in storage order
-// into LDS, then every column's table entries are written in window-local z
-// order (a transpose through LDS keeps both sides coalesced).
+// into LDS rows in window-local z order, then every lane writes four
+// consecutive table entries of one column (a transpose through LDS keeps both
+// sides coalesced; one 16-byte LDS read and one 16-byte store per lane).
 constexpr int kRegCols = 64;
+
+// LDS row stride of a column's passes: a multiple of 4 words.
+__host__ __device__ __forceinline__ int lut_row(int nz) { return ((nz + 3) & ~3) + 4; }
 
 __device__ __forceinline__ void lut_write_body(const LutArgs& a, const uint32_t nz_magic,
                                                const int bxr, const int byr) {
-  extern __shared__ int32_t lpass[];  // [64][nz + 1]
+  extern __shared__ __attribute__((aligned(16))) int32_t lpass[];  // [64][lut_row(nz)]
   __shared__ unsigned long long slo[kRegCols], shi[kRegCols];
   __shared__ int32_t sbase[kRegCols];
   __shared__ int64_t scb[kRegCols], slut[kRegCols];
   const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, W = a.d.W, roz = a.d.ro[2];
-  const int nzp = nz + 1;
+  const int nzp = lut_row(nz);
   if (threadIdx.x < kRegCols) {
     const int t = threadIdx.x;
     const int ix = t >> 4, jy = t & 15;
@@ -420,34 +424,51 @@ __device__ __forceinline__ void lut_write_body(const LutArgs& a, const uint32_t 
   for (int k = threadIdx.x; k < total; k += kBlock) {
     const int bz = k >> 4, l16 = k & 15;
     const int b = nz == 1 ? bz : (int)__umulhi((uint32_t)bz, nz_magic);
-    const int z = bz - b * nz;
+    const int zs = bz - b * nz;
+    const int lz = zs >= roz ? zs - roz : zs - roz + nz;
     const int slot = (l16 & 3) * 16 + 4 * b + (l16 >> 2);
-    lpass[slot * nzp + z] = passes[r0 + k];
+    lpass[slot * nzp + lz] = passes[r0 + k];
   }
   __syncthreads();
-  const int lane = __lane_id(), wv = threadIdx.x >> 6;
-  for (int t = wv; t < kRegCols; t += kBlock / 64) {
-    if (scb[t] < 0) continue;
+  // items (column t, quad q): window-local z = 4q .. 4q+3; qs quads per column
+  // rounded up to a power of two so that t and q are shifts
+  const int nq = (nz + 3) >> 2;
+  const int qsh = nq > 1 ? 32 - __clz(nq - 1) : 0;
+  const bool vec = (nz & 3) == 0 && ((uintptr_t)a.lut & 15) == 0;
+  for (int i = threadIdx.x; i < (kRegCols << qsh); i += kBlock) {
+    const int t = i >> qsh, q = i & ((1 << qsh) - 1);
+    if (q >= nq || scb[t] < 0) continue;
     const Mask128 m = {slo[t], shi[t]};
-    int32_t* __restrict__ lut = a.lut + slut[t];
-    for (int z = lane; z < nz; z += 64) {
-      const int zs = wrap_add(z + roz, nz);
-      int32_t v;
-      if (test_bit(m, z)) {
-        const int32_t rank = sbase[t] + rank_below(m, z);
-        v = rank;
+    const int z0 = 4 * q;
+    const int4 pv = *(const int4*)(lpass + t * nzp + z0);
+    const int32_t p4[4] = {pv.x, pv.y, pv.z, pv.w};
+    int32_t rank = sbase[t] + rank_below(m, z0);
+    int32_t v[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int z = z0 + e;
+      if (z < nz && test_bit(m, z)) {
+        v[e] = rank;
         if (rank < a.cap) {
-          const int64_t e = scb[t] + ((int64_t)zs << 4);
+          const int64_t idx = scb[t] + ((int64_t)wrap_add(z + roz, nz) << 4);
           map_voxel_t d;
-          d.hits = a.hits[e];
-          d.passes = lpass[t * nzp + zs];
-          d.min_qz = a.minqz[e];
+          d.hits = a.hits[idx];
+          d.passes = p4[e];
+          d.min_qz = a.minqz[idx];
           a.data[rank] = d;
         }
+        rank++;
       } else {
-        v = -1 - lpass[t * nzp + zs];
+        v[e] = -1 - p4[e];
       }
-      lut[z] = v;
+    }
+    int32_t* __restrict__ lut = a.lut + slut[t] + z0;
+    if (vec) {
+      *(int4*)lut = make_int4(v[0], v[1], v[2], v[3]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        if (z0 + e < nz) lut[e] = v[e];
     }
   }
 }
@@ -625,7 +646,7 @@ size_t surface_lds(int H) {
   return (size_t)((T * T + 1) & ~1) * 4 + 2 * (size_t)T * MW * 8 + 2 * (size_t)T * kTile;
 }
 
-size_t lut_lds(int nz) { return (size_t)kRegCols * (nz + 1) * 4; }
+size_t lut_lds(int nz) { return (size_t)kRegCols * lut_row(nz) * 4; }
 
 uint32_t nz_magic(int nz) {
   return nz > 1 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)nz - 1) / (uint64_t)nz) : 0u;
@@ -656,7 +677,7 @@ hipError_t launch_lut(const LutArgs& a, hipStream_t s) {
   // b / nz == umulhi(b, ceil(2^32 / nz)) for every b < 2^20 (here b < 4 * 128)
   const uint32_t magic =
       a.d.nz > 1 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)a.d.nz - 1) / (uint64_t)a.d.nz) : 0u;
-  const size_t lds = (size_t)kRegCols * (a.d.nz + 1) * 4;
+  const size_t lds = lut_lds(a.d.nz);
   hipLaunchKernelGGL(k_lut_count, dim3((C + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_lut_scan, dim3(1), dim3(1024), 0, s, a.block_base, ng, a.n_occupied);
   dim3 g((a.d.nx + 3) / 4, (a.d.nby + 3) / 4);
