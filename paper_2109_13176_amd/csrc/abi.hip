@@ -863,7 +863,7 @@ int32_t map_batch_create(map_t* const* maps, int32_t k, void* stream, map_batch_
     lut = s2 > lut ? s2 : lut;
   }
   const int cu = b->n_cu;
-  b->grid = gvom::BatchGrid{cu * 4, cu * 2, cu * 8, cu * 4, cu * 2, cu * 4, cu * 4, surf, lut};
+  b->grid = gvom::BatchGrid{cu * 4, cu * 8, cu * 8, cu * 4, cu * 2, cu * 4, cu * 4, surf, lut};
   hipError_t e = hipMalloc((void**)&b->dtab, sizeof(gvom::BatchTables));
   if (e == hipSuccess) e = hipHostMalloc((void**)&b->htab, sizeof(gvom::BatchTables), 0);
   if (e == hipSuccess) e = hipMalloc((void**)&b->dstamps, (gvom::kMaxBatch + 1) * 8);

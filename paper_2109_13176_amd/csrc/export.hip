@@ -224,7 +224,7 @@ __device__ __forceinline__ void surface_body(const SurfaceArgs& a, const int H, 
   float slope = __uint_as_float(kQNaN), rough = __uint_as_float(kQNaN);
   if (hc != INT32_MIN) {
     int32_t n = 0, sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0;
-    int64_t sz = 0, sxz = 0, syz = 0;
+    int64_t sz = 0, sxz = 0, syz = 0, szz = 0;
     for (int dx = -h; dx <= h; dx++)
       for (int dy = -h; dy <= h; dy++) {
         const int32_t v = th[(tx + dx) * T + ty + dy];
@@ -239,6 +239,7 @@ __device__ __forceinline__ void surface_body(const SurfaceArgs& a, const int H, 
         sz += dz;
         sxz += dx * dz;
         syz += dy * dz;
+        szz += dz * dz;
       }
     // adjugate of M = [[sxx sxy sx] [sxy syy sy] [sx sy n]] (symmetric)
     const int64_t c00 = (int64_t)syy * n - (int64_t)sy * sy;
@@ -254,14 +255,10 @@ __device__ __forceinline__ void surface_body(const SurfaceArgs& a, const int H, 
       const double al = ((double)c00 * bx + (double)c01 * by + (double)c02 * bz) * inv;
       const double be = ((double)c01 * bx + (double)c11 * by + (double)c12 * bz) * inv;
       const double ga = ((double)c02 * bx + (double)c12 * by + (double)c22 * bz) * inv;
-      double ss = 0.0;
-      for (int dx = -h; dx <= h; dx++)
-        for (int dy = -h; dy <= h; dy++) {
-          const int32_t v = th[(tx + dx) * T + ty + dy];
-          if (v == INT32_MIN) continue;
-          const double e = (double)((int64_t)v - hc) - (al * dx + be * dy + ga);
-          ss += e * e;
-        }
+      // residual sum of squares of the least-squares plane: z.z - beta.(X^T z)
+      // (integer sums exact; |dz| < 2^23 Q units as nz <= 128, so the double
+      // cancellation error stays far below the roughness tolerance)
+      const double ss = fmax((double)szz - (al * bx + be * by + ga * bz), 0.0);
       slope = (float)(sqrt(al * al + be * be) / 65536.0);
       rough = (float)(ss / (double)n * a.q2m * a.q2m);
       fl |= 32;

@@ -85,7 +85,7 @@ struct InsertArgs {
   int32_t tb_blocks;           // grid of the binned traversal
 };
 
-constexpr int kRayBlock = 1024;   // threads per block of the ray pass
+constexpr int kRayBlock = 256;    // threads per block of the ray pass
 
 // Segments one ray can produce at most (segmented / binned traversal).
 int64_t max_segments(const Dims& d, int32_t seg_len);
