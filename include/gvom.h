@@ -212,10 +212,11 @@ int32_t map_get_tuning(const map_t* m, map_tuning_t* out);
  * MAP_PROF_SCROLL (window clears), MAP_PROF_RAYS (transform, returns and the
  * ray-segment list), MAP_PROF_TRACE (ray traversal), MAP_PROF_COLUMN (column
  * reduction), MAP_PROF_SURFACE (slope, roughness, negative obstacles),
- * MAP_PROF_LUT (lookup-table export).
- * map_profile_read synchronises, adds the elapsed milliseconds and launch
- * counts since the last read into ms[MAP_PROF_N] / count[MAP_PROF_N] (host),
- * and releases the events. */
+ * MAP_PROF_LUT (lookup-table export).  map_profile_enable takes a mask (bit p
+ * = phase p, 0 = off, MAP_PROF_ALL = every phase; each profiled phase costs
+ * two event records per call).  map_profile_read synchronises, adds the
+ * elapsed milliseconds and launch counts since the last read into
+ * ms[MAP_PROF_N] / count[MAP_PROF_N] (host), and releases the events. */
 #define MAP_PROF_SCROLL  0
 #define MAP_PROF_RAYS    1
 #define MAP_PROF_TRACE   2
@@ -223,7 +224,8 @@ int32_t map_get_tuning(const map_t* m, map_tuning_t* out);
 #define MAP_PROF_SURFACE 4
 #define MAP_PROF_LUT     5
 #define MAP_PROF_N       6
-int32_t map_profile_enable(map_t* m, int32_t enable);
+#define MAP_PROF_ALL     ((1 << MAP_PROF_N) - 1)
+int32_t map_profile_enable(map_t* m, int32_t phase_mask);
 int32_t map_profile_read(map_t* m, double ms[MAP_PROF_N], int64_t count[MAP_PROF_N]);
 
 /* ---- batched serving (project extension, not in the paper) ---------------

@@ -125,7 +125,7 @@ bool move_window(map_t* m, const int32_t o[3], gvom::ClearArgs* plan) {
 
 // Records the start event of a profiled phase (no-op when profiling is off).
 int prof_begin(map_t* m, int phase) {
-  if (!m->prof) return -1;
+  if (!((m->prof_mask >> phase) & 1)) return -1;
   map_t::Mark k{phase, nullptr, nullptr};
   if (hipEventCreate(&k.a) != hipSuccess || hipEventCreate(&k.b) != hipSuccess) return -1;
   (void)hipEventRecord(k.a, m->stream);
@@ -656,9 +656,9 @@ int32_t map_get_tuning(const map_t* m, map_tuning_t* out) {
   return MAP_OK;
 }
 
-int32_t map_profile_enable(map_t* m, int32_t enable) {
-  if (!m) return MAP_E_INVALID;
-  m->prof = enable != 0;
+int32_t map_profile_enable(map_t* m, int32_t phase_mask) {
+  if (!m || phase_mask < 0 || phase_mask > MAP_PROF_ALL) return MAP_E_INVALID;
+  m->prof_mask = phase_mask;
   return MAP_OK;
 }
 

@@ -43,7 +43,7 @@ struct map_t {
   int32_t sticky;
   int64_t last_points, last_cleared;
   bool last_distinct;
-  bool prof;
+  int32_t prof_mask;          // profiled phases (bit p = phase p)
   struct Mark {
     int phase;
     hipEvent_t a, b;

@@ -240,8 +240,13 @@ def map_get_tuning(h):
                "traversal": t.traversal}
 
 
-def map_profile_enable(h, enable: bool) -> int:
-    return lib().map_profile_enable(h, 1 if enable else 0)
+MAP_PROF_ALL = (1 << len(PROF_PHASES)) - 1
+
+
+def map_profile_enable(h, enable=True) -> int:
+    """enable: True (every phase), False, or a mask of phases (bit p = PROF_PHASES[p])."""
+    mask = MAP_PROF_ALL if enable is True else (0 if enable is False else int(enable))
+    return lib().map_profile_enable(h, mask)
 
 
 def map_profile_read(h):

@@ -284,3 +284,28 @@ def test_traversal_modes_bit_identical(distinct):
     finally:
         for m in maps:
             m.close()
+
+
+def test_profile_phase_mask():
+    """Only the phases in the mask are timed; results do not depend on it."""
+    from paper_2109_13176_amd import gvom
+    w = scenegen.single_scan_16beam(seed=7)
+    m = gvom.VoxelMap(w["params"])
+    try:
+        xyz = w["scans"][0].cuda()
+        trace = 1 << gvom.PROF_PHASES.index("trace")
+        assert gvom.map_profile_enable(m.h, trace) == 0
+        m.insert(xyz, w["poses"][0], gvom.MAP_RECENTER)
+        m.export_2d()
+        s, prof = gvom.map_profile_read(m.h)
+        assert s == 0 and prof["trace"][1] == 1 and prof["trace"][0] > 0
+        assert all(prof[p][1] == 0 for p in gvom.PROF_PHASES if p != "trace")
+        assert gvom.map_profile_enable(m.h, True) == 0
+        m.insert(xyz, w["poses"][0], 0)
+        m.export_2d()
+        m.export_voxels()
+        s, prof = gvom.map_profile_read(m.h)
+        assert all(prof[p][1] == 1 for p in ("rays", "trace", "column", "surface", "lut"))
+        assert gvom.map_profile_enable(m.h, 1 << 10) != 0
+    finally:
+        m.close()
