@@ -116,9 +116,11 @@ typedef struct {
   int64_t n_distinct_pass;  /* distinct voxels passed (-1 without MAP_STATS_DISTINCT) */
   int64_t n_distinct_hit;   /* distinct voxels hit   (-1 without MAP_STATS_DISTINCT) */
   int64_t n_cleared;        /* window voxels reset by the recentring              */
-  int64_t n_pass_updates;   /* global-memory pass updates the traversal issued
-                               (diagnostic: depends on the work order, so it is
-                               not reproducible from run to run)                  */
+  int64_t n_pass_updates;   /* global-memory pass updates the traversal issued,
+                               not counting the cells next to the sensor, which
+                               are summed on chip first (diagnostic: depends on
+                               the work order, so it is not reproducible from run
+                               to run)                                            */
 } map_stats_t;
 
 typedef struct map_t map_t;  /* opaque */
@@ -191,11 +193,13 @@ int32_t map_sync(map_t* m);
 /* Launch tuning (performance only: results are bit-identical for every
  * setting).  traversal: 2 = segmented (rays cut every seg_len dominant-axis
  * voxels, runs of equal voxels in neighbouring lanes merged, one global
- * atomic per run; default, and always used by batches), 1 = binned (rays
- * cut at 16-voxel storage slabs, passes counted per slab tile in LDS, then
- * added to the map; single-map inserts only, when the window has at most
- * 16,384 tiles and the scan at most 524,288 points, else segmented).  seg_len: dominant-axis voxels per ray
- * segment of the segmented traversal, 1..1024 (default 32);
+ * atomic per run; in single-map inserts the passes of a 17 x 17 x 9 box
+ * around the sensor are summed per block on chip first; default, and always
+ * used by batches), 1 = binned (rays cut at 16-voxel storage slabs, passes
+ * counted per slab tile in LDS, then added to the map; single-map inserts
+ * only, when the window has at most 16,384 tiles and the scan at most
+ * 524,288 points, else segmented).  seg_len: dominant-axis voxels per ray
+ * segment of the segmented traversal, 1..1024 (default 8);
  * trace_waves_per_cu: resident waves per compute unit requested for the
  * segmented traversal grid, 1..32 (default 32).  A field <= 0 keeps the
  * current value. */
@@ -262,7 +266,7 @@ int32_t map_batch_latency(const map_batch_t* b, double* ms);
 /* Graph replay on (default) or off (plain stream launches of the same kernels). */
 int32_t map_batch_set_graph(map_batch_t* b, int32_t enable);
 
-/* Autotuner: times every candidate tuning (seg_len 16/32/64 x
+/* Autotuner: times every candidate tuning (seg_len 8/16/32 x
  * trace_waves_per_cu 8/16/32) on this step's inputs with batch steps, applies
  * the fastest to all maps and appends it to the text cache `cache_path`
  * (NULL: no cache).  A cached entry for the same device, map shapes and

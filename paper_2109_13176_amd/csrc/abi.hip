@@ -201,10 +201,11 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
     delete m;
     return MAP_E_DEVICE;
   }
-  m->seg_len = 32;
+  m->seg_len = 8;
   m->trace_wpc = 32;
   m->traversal = 2;
-  m->part_trace_cap = (int64_t)m->n_cu * 32 / 4 + 1;
+  // traversal blocks (at most 32 waves per CU) + the sensor-box fold blocks
+  m->part_trace_cap = (int64_t)m->n_cu * 32 / 4 + gvom::box_fold_blocks() + 1;
   m->d.nx = p->nx;
   m->d.ny = p->ny;
   m->d.nz = p->nz;
@@ -227,6 +228,9 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   if (e == hipSuccess) e = dmalloc(&m->stats, kStatsBytes);
   if (e == hipSuccess) e = dmalloc(&m->err, 4);
   if (e == hipSuccess) e = dmalloc(&m->part_trace, m->part_trace_cap * 32);
+  if (e == hipSuccess) e = dmalloc(&m->box_rep, (int64_t)gvom::kBoxReps * gvom::kBoxCells * 4);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(m->box_rep, 0, (size_t)gvom::kBoxReps * gvom::kBoxCells * 4, m->stream);
   m->gx = (p->nx + gvom::kBinT - 1) / gvom::kBinT;
   m->gy = (p->ny + gvom::kBinT - 1) / gvom::kBinT;
   m->nbins = 4 * m->gx * m->gy + 1;
@@ -274,6 +278,7 @@ int32_t map_destroy(map_t* m) {
   (void)hipFree(m->uctl);
   (void)hipFree(m->bin_ent);
   (void)hipFree(m->units);
+  (void)hipFree(m->box_rep);
   delete m;
   return MAP_OK;
 }
@@ -293,6 +298,9 @@ int32_t map_reset(map_t* m) {
   if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, kStatsBytes, m->stream);
   if (e == hipSuccess && m->bin_cnt)
     e = hipMemsetAsync(m->bin_cnt, 0, (size_t)m->nbins * 4, m->stream);
+  // an insert that failed between the traversal and the fold leaves counts
+  if (e == hipSuccess)
+    e = hipMemsetAsync(m->box_rep, 0, (size_t)gvom::kBoxReps * gvom::kBoxCells * 4, m->stream);
   return dev_status(m, e);
 }
 
@@ -342,15 +350,17 @@ bool grow(map_t* m, T** p, int64_t* cap, int64_t need, size_t elem) {
 
 // Second half of an insert (after check_insert): grows the per-scan buffers,
 // moves the window (the slab clears go to `plan`; *full = whole window), and
-// fills the kernel arguments.  Updates the host-side map state.
+// fills the kernel arguments.  Updates the host-side map state.  `single`:
+// a single-map insert (binned traversal allowed, sensor box folded); the
+// batched step traverses without either.
 int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* pose,
                        uint32_t flags, const int32_t S[3], gvom::InsertArgs* a,
-                       gvom::ClearArgs* plan, bool* full, bool allow_binned) {
+                       gvom::ClearArgs* plan, bool* full, bool single) {
   // ray block b writes its segments into the region of stripe b mod kStripes,
   // sized for the most segments that stripe's points can produce
   const int64_t bin_blocks = (n + gvom::kRayBinBlock - 1) / gvom::kRayBinBlock;
   const bool binned =
-      allow_binned && m->traversal == 1 && m->bin_cnt && bin_blocks <= gvom::kMaxEnt;
+      single && m->traversal == 1 && m->bin_cnt && bin_blocks <= gvom::kMaxEnt;
   const int64_t rb = binned ? gvom::kRayBinBlock : gvom::kRayBlock;  // threads per ray block
   const int64_t ray_blocks = (n + rb - 1) / rb;
   const int64_t per_ray =
@@ -413,8 +423,10 @@ int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* p
   a->part_trace = m->part_trace;
   a->item_cap = m->item_cap;
   a->seg_len = m->seg_len;
-  const int64_t want = (need + 255) / 256;
-  const int64_t lim = (int64_t)m->n_cu * m->trace_wpc / 4;
+  const int64_t tpb = single ? gvom::kTraceBlock : 256;  // threads per traversal block
+  const int64_t want = (need + tpb - 1) / tpb;
+  int64_t lim = (int64_t)m->n_cu * m->trace_wpc / (tpb / 64);
+  if (lim < 1) lim = 1;
   a->trace_blocks = n > 0 ? (int32_t)(want < lim ? want : lim) : 0;
   a->binned = binned ? 1 : 0;
   a->gx = m->gx;
@@ -432,7 +444,22 @@ int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* p
   int64_t tb = (int64_t)m->n_cu * per_cu;
   if (tb > m->part_trace_cap) tb = m->part_trace_cap;
   a->tb_blocks = (int32_t)tb;
-  m->last_trace_blocks = binned ? a->tb_blocks : a->trace_blocks;
+  // sensor box of the segmented traversal: the box of kBoxXY x kBoxXY x kBoxZ
+  // window cells centred on the sensor's voxel, moved inside the window
+  const int32_t ext[3] = {gvom::kBoxXY, gvom::kBoxXY, gvom::kBoxZ};
+  const int32_t dims[3] = {m->d.nx, m->d.ny, m->d.nz};
+  for (int k = 0; k < 3; k++) {
+    const int32_t e = ext[k] < dims[k] ? ext[k] : dims[k];
+    int64_t lo = (int64_t)(S[k] >> 16) - m->origin[k] - ext[k] / 2;
+    if (lo > dims[k] - e) lo = dims[k] - e;
+    if (lo < 0) lo = 0;
+    a->box_e[k] = e;
+    a->box_l[k] = (int32_t)lo;
+    a->box_s[k] = (int32_t)((lo + m->d.ro[k]) % dims[k]);
+  }
+  a->box_rep = single ? m->box_rep : nullptr;
+  m->last_trace_blocks =
+      binned ? a->tb_blocks : a->trace_blocks + (single ? gvom::box_fold_blocks() : 0);
   if (n <= 0) m->last_trace_blocks = 0;
   return MAP_OK;
 }
@@ -961,7 +988,7 @@ int32_t map_batch_autotune(map_batch_t* b, const float* const* xyz_dev, const in
     }
   }
   if (!cached) {
-    const int segs[3] = {16, 32, 64}, wpcs[3] = {8, 16, 32};
+    const int segs[3] = {8, 16, 32}, wpcs[3] = {8, 16, 32};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MAP_E_DEVICE;
     float best_ms = 1e30f;

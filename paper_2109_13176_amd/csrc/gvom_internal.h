@@ -34,6 +34,7 @@ __host__ __device__ __forceinline__ int32_t col_base(const Dims& d, int32_t sx, 
 }
 
 constexpr int kStripes = 16;  // independent segment counters of the ray pass
+static_assert((kStripes & (kStripes - 1)) == 0, "the traversal binary-searches the stripes");
 
 // Binned traversal: slab / tile edge along x and y (storage cells), storage
 // rows of a bin's LDS region along the cross axis, segments per work unit,
@@ -48,6 +49,17 @@ constexpr int kMaxBins = 16385;
 constexpr int kMaxEnt = 512;
 constexpr int kTraceBinThreads = 512;
 constexpr int kRayBinBlock = 512;  // threads per block of the binned ray pass
+
+// Sensor box of the segmented traversal: every ray starts in the sensor's
+// voxel, so the cells around it take the passes of thousands of waves and
+// device atomics on their few cache lines serialize.  Passes of cells inside a
+// kBoxXY x kBoxXY x kBoxZ box around the sensor are summed per block in LDS,
+// flushed into one of kBoxReps replicas of the box, and the replicas are
+// added into the map by a small fold kernel.
+constexpr int kBoxXY = 17;
+constexpr int kBoxZ = 9;
+constexpr int kBoxCells = kBoxXY * kBoxXY * kBoxZ;
+constexpr int kBoxReps = 128;
 
 struct InsertArgs {
   const float* xyz;
@@ -72,7 +84,8 @@ struct InsertArgs {
   int64_t stripe_off[kStripes];  // item region of each stripe of ray blocks
   int64_t stripe_cap[kStripes];
   int32_t seg_len;             // dominant-axis voxels per segment
-  int32_t trace_blocks;        // grid of the trace kernel
+  int32_t trace_blocks;        // grid of the trace kernel (kTraceBlock threads per block
+                               // for a single map, 256 in a batch)
   // binned traversal (used when `binned` is set)
   int32_t binned;
   int32_t gx, gy;              // slabs along x and along y (ceil(n / kBinT))
@@ -83,9 +96,22 @@ struct InsertArgs {
   int4* units;                 // {bin, first segment, segments, 0}
   int32_t* uctl;               // [0] units
   int32_t tb_blocks;           // grid of the binned traversal
+  // sensor box (segmented traversal): storage coordinate of its first cell
+  // and extent per axis; cell (dx, dy, dz) has box index
+  // (dx * kBoxXY + dy) * kBoxZ + dz
+  int32_t box_s[3];
+  int32_t box_e[3];
+  int32_t box_l[3];            // window-local coordinate of the box's first cell
+  int32_t* box_rep;            // [kBoxReps][kBoxCells], zero between inserts
 };
 
 constexpr int kRayBlock = 256;    // threads per block of the ray pass
+// threads per block of the single-map traversal: eight waves share one LDS
+// copy of the sensor box (the batched traversal uses 256-thread blocks)
+constexpr int kTraceBlock = 512;
+
+// Blocks of the sensor-box fold that follows the segmented traversal.
+int box_fold_blocks();
 
 // Segments one ray can produce at most (segmented / binned traversal).
 int64_t max_segments(const Dims& d, int32_t seg_len);

@@ -130,39 +130,57 @@ __global__ __launch_bounds__(kRayBlock) void k_rays(InsertArgs a) {
 //
 // Lanes of a wave step in lock-step; the lanes that pass the same voxel as
 // their left neighbour join its run and the run's first lane adds the run
-// length with one atomic.
-template <bool DISTINCT>
+// length with one atomic.  With BOX, runs in the sensor box add into the
+// block's LDS copy of the box instead, which the block flushes into its
+// replica at the end (k_box_fold adds the replicas into the map).
+template <bool DISTINCT, bool BOX, int NT>
 __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, const int nblk) {
   const int lane = __lane_id();
+  __shared__ int32_t box_cnt[BOX ? kBoxCells : 1];
+  if (BOX) {
+    for (int i = threadIdx.x; i < kBoxCells; i += NT) box_cnt[i] = 0;
+    __syncthreads();
+  }
   const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
   const int32_t dims[3] = {nx, ny, nz};
   // items of stripe t occupy [stripe_off[t], stripe_off[t] + cnt[t]); the
-  // loop runs over their concatenation
-  int64_t pre[kStripes + 1];
-  pre[0] = 0;
+  // loop runs over their concatenation.  The stripe prefix lives in LDS
+  // (in registers it would cost the kernel its last wave per SIMD).
+  __shared__ int64_t s_pre[kStripes + 1];
+  __shared__ int64_t s_base[kStripes];  // stripe_off[t] - s_pre[t]
+  if (threadIdx.x == 0) {
+    int64_t p = 0;
 #pragma unroll
-  for (int t = 0; t < kStripes; t++)
-    pre[t + 1] = pre[t] + min((int64_t)a.stats[8 + t], a.stripe_cap[t]);
-  const int64_t count = pre[kStripes];
-  const int64_t stride = (int64_t)nblk * kBlock;
+    for (int t = 0; t < kStripes; t++) {
+      s_pre[t] = p;
+      s_base[t] = a.stripe_off[t] - p;
+      p += min((int64_t)a.stats[8 + t], a.stripe_cap[t]);
+    }
+    s_pre[kStripes] = p;
+  }
+  __syncthreads();
+  const int64_t count = s_pre[kStripes];
+  const int64_t stride = (int64_t)nblk * NT;
   uint32_t* touch_p = DISTINCT ? a.touch + ((a.d.vs + 31) >> 5) : nullptr;
   int32_t* const passes = a.passes;  // kept in registers across the loop
-  int n_pass = 0, n_dpass = 0, n_upd = 0;
+  int n_pass = 0, n_dpass = 0, n_upd = 0;  // n_pass is wave-uniform
 
-  for (int64_t wbase = (int64_t)blk * kBlock + (threadIdx.x & ~63); wbase < count;
+  for (int64_t wbase = (int64_t)blk * NT + (threadIdx.x & ~63); wbase < count;
        wbase += stride) {
     const int64_t it = wbase + lane;
-    bool active = false;
+    bool active = false, near = false;
     Walk w = {};
+    int32_t cnt[3] = {0, 0, 0};
+    bool stop[3] = {false, false, false};
     int32_t sc[3] = {0, 0, 0};
-    int32_t sidx = 0, segleft = 0;
-    bool mdx = false, mdy = false, mdz = false;
+    int32_t sidx = 0;
     if (it < count) {
-      int64_t base = a.stripe_off[0] - pre[0];
+      // last stripe t with s_pre[t] <= it (empty stripes share their prefix)
+      int t = 0;
 #pragma unroll
-      for (int k = 1; k < kStripes; k++)
-        if (it >= pre[k]) base = a.stripe_off[k] - pre[k];
-      const int4 item = a.items[base + it];
+      for (int step = kStripes / 2; step >= 1; step >>= 1)
+        if (it >= s_pre[t + step]) t += step;
+      const int4 item = a.items[s_base[t] + it];
       const int32_t q[3] = {item.x, item.y, item.z};
       const int j = item.w;
       int32_t sv[3], n[3], sg[3], ad[3];
@@ -187,61 +205,87 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
       }
       if (inside) {
         walk_init(a, q, v, l, w);
+        budget_init(w, dom, a.seg_len, cnt, stop);
 #pragma unroll
         for (int k = 0; k < 3; k++) sc[k] = wrap_add(l[k] + a.d.ro[k], dims[k]);
-        sidx = col_base(a.d, sc[0], sc[1]) + (sc[2] << 4);
-        segleft = a.seg_len - 1;
-        mdx = dom == 0;
-        mdy = dom == 1;
-        mdz = dom == 2;
-        active = w.rem[0] + w.rem[1] + w.rem[2] > 0;
+        sidx = col_base24(a.d, sc[0], sc[1]) + (sc[2] << 4);
+        active = (cnt[0] | cnt[1] | cnt[2]) != 0;
+        if (BOX) {
+          // the segment's dominant-axis cells (window-local) against the box's
+          const int32_t c0 = l[dom], c1 = l[dom] + sg[dom] * (a.seg_len - 1);
+          const int32_t lo = c0 < c1 ? c0 : c1, hi = c0 < c1 ? c1 : c0;
+          near = hi >= a.box_l[dom] && lo < a.box_l[dom] + a.box_e[dom];
+        }
       }
     }
+    // box lookups only in waves that can reach the box
+    const bool wnear = BOX && __any(near);
 
     // per-lane constants of the storage wrap
     const bool px = w.sg[0] > 0, py = w.sg[1] > 0, pz = w.sg[2] > 0;
     const int32_t trig0 = px ? nx : -1, trig1 = py ? ny : -1, trig2 = pz ? nz : -1;
     const int32_t wv0 = px ? 0 : nx - 1, wv1 = py ? 0 : ny - 1, wv2 = pz ? 0 : nz - 1;
-    while (__any(active)) {
+    for (;;) {
+      const unsigned long long ab = __ballot(active);
+      if (!ab) break;
+      n_pass += __popcll(ab);
       // ---- aggregated pass of the current voxel: runs of equal addresses in
       // neighbouring lanes (left neighbour via a whole-wave DPP shift)
       const int addr = active ? sidx : -1;
       const int prev = __builtin_amdgcn_update_dpp(-2, addr, 0x138, 0xf, 0xf, false);
       const bool head = active && prev != addr;
       const unsigned long long hb = __ballot(head);
-      const unsigned long long ab = __ballot(active);
-      n_upd += head;
       if (head) {
         const unsigned long long bnd = hb | ~ab;
         const unsigned long long after = lane == 63 ? 0ull : (bnd >> (lane + 1));
         const int len = after ? __ffsll((long long)after) : 64 - lane;
-        atomicAdd(&passes[addr], len);
-        if (DISTINCT) {
-          const uint32_t bit = 1u << (addr & 31);
-          const uint32_t old = atomicOr(&touch_p[(uint32_t)addr >> 5], bit);
-          n_dpass += !(old & bit);
+        int bidx = -1;
+        if (BOX && wnear) {
+          // storage offsets from the box's first cell (unsigned: wrapped)
+          const uint32_t d0 = (uint32_t)wrap_add(sc[0] - a.box_s[0] + nx, nx);
+          const uint32_t d1 = (uint32_t)wrap_add(sc[1] - a.box_s[1] + ny, ny);
+          const uint32_t d2 = (uint32_t)wrap_add(sc[2] - a.box_s[2] + nz, nz);
+          if (d0 < (uint32_t)a.box_e[0] && d1 < (uint32_t)a.box_e[1] && d2 < (uint32_t)a.box_e[2])
+            bidx = (int)((d0 * kBoxXY + d1) * kBoxZ + d2);
+        }
+        if (BOX && bidx >= 0) {
+          atomicAdd(&box_cnt[bidx], len);
+        } else {
+          n_upd++;
+          atomicAdd(&passes[addr], len);
+          if (DISTINCT) {
+            const uint32_t bit = 1u << (addr & 31);
+            const uint32_t old = atomicOr(&touch_p[(uint32_t)addr >> 5], bit);
+            n_dpass += !(old & bit);
+          }
         }
       }
-      n_pass += active;
       // ---- step
       bool mx, my, mz;
-      bool out = walk_step(w, mx, my, mz);
-      const bool domstep = (mx & mdx) | (my & mdy) | (mz & mdz);
-      out = out | (domstep & (segleft == 0));
-      segleft -= domstep;
+      const bool out = budget_step(w, cnt, stop, px, py, pz, mx, my, mz);
       const int32_t t0 = sc[0] + (mx ? w.sg[0] : 0);
       const int32_t t1 = sc[1] + (my ? w.sg[1] : 0);
       const int32_t t2 = sc[2] + (mz ? w.sg[2] : 0);
       sc[0] = t0 == trig0 ? wv0 : t0;
       sc[1] = t1 == trig1 ? wv1 : t1;
       sc[2] = t2 == trig2 ? wv2 : t2;
-      sidx = col_base(a.d, sc[0], sc[1]) + (sc[2] << 4);
-      active = active & !out & (w.rem[0] + w.rem[1] + w.rem[2] > 0);
+      sidx = col_base24(a.d, sc[0], sc[1]) + (sc[2] << 4);
+      active = active & !out & ((cnt[0] | cnt[1] | cnt[2]) != 0);
+    }
+  }
+  if (BOX) {
+    // flush the block's box counts into its replica (coalesced; zero cells
+    // are skipped)
+    __syncthreads();
+    int32_t* rep = a.box_rep + (size_t)(blk % kBoxReps) * kBoxCells;
+    for (int i = threadIdx.x; i < kBoxCells; i += NT) {
+      const int32_t c = box_cnt[i];
+      if (c) atomicAdd(&rep[i], c);
     }
   }
   // per-block counters, written without atomics (summed by the host)
-  __shared__ int wsum[kBlock / 64][3];
-  const int c3 = wave_sum(n_pass);
+  __shared__ int wsum[NT / 64][3];
+  const int c3 = n_pass;
   const int c4 = DISTINCT ? wave_sum(n_dpass) : 0;
   const int c6 = wave_sum(n_upd);
   if (lane == 0) {
@@ -252,7 +296,7 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long p = 0, q = 0, u = 0;
-    for (int w = 0; w < kBlock / 64; w++) {
+    for (int w = 0; w < NT / 64; w++) {
       p += wsum[w][0];
       q += wsum[w][1];
       u += wsum[w][2];
@@ -264,9 +308,69 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
   }
 }
 
+// At most 96 scalar registers (granules of 16 out of 800 per SIMD) leave room
+// for eight waves per SIMD.
 template <bool DISTINCT>
-__global__ __launch_bounds__(kBlock) void k_trace(InsertArgs a) {
-  trace_body<DISTINCT>(a, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_num_sgpr(88))) void k_trace(
+    InsertArgs a) {
+  trace_body<DISTINCT, true, kTraceBlock>(a, blockIdx.x, gridDim.x);
+}
+
+// Sensor-box fold: thread (cell i, group g) sums cell i over the kFoldReps
+// replicas of group g (zeroing them for the next insert) and adds the sum to
+// the cell's passes.  Distinct passes of box cells are counted here (the
+// traversal skipped them): the group whose bit-or finds the cell's bit clear
+// counts it.  Block b (linear over the grid) writes its counters to slot
+// trace_blocks + b.
+constexpr int kFoldReps = 8;
+constexpr int kFoldGroups = kBoxReps / kFoldReps;
+static_assert(kBoxReps % kFoldReps == 0, "replica groups");
+
+template <bool DISTINCT>
+__global__ __launch_bounds__(kBlock) void k_box_fold(InsertArgs a) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  int n_dpass = 0;
+  if (i < kBoxCells) {
+    int32_t v[kFoldReps];
+    int32_t* p = a.box_rep + (size_t)blockIdx.y * kFoldReps * kBoxCells + i;
+#pragma unroll
+    for (int r = 0; r < kFoldReps; r++) v[r] = p[(size_t)r * kBoxCells];
+    int32_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < kFoldReps; r++) {
+      sum += v[r];
+      if (v[r]) p[(size_t)r * kBoxCells] = 0;
+    }
+    const int dz = i % kBoxZ, t = i / kBoxZ;
+    const int dy = t % kBoxXY, dx = t / kBoxXY;
+    if (sum && dx < a.box_e[0] && dy < a.box_e[1] && dz < a.box_e[2]) {
+      const int32_t sx = wrap_add(a.box_s[0] + dx, a.d.nx);
+      const int32_t sy = wrap_add(a.box_s[1] + dy, a.d.ny);
+      const int32_t sz = wrap_add(a.box_s[2] + dz, a.d.nz);
+      const int32_t idx = col_base(a.d, sx, sy) + (sz << 4);
+      atomicAdd(&a.passes[idx], sum);
+      if (DISTINCT) {
+        uint32_t* touch_p = a.touch + ((a.d.vs + 31) >> 5);
+        const uint32_t bit = 1u << (idx & 31);
+        const uint32_t old = atomicOr(&touch_p[(uint32_t)idx >> 5], bit);
+        n_dpass = !(old & bit);
+      }
+    }
+  }
+  __shared__ int wsum[kBlock / 64];
+  const int c = DISTINCT ? wave_sum(n_dpass) : 0;
+  if (__lane_id() == 0) wsum[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long q = 0;
+    for (int w = 0; w < kBlock / 64; w++) q += wsum[w];
+    const size_t slot = (size_t)a.trace_blocks + blockIdx.y * gridDim.x + blockIdx.x;
+    unsigned long long* pt = a.part_trace + 4 * slot;
+    pt[0] = 0;
+    pt[1] = q;
+    pt[2] = 0;
+    pt[3] = 0;
+  }
 }
 
 // Window scroll: box k resets the storage voxels of
@@ -372,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_b_trace(const BatchTables* __restric
   const int total = t->st.pre_trace[n];
   for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
     const int m = find_map(t->st.pre_trace, n, vb);
-    trace_body<false>(t->ins[m], vb - t->st.pre_trace[m], t->ins[m].trace_blocks);
+    trace_body<false, false, kBlock>(t->ins[m], vb - t->st.pre_trace[m], t->ins[m].trace_blocks);
     __syncthreads();
   }
 }
@@ -437,11 +541,18 @@ hipError_t launch_rays(const InsertArgs& a, bool distinct, hipStream_t s) {
 hipError_t launch_trace(const InsertArgs& a, bool distinct, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
   if (a.binned) return launch_trace_bin(a, distinct, s);
-  if (distinct)
-    hipLaunchKernelGGL(k_trace<true>, dim3(a.trace_blocks), dim3(kBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_trace<false>, dim3(a.trace_blocks), dim3(kBlock), 0, s, a);
+  if (!a.box_rep || a.trace_blocks < 1) return hipErrorInvalidValue;
+  const dim3 fb((kBoxCells + kBlock - 1) / kBlock, kFoldGroups);
+  if (distinct) {
+    hipLaunchKernelGGL(k_trace<true>, dim3(a.trace_blocks), dim3(kTraceBlock), 0, s, a);
+    hipLaunchKernelGGL(k_box_fold<true>, dim3(fb), dim3(kBlock), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_trace<false>, dim3(a.trace_blocks), dim3(kTraceBlock), 0, s, a);
+    hipLaunchKernelGGL(k_box_fold<false>, dim3(fb), dim3(kBlock), 0, s, a);
+  }
   return hipGetLastError();
 }
+
+int box_fold_blocks() { return (kBoxCells + kBlock - 1) / kBlock * kFoldGroups; }
 
 }  // namespace gvom

@@ -39,6 +39,7 @@ struct map_t {
   int2* bin_ent;              // [nbins][blocks]
   int4* units;
   int64_t bin_ent_cap, units_cap;
+  int32_t* box_rep;           // sensor-box replicas of the segmented traversal
   int32_t n_cu;
   int32_t sticky;
   int64_t last_points, last_cleared;

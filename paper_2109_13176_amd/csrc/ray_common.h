@@ -200,5 +200,54 @@ __device__ __forceinline__ bool walk_step(Walk& w, bool& mx, bool& my, bool& mz)
   return out;
 }
 
+// Budgeted stepping for the segmented traversal.  cnt[k] = moves left along
+// axis k before it either reaches the end voxel's coordinate (the axis stops
+// moving) or, when stop[k], makes the move that leaves the window or the
+// segment (the walk ends before that voxel).  While the walk is on,
+// cnt[k] > 0 iff the axis still has steps to the end voxel, so the axis
+// choice is the one of walk_step.
+__device__ __forceinline__ void budget_init(const Walk& w, const int dom, const int32_t seg_len,
+                                            int32_t cnt[3], bool stop[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    int32_t T = w.room[k] + 1;                   // the move that leaves the window
+    if (k == dom && seg_len < T) T = seg_len;    // the move that leaves the segment
+    stop[k] = w.rem[k] >= T;
+    cnt[k] = stop[k] ? T : w.rem[k];
+  }
+}
+
+// One step of walk_step's rule under the budgets; returns whether the walk
+// ends (a stopping axis spent its budget).
+__device__ __forceinline__ bool budget_step(Walk& w, int32_t cnt[3], const bool stop[3],
+                                            const bool px, const bool py, const bool pz,
+                                            bool& mx, bool& my, bool& mz) {
+  const bool ax = cnt[0] > 0, ay = cnt[1] > 0, az = cnt[2] > 0;
+  mx = ax & (!ay | (w.fxy <= w.cxy)) & (!az | (w.fxz <= w.cxz));
+  my = ay & (!ax | (w.fxy >= 0)) & (!az | (w.fyz <= w.cyz));
+  mz = az & (!ax | (w.fxz >= 0)) & (!ay | (w.fyz >= 0));
+  const bool up = (mx & px) | (my & py) | (mz & pz);
+  mx = mx & (!up | px);
+  my = my & (!up | py);
+  mz = mz & (!up | pz);
+  cnt[0] -= mx;
+  cnt[1] -= my;
+  cnt[2] -= mz;
+  const bool out = (mx & stop[0] & (cnt[0] == 0)) | (my & stop[1] & (cnt[1] == 0)) |
+                   (mz & stop[2] & (cnt[2] == 0));
+  w.fxy = (int32_t)((uint32_t)w.fxy + (mx ? (uint32_t)w.ad[1] : 0u) - (my ? (uint32_t)w.ad[0] : 0u));
+  w.fxz = (int32_t)((uint32_t)w.fxz + (mx ? (uint32_t)w.ad[2] : 0u) - (mz ? (uint32_t)w.ad[0] : 0u));
+  w.fyz = (int32_t)((uint32_t)w.fyz + (my ? (uint32_t)w.ad[2] : 0u) - (mz ? (uint32_t)w.ad[1] : 0u));
+  return out;
+}
+
+// col_base with 24-bit multiplies (full rate): brick coordinates < 2^11,
+// nby <= 2048 and nz <= 128 keep every operand within 24 bits, and the
+// index is below 2^31 for every map the library accepts.
+__device__ __forceinline__ int32_t col_base24(const Dims& d, int32_t sx, int32_t sy) {
+  const uint32_t b = __umul24((uint32_t)(sx >> 2), (uint32_t)d.nby) + (uint32_t)(sy >> 2);
+  return (int32_t)((__umul24(b, (uint32_t)d.nz) << 4) + ((sy & 3) << 2) + (sx & 3));
+}
+
 }  // namespace
 }  // namespace gvom
