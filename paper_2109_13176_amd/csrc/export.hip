@@ -147,36 +147,47 @@ __device__ __forceinline__ int line_distance(const unsigned long long* L, int MW
   return best;
 }
 
+// LDS row stride of the staged heights: odd, so that the column reads of
+// the mask pass hit distinct banks
+__host__ __device__ __forceinline__ int surface_stride(int T) { return T | 1; }
+
 __device__ __forceinline__ void surface_body(const SurfaceArgs& a, const int H, const int bx,
                                              const int by) {
   extern __shared__ int32_t lds[];
   const int T = kTile + 2 * H;          // staged tile edge
+  const int TS = surface_stride(T);     // LDS row stride of th
   const int MW = (T + 63) >> 6;         // mask words per staged row / column
-  int32_t* th = lds;                                                    // [T][T]
-  unsigned long long* rmask = (unsigned long long*)(lds + ((T * T + 1) & ~1));  // [T][MW]
+  int32_t* th = lds;                                                    // [T][TS]
+  unsigned long long* rmask = (unsigned long long*)(lds + ((T * TS + 1) & ~1));  // [T][MW]
   unsigned long long* cmask = rmask + T * MW;                            // [T][MW]
   uint8_t* rdist = (uint8_t*)(cmask + T * MW);  // [T][kTile]: row r, tile column j
   uint8_t* cdist = rdist + T * kTile;           // [T][kTile]: column c, tile row i
   const int gx0 = bx * kTile - H, gy0 = by * kTile - H;
-  for (int i = threadIdx.x; i < T * T; i += kSurfThreads) {
-    const int tx = i / T, ty = i - tx * T;
-    const int gx = gx0 + tx, gy = gy0 + ty;
-    int32_t v = INT32_MIN;
-    if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny) v = a.hq[(int64_t)gx * a.ny + gy];
-    th[i] = v;
+  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+  constexpr int kWaves = kSurfThreads / 64;
+  // stage the heights row by row (a wave per row, lanes along y); the
+  // ballot of each 64-cell piece is that row's mask word
+  for (int r = wv; r < T; r += kWaves) {
+    const int gx = gx0 + r;
+    const bool rowok = gx >= 0 && gx < a.nx;
+    for (int w = 0; w < MW; w++) {
+      const int k = 64 * w + lane;
+      const int gy = gy0 + k;
+      int32_t v = INT32_MIN;
+      if (k < T && rowok && gy >= 0 && gy < a.ny) v = a.hq[(int64_t)gx * a.ny + gy];
+      if (k < T) th[r * TS + k] = v;
+      const unsigned long long b = __ballot(v != INT32_MIN);
+      if (lane == 0) rmask[r * MW + w] = b;
+    }
   }
   __syncthreads();
-  {
-    const int lane = __lane_id(), wv = threadIdx.x >> 6;
-    for (int j = wv; j < 2 * T * MW; j += kSurfThreads / 64) {
-      const bool col = j >= T * MW;
-      const int jj = col ? j - T * MW : j;
-      const int r = jj / MW, w = jj - r * MW;
+  // column masks: lanes along x
+  for (int c = wv; c < T; c += kWaves) {
+    for (int w = 0; w < MW; w++) {
       const int k = 64 * w + lane;
-      bool d = false;
-      if (k < T) d = (col ? th[k * T + r] : th[r * T + k]) != INT32_MIN;
+      const bool d = k < T && th[k * TS + c] != INT32_MIN;
       const unsigned long long b = __ballot(d);
-      if (lane == 0) (col ? cmask : rmask)[r * MW + w] = b;
+      if (lane == 0) cmask[c * MW + w] = b;
     }
   }
   __syncthreads();
@@ -187,29 +198,42 @@ __device__ __forceinline__ void surface_body(const SurfaceArgs& a, const int H, 
     const int dd = line_distance((col ? cmask : rmask) + line * MW, MW, T, H + j);
     (col ? cdist : rdist)[ii] = (uint8_t)dd;
   }
-  __syncthreads();
 
   // defined pixels (plane fit) and undefined ones (cone search) go to
-  // separate waves: the block's pixels are listed defined-first
-  __shared__ int n_def, n_und;
+  // separate waves: the block's pixels are listed defined-first, ranks from
+  // ballots (deterministic order)
   __shared__ int16_t order[kSurfThreads];
-  if (threadIdx.x == 0) {
-    n_def = 0;
-    n_und = 0;
-  }
-  __syncthreads();
+  __shared__ int wcnt[kWaves][2];
   {
     const int px = threadIdx.x / kTile, py = threadIdx.x - px * kTile;
     const int gx = bx * kTile + px, gy = by * kTile + py;
-    if (gx < a.nx && gy < a.ny) {
-      if (th[(px + H) * T + py + H] != INT32_MIN)
-        order[atomicAdd(&n_def, 1)] = (int16_t)threadIdx.x;
-      else
-        order[kSurfThreads - 1 - atomicAdd(&n_und, 1)] = (int16_t)threadIdx.x;
+    const bool valid = gx < a.nx && gy < a.ny;
+    const bool def = valid && th[(px + H) * TS + py + H] != INT32_MIN;
+    const bool und = valid && !def;
+    const unsigned long long bd = __ballot(def), bu = __ballot(und);
+    if (lane == 0) {
+      wcnt[wv][0] = __popcll(bd);
+      wcnt[wv][1] = __popcll(bu);
     }
+    __syncthreads();
+    int pd = 0, pu = 0;
+    for (int w = 0; w < wv; w++) {
+      pd += wcnt[w][0];
+      pu += wcnt[w][1];
+    }
+    const int below_d = __builtin_amdgcn_mbcnt_hi((uint32_t)(bd >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bd, 0));
+    const int below_u = __builtin_amdgcn_mbcnt_hi((uint32_t)(bu >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bu, 0));
+    if (def) order[pd + below_d] = (int16_t)threadIdx.x;
+    if (und) order[kSurfThreads - 1 - (pu + below_u)] = (int16_t)threadIdx.x;
   }
   __syncthreads();
-  const int nd = n_def, nu = n_und;
+  int nd = 0, nu = 0;
+  for (int w = 0; w < kWaves; w++) {
+    nd += wcnt[w][0];
+    nu += wcnt[w][1];
+  }
   int me;
   if ((int)threadIdx.x < nd) me = order[threadIdx.x];
   else if ((int)threadIdx.x >= kSurfThreads - nu) me = order[threadIdx.x];
@@ -218,7 +242,7 @@ __device__ __forceinline__ void surface_body(const SurfaceArgs& a, const int H, 
   const int gx = bx * kTile + px, gy = by * kTile + py;
   const int h = a.half_fit, D = a.search_d;
   const int tx = px + H, ty = py + H;
-  const int32_t hc = th[tx * T + ty];
+  const int32_t hc = th[tx * TS + ty];
   const int64_t c = (int64_t)gx * a.ny + gy;
   uint8_t fl = a.flags[c];
   float slope = __uint_as_float(kQNaN), rough = __uint_as_float(kQNaN);
@@ -227,7 +251,7 @@ __device__ __forceinline__ void surface_body(const SurfaceArgs& a, const int H, 
     int64_t sz = 0, sxz = 0, syz = 0, szz = 0;
     for (int dx = -h; dx <= h; dx++)
       for (int dy = -h; dy <= h; dy++) {
-        const int32_t v = th[(tx + dx) * T + ty + dy];
+        const int32_t v = th[(tx + dx) * TS + ty + dy];
         if (v == INT32_MIN) continue;
         const int64_t dz = (int64_t)v - hc;
         n++;
@@ -274,8 +298,20 @@ __device__ __forceinline__ void surface_body(const SurfaceArgs& a, const int H, 
       const int oth = alongx ? ty : tx;        // centre of the slice span
       const uint8_t* dist = alongx ? rdist : cdist;
       const int j = alongx ? py : px;
+      // first ring holding a defined cell: four rings per round (independent
+      // LDS reads; ring indexes clamped to D stay inside the staged tile)
       int d = 1;
-      while (d <= D && dist[(ctr + dir * d) * kTile + j] > d) d++;
+      for (; d <= D; d += 4) {
+        const int d1 = min(d + 1, D), d2 = min(d + 2, D), d3 = min(d + 3, D);
+        const int b0 = dist[(ctr + dir * d) * kTile + j];
+        const int b1 = dist[(ctr + dir * d1) * kTile + j];
+        const int b2 = dist[(ctr + dir * d2) * kTile + j];
+        const int b3 = dist[(ctr + dir * d3) * kTile + j];
+        if (b0 <= d) break;
+        if (b1 <= d1) { d = d1; break; }
+        if (b2 <= d2) { d = d2; break; }
+        if (b3 <= d3) { d = d3; break; }
+      }
       if (d > D) continue;
       const int line = ctr + dir * d;
       const int s0 = oth - d, s1 = oth + d;
@@ -285,7 +321,7 @@ __device__ __forceinline__ void surface_body(const SurfaceArgs& a, const int H, 
         while (b) {
           const int k = 64 * w + __ffsll((long long)b) - 1;
           b &= b - 1;
-          const int32_t v = alongx ? th[line * T + k] : th[k * T + line];
+          const int32_t v = alongx ? th[line * TS + k] : th[k * TS + line];
           lo = min(lo, v);
           hi = max(hi, v);
           found++;
@@ -640,7 +676,8 @@ int surface_tile() { return kTile; }
 size_t surface_lds(int H) {
   const int T = kTile + 2 * H;
   const int MW = (T + 63) / 64;
-  return (size_t)((T * T + 1) & ~1) * 4 + 2 * (size_t)T * MW * 8 + 2 * (size_t)T * kTile;
+  return (size_t)((T * surface_stride(T) + 1) & ~1) * 4 + 2 * (size_t)T * MW * 8 +
+         2 * (size_t)T * kTile;
 }
 
 size_t lut_lds(int nz) { return (size_t)kRegCols * lut_row(nz) * 4; }
@@ -654,8 +691,7 @@ hipError_t launch_surface(const SurfaceArgs& a, hipStream_t s) {
   const int T = kTile + 2 * H;
   const int MW = (T + 63) / 64;
   if (MW > kMaxMaskWords) return hipErrorInvalidValue;
-  const size_t lds = (size_t)((T * T + 1) & ~1) * 4 + 2 * (size_t)T * MW * 8 +
-                     2 * (size_t)T * kTile;
+  const size_t lds = surface_lds(H);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute((const void*)k_surface,
