@@ -193,9 +193,8 @@ int32_t map_sync(map_t* m);
 /* Launch tuning (performance only: results are bit-identical for every
  * setting).  traversal: 2 = segmented (rays cut every seg_len dominant-axis
  * voxels, runs of equal voxels in neighbouring lanes merged, one global
- * atomic per run; in single-map inserts the passes of a 17 x 17 x 9 box
- * around the sensor are summed per block on chip first; default, and always
- * used by batches), 1 = binned (rays cut at 16-voxel storage slabs, passes
+ * atomic per run; the passes of a 17 x 17 x 9 box around the sensor are
+ * summed per block on chip first; default, and always used by batches), 1 = binned (rays cut at 16-voxel storage slabs, passes
  * counted per slab tile in LDS, then added to the map; single-map inserts
  * only, when the window has at most 16,384 tiles and the scan at most
  * 524,288 points, else segmented).  seg_len: dominant-axis voxels per ray

@@ -351,8 +351,8 @@ bool grow(map_t* m, T** p, int64_t* cap, int64_t need, size_t elem) {
 // Second half of an insert (after check_insert): grows the per-scan buffers,
 // moves the window (the slab clears go to `plan`; *full = whole window), and
 // fills the kernel arguments.  Updates the host-side map state.  `single`:
-// a single-map insert (binned traversal allowed, sensor box folded); the
-// batched step traverses without either.
+// a single-map insert (binned traversal allowed; the batched step always
+// takes the segmented traversal).
 int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* pose,
                        uint32_t flags, const int32_t S[3], gvom::InsertArgs* a,
                        gvom::ClearArgs* plan, bool* full, bool single) {
@@ -457,9 +457,8 @@ int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* p
     a->box_l[k] = (int32_t)lo;
     a->box_s[k] = (int32_t)((lo + m->d.ro[k]) % dims[k]);
   }
-  a->box_rep = single ? m->box_rep : nullptr;
-  m->last_trace_blocks =
-      binned ? a->tb_blocks : a->trace_blocks + (single ? gvom::box_fold_blocks() : 0);
+  a->box_rep = m->box_rep;
+  m->last_trace_blocks = binned ? a->tb_blocks : a->trace_blocks + gvom::box_fold_blocks();
   if (n <= 0) m->last_trace_blocks = 0;
   return MAP_OK;
 }
@@ -890,7 +889,8 @@ int32_t map_batch_create(map_t* const* maps, int32_t k, void* stream, map_batch_
     lut = s2 > lut ? s2 : lut;
   }
   const int cu = b->n_cu;
-  b->grid = gvom::BatchGrid{cu * 4, cu * 8, cu * 8, cu * 4, cu * 2, cu * 4, cu * 4, surf, lut};
+  b->grid = gvom::BatchGrid{cu * 4, cu * 8, cu * 8, cu * 4, cu * 2, cu * 4, cu * 4,
+                            k * gvom::box_fold_blocks(), surf, lut};
   hipError_t e = hipMalloc((void**)&b->dtab, sizeof(gvom::BatchTables));
   if (e == hipSuccess) e = hipHostMalloc((void**)&b->htab, sizeof(gvom::BatchTables), 0);
   if (e == hipSuccess) e = hipMalloc((void**)&b->dstamps, (gvom::kMaxBatch + 1) * 8);

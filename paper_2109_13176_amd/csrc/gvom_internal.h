@@ -206,6 +206,7 @@ struct BatchTables {
 
 struct BatchGrid {
   int clear, rays, trace, col, surf, lcount, lwrite;  // persistent grid sizes
+  int fold;                                            // maps x sensor-box fold blocks
   size_t surf_lds, lut_lds;
 };
 

@@ -308,11 +308,8 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
   }
 }
 
-// At most 96 scalar registers (granules of 16 out of 800 per SIMD) leave room
-// for eight waves per SIMD.
 template <bool DISTINCT>
-__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_num_sgpr(88))) void k_trace(
-    InsertArgs a) {
+__global__ __launch_bounds__(kTraceBlock) void k_trace(InsertArgs a) {
   trace_body<DISTINCT, true, kTraceBlock>(a, blockIdx.x, gridDim.x);
 }
 
@@ -326,13 +323,16 @@ constexpr int kFoldReps = 8;
 constexpr int kFoldGroups = kBoxReps / kFoldReps;
 static_assert(kBoxReps % kFoldReps == 0, "replica groups");
 
+constexpr int kFoldCellBlocks = (kBoxCells + kBlock - 1) / kBlock;
+
+// Fold block (cell block bx, replica group by) of one map.
 template <bool DISTINCT>
-__global__ __launch_bounds__(kBlock) void k_box_fold(InsertArgs a) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void box_fold_body(const InsertArgs& a, const int bx, const int by) {
+  const int i = bx * kBlock + threadIdx.x;
   int n_dpass = 0;
   if (i < kBoxCells) {
     int32_t v[kFoldReps];
-    int32_t* p = a.box_rep + (size_t)blockIdx.y * kFoldReps * kBoxCells + i;
+    int32_t* p = a.box_rep + (size_t)by * kFoldReps * kBoxCells + i;
 #pragma unroll
     for (int r = 0; r < kFoldReps; r++) v[r] = p[(size_t)r * kBoxCells];
     int32_t sum = 0;
@@ -364,13 +364,18 @@ __global__ __launch_bounds__(kBlock) void k_box_fold(InsertArgs a) {
   if (threadIdx.x == 0) {
     unsigned long long q = 0;
     for (int w = 0; w < kBlock / 64; w++) q += wsum[w];
-    const size_t slot = (size_t)a.trace_blocks + blockIdx.y * gridDim.x + blockIdx.x;
+    const size_t slot = (size_t)a.trace_blocks + by * kFoldCellBlocks + bx;
     unsigned long long* pt = a.part_trace + 4 * slot;
     pt[0] = 0;
     pt[1] = q;
     pt[2] = 0;
     pt[3] = 0;
   }
+}
+
+template <bool DISTINCT>
+__global__ __launch_bounds__(kBlock) void k_box_fold(InsertArgs a) {
+  box_fold_body<DISTINCT>(a, blockIdx.x, blockIdx.y);
 }
 
 // Window scroll: box k resets the storage voxels of
@@ -476,9 +481,18 @@ __global__ __launch_bounds__(kBlock) void k_b_trace(const BatchTables* __restric
   const int total = t->st.pre_trace[n];
   for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
     const int m = find_map(t->st.pre_trace, n, vb);
-    trace_body<false, false, kBlock>(t->ins[m], vb - t->st.pre_trace[m], t->ins[m].trace_blocks);
+    trace_body<false, true, kBlock>(t->ins[m], vb - t->st.pre_trace[m], t->ins[m].trace_blocks);
     __syncthreads();
   }
+}
+
+// Sensor-box folds of every map of the batch: block b = map b / F, fold block
+// b mod F (F = kFoldCellBlocks x kFoldGroups).
+__global__ __launch_bounds__(kBlock) void k_b_box_fold(const BatchTables* __restrict__ t) {
+  constexpr int F = kFoldCellBlocks * kFoldGroups;
+  const int m = blockIdx.x / F, f = blockIdx.x - m * F;
+  if (m >= t->st.nmaps) return;
+  box_fold_body<false>(t->ins[m], f % kFoldCellBlocks, f / kFoldCellBlocks);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
@@ -512,6 +526,7 @@ hipError_t launch_batch_insert(const BatchTables* tab, const BatchGrid& g,
   hipLaunchKernelGGL(k_b_clear, dim3(g.clear), dim3(kBlock), 0, s, tab, stamps, done);
   hipLaunchKernelGGL(k_b_rays, dim3(g.rays), dim3(kRayBlock), 0, s, tab);
   hipLaunchKernelGGL(k_b_trace, dim3(g.trace), dim3(kBlock), 0, s, tab);
+  hipLaunchKernelGGL(k_b_box_fold, dim3(g.fold), dim3(kBlock), 0, s, tab);
   return hipGetLastError();
 }
 
@@ -542,7 +557,7 @@ hipError_t launch_trace(const InsertArgs& a, bool distinct, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
   if (a.binned) return launch_trace_bin(a, distinct, s);
   if (!a.box_rep || a.trace_blocks < 1) return hipErrorInvalidValue;
-  const dim3 fb((kBoxCells + kBlock - 1) / kBlock, kFoldGroups);
+  const dim3 fb(kFoldCellBlocks, kFoldGroups);
   if (distinct) {
     hipLaunchKernelGGL(k_trace<true>, dim3(a.trace_blocks), dim3(kTraceBlock), 0, s, a);
     hipLaunchKernelGGL(k_box_fold<true>, dim3(fb), dim3(kBlock), 0, s, a);
@@ -553,6 +568,6 @@ hipError_t launch_trace(const InsertArgs& a, bool distinct, hipStream_t s) {
   return hipGetLastError();
 }
 
-int box_fold_blocks() { return (kBoxCells + kBlock - 1) / kBlock * kFoldGroups; }
+int box_fold_blocks() { return kFoldCellBlocks * kFoldGroups; }
 
 }  // namespace gvom
