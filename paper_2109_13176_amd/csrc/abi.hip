@@ -716,7 +716,6 @@ struct map_batch_t {
   gvom::BatchTables* htab;  // pinned
   unsigned long long* dstamps;
   unsigned long long* hstamps;  // pinned
-  unsigned int* ddone;
   gvom::BatchGrid grid;
   bool use_graph, captured;
   hipGraph_t graph;
@@ -731,8 +730,8 @@ namespace {
 hipError_t enqueue_batch(map_batch_t* b) {
   hipError_t e = hipMemcpyAsync(b->dtab, b->htab, sizeof(gvom::BatchTables),
                                 hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess) e = gvom::launch_batch_insert(b->dtab, b->grid, b->dstamps, b->ddone, b->stream);
-  if (e == hipSuccess) e = gvom::launch_batch_export(b->dtab, b->grid, b->dstamps, b->ddone, b->stream);
+  if (e == hipSuccess) e = gvom::launch_batch_insert(b->dtab, b->grid, b->dstamps, b->stream);
+  if (e == hipSuccess) e = gvom::launch_batch_export(b->dtab, b->grid, b->dstamps, b->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->hstamps, b->dstamps, (b->k + 1) * sizeof(unsigned long long),
                        hipMemcpyDeviceToHost, b->stream);
@@ -788,7 +787,6 @@ int32_t batch_prepare(map_batch_t* b, const float* const* xyz_dev, const int64_t
     st.lut_groups[i] = (int)((C + 63) / 64);
     st.nz_magic[i] = gvom::nz_magic(m->p.nz);
     st.last_is_lut[i] = lut ? 1 : 0;
-    st.last_blocks[i] = lut ? lw : tiles;
     (void)full;  // a whole-window clear is the plan's single full box
   }
   return MAP_OK;
@@ -889,13 +887,14 @@ int32_t map_batch_create(map_t* const* maps, int32_t k, void* stream, map_batch_
     lut = s2 > lut ? s2 : lut;
   }
   const int cu = b->n_cu;
-  b->grid = gvom::BatchGrid{cu * 4, cu * 8, cu * 8, cu * 4, cu * 2, cu * 4, cu * 4,
+  // persistent grids; the bandwidth-bound column and table passes get eight
+  // blocks per CU (the table pass's LDS regions allow it)
+  b->grid = gvom::BatchGrid{cu * 4, cu * 8, cu * 8, cu * 8, cu * 2, cu * 4, cu * 8,
                             k * gvom::box_fold_blocks(), surf, lut};
   hipError_t e = hipMalloc((void**)&b->dtab, sizeof(gvom::BatchTables));
   if (e == hipSuccess) e = hipHostMalloc((void**)&b->htab, sizeof(gvom::BatchTables), 0);
   if (e == hipSuccess) e = hipMalloc((void**)&b->dstamps, (gvom::kMaxBatch + 1) * 8);
   if (e == hipSuccess) e = hipHostMalloc((void**)&b->hstamps, (gvom::kMaxBatch + 1) * 8, 0);
-  if (e == hipSuccess) e = hipMalloc((void**)&b->ddone, gvom::kMaxBatch * 4);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     map_batch_destroy(b);
@@ -917,7 +916,6 @@ int32_t map_batch_destroy(map_batch_t* b) {
   (void)hipHostFree(b->htab);
   (void)hipFree(b->dstamps);
   (void)hipHostFree(b->hstamps);
-  (void)hipFree(b->ddone);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return MAP_OK;

@@ -579,14 +579,27 @@ __device__ __forceinline__ int find_map_e(const int32_t* pre, int n, int vb) {
   return lo;
 }
 
-__device__ __forceinline__ void stamp_done(const BatchStep& st, int m, unsigned long long* stamps,
-                                           unsigned int* done) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    if (atomicAdd(&done[m], 1u) + 1u == (unsigned)st.last_blocks[m]) stamps[1 + m] = wall_clock64();
+// Completion time of map m: the latest end of its last-stage blocks, kept by
+// a fire-and-forget 64-bit max (no fence: only the clock value matters).  A
+// persistent block folds consecutive virtual blocks of one map into one
+// update, made when it moves on to another map and at its end.
+struct Stamper {
+  int m = -1;
+  unsigned long long end = 0;
+  // after the (synchronised) virtual block of map mm; counts only if `last`
+  __device__ __forceinline__ void done(int mm, bool last, unsigned long long* stamps) {
+    if (threadIdx.x != 0) return;
+    if (mm != m) flush(stamps);
+    if (last) {
+      m = mm;
+      end = wall_clock64();
+    }
   }
-}
+  __device__ __forceinline__ void flush(unsigned long long* stamps) {
+    if (threadIdx.x == 0 && m >= 0) atomicMax(&stamps[1 + m], end);
+    m = -1;
+  }
+};
 
 __global__ __launch_bounds__(kBlock) void k_b_column(const BatchTables* __restrict__ t) {
   const int n = t->st.nmaps;
@@ -598,18 +611,19 @@ __global__ __launch_bounds__(kBlock) void k_b_column(const BatchTables* __restri
 }
 
 __global__ __launch_bounds__(kSurfThreads) void k_b_surface(const BatchTables* __restrict__ t,
-                                                            unsigned long long* stamps,
-                                                            unsigned int* done) {
+                                                            unsigned long long* stamps) {
   const int n = t->st.nmaps;
   const int total = t->st.pre_surf[n];
+  Stamper sp;
   for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
     const int m = find_map_e(t->st.pre_surf, n, vb);
     const int tile = vb - t->st.pre_surf[m];
     const int ty = t->st.surf_tiles_y[m];
     surface_body(t->sur[m], t->st.surf_H[m], tile / ty, tile % ty);
-    if (!t->st.last_is_lut[m]) stamp_done(t->st, m, stamps, done);
     __syncthreads();
+    sp.done(m, !t->st.last_is_lut[m], stamps);
   }
+  sp.flush(stamps);
 }
 
 __global__ __launch_bounds__(kBlock) void k_b_lut_count(const BatchTables* __restrict__ t) {
@@ -632,24 +646,25 @@ __global__ __launch_bounds__(1024) void k_b_lut_scan(const BatchTables* __restri
 }
 
 __global__ __launch_bounds__(kBlock) void k_b_lut_write(const BatchTables* __restrict__ t,
-                                                        unsigned long long* stamps,
-                                                        unsigned int* done) {
+                                                        unsigned long long* stamps) {
   const int n = t->st.nmaps;
   const int total = t->st.pre_lwrite[n];
+  Stamper sp;
   for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
     const int m = find_map_e(t->st.pre_lwrite, n, vb);
     const int b = vb - t->st.pre_lwrite[m];
     const int by = t->st.lw_by[m];
     lut_write_body(t->lut[m], t->st.nz_magic[m], b / by, b % by);
-    stamp_done(t->st, m, stamps, done);
     __syncthreads();
+    sp.done(m, true, stamps);
   }
+  sp.flush(stamps);
 }
 
 }  // namespace
 
 hipError_t launch_batch_export(const BatchTables* tab, const BatchGrid& g,
-                               unsigned long long* stamps, unsigned int* done, hipStream_t s) {
+                               unsigned long long* stamps, hipStream_t s) {
   if (g.surf_lds > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute((const void*)k_b_surface,
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -657,11 +672,10 @@ hipError_t launch_batch_export(const BatchTables* tab, const BatchGrid& g,
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_b_column, dim3(g.col), dim3(kBlock), 0, s, tab);
-  hipLaunchKernelGGL(k_b_surface, dim3(g.surf), dim3(kSurfThreads), g.surf_lds, s, tab, stamps,
-                     done);
+  hipLaunchKernelGGL(k_b_surface, dim3(g.surf), dim3(kSurfThreads), g.surf_lds, s, tab, stamps);
   hipLaunchKernelGGL(k_b_lut_count, dim3(g.lcount), dim3(kBlock), 0, s, tab);
   hipLaunchKernelGGL(k_b_lut_scan, dim3(g.lcount), dim3(1024), 0, s, tab);
-  hipLaunchKernelGGL(k_b_lut_write, dim3(g.lwrite), dim3(kBlock), g.lut_lds, s, tab, stamps, done);
+  hipLaunchKernelGGL(k_b_lut_write, dim3(g.lwrite), dim3(kBlock), g.lut_lds, s, tab, stamps);
   return hipGetLastError();
 }
 

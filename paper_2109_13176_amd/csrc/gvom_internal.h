@@ -191,7 +191,6 @@ struct BatchStep {
   int32_t lw_by[kMaxBatch];
   int32_t lut_groups[kMaxBatch];
   uint32_t nz_magic[kMaxBatch];
-  int32_t last_blocks[kMaxBatch];  // blocks of the map's last stage (completion stamp)
   int32_t last_is_lut[kMaxBatch];
 };
 
@@ -211,12 +210,12 @@ struct BatchGrid {
 };
 
 // Enqueues one batched step (all stages of all maps) reading `tab` (device).
-// stamps[0] = step start, stamps[1 + m] = completion of map m (wall clock);
-// done[m] counts finished last-stage blocks of map m.
+// stamps[0] = step start, stamps[1 + m] = completion of map m (wall clock:
+// the latest end of its last-stage blocks).
 hipError_t launch_batch_insert(const BatchTables* tab, const BatchGrid& g,
-                               unsigned long long* stamps, unsigned int* done, hipStream_t s);
+                               unsigned long long* stamps, hipStream_t s);
 hipError_t launch_batch_export(const BatchTables* tab, const BatchGrid& g,
-                               unsigned long long* stamps, unsigned int* done, hipStream_t s);
+                               unsigned long long* stamps, hipStream_t s);
 int surface_tile();
 size_t surface_lds(int H);
 size_t lut_lds(int nz);

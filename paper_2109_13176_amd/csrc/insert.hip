@@ -455,15 +455,14 @@ __device__ __forceinline__ int find_map(const int32_t* pre, int n, int vb) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_b_clear(const BatchTables* __restrict__ t,
-                                                    unsigned long long* stamps,
-                                                    unsigned int* done) {
+                                                    unsigned long long* stamps) {
   const int n = t->st.nmaps;
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   if (gid == 0) stamps[0] = wall_clock64();
   constexpr int kWords = 8 + kStripes;
   for (int64_t i = gid; i < (int64_t)n * kWords; i += stride) t->ins[i / kWords].stats[i % kWords] = 0;
-  for (int64_t i = gid; i < n; i += stride) done[i] = 0;
+  for (int64_t i = gid; i < n; i += stride) stamps[1 + i] = 0;  // per-map completion maxima
   for (int m = 0; m < n; m++) clear_body(t->clr[m], gid, stride);
 }
 
@@ -522,8 +521,8 @@ hipError_t launch_clear(const ClearArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_batch_insert(const BatchTables* tab, const BatchGrid& g,
-                               unsigned long long* stamps, unsigned int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_b_clear, dim3(g.clear), dim3(kBlock), 0, s, tab, stamps, done);
+                               unsigned long long* stamps, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_clear, dim3(g.clear), dim3(kBlock), 0, s, tab, stamps);
   hipLaunchKernelGGL(k_b_rays, dim3(g.rays), dim3(kRayBlock), 0, s, tab);
   hipLaunchKernelGGL(k_b_trace, dim3(g.trace), dim3(kBlock), 0, s, tab);
   hipLaunchKernelGGL(k_b_box_fold, dim3(g.fold), dim3(kBlock), 0, s, tab);
