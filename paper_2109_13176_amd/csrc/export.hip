@@ -495,13 +495,16 @@ __device__ __forceinline__ void lut_write_body(const LutArgs& a, const uint32_t 
         v[e] = -1 - p4[e];
       }
     }
+    // the table is written once and not read back here: streaming stores
     int32_t* __restrict__ lut = a.lut + slut[t] + z0;
     if (vec) {
-      *(int4*)lut = make_int4(v[0], v[1], v[2], v[3]);
+      typedef int32_t v4i __attribute__((ext_vector_type(4)));
+      const v4i vv = {v[0], v[1], v[2], v[3]};
+      __builtin_nontemporal_store(vv, (v4i*)lut);
     } else {
 #pragma unroll
       for (int e = 0; e < 4; e++)
-        if (z0 + e < nz) lut[e] = v[e];
+        if (z0 + e < nz) __builtin_nontemporal_store(v[e], lut + e);
     }
   }
 }
