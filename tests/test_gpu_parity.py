@@ -57,6 +57,29 @@ def test_shapes_and_distinct_counts(dims, traversal):
         pair.close()
 
 
+@pytest.mark.parametrize("corner", [(1, 1, 1), (62, 1, 30), (1, 62, 16), (62, 62, 2), (32, 32, 16)])
+@pytest.mark.parametrize("distinct", [False, True])
+def test_sensor_box_near_window_edges(corner, distinct):
+    """The segmented traversal sums the passes next to the sensor on chip (a
+    17 x 17 x 9 box moved inside the window): with the sensor one voxel from
+    a corner of a 64 x 64 x 32 window the box is clamped on every axis.  Two
+    dense scans per placement, no recentring, every count against the
+    oracle."""
+    rng = np.random.default_rng(7000 + 97 * corner[0] + 13 * corner[1] + corner[2])
+    res = 0.25
+    pair = Pair(params(64, 64, 32, res, szv=16))
+    try:
+        org = pair.g.origin()
+        t = [(corner[k] + int(org[k]) + 0.5) * res for k in range(3)]
+        for k in range(2):
+            pose = scenegen.pose12(_rot(*(rng.uniform(-np.pi, np.pi, 3) * [1, 0.2, 0.2])), t)
+            pts = _cloud(rng, 6000, 9.0)
+            assert pair.insert(pts, pose, 2 if distinct else 0) == 0
+            compare_all(pair, distinct=distinct)
+    finally:
+        pair.close()
+
+
 @pytest.mark.parametrize("traversal", [1, 2])
 def test_single_scan_16beam_scene(traversal):
     w = scenegen.single_scan_16beam(seed=1)
