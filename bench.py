@@ -63,7 +63,7 @@ def read_summary(name):
     out = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
+            k, v = line.rsplit(":", 1)  # keys may hold a colon ("sha256[:16]")
             out[k.strip()] = v.strip()
     return out
 
@@ -74,6 +74,16 @@ def source_sha(paths):
     for p in paths:
         h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
+
+
+def measured_line_requests():
+    """Atomic line requests per traversal phase (TCC_ATOMIC of the traversal
+    and the sensor-box fold) from the committed PMC summary, or None when the
+    kernel source changed since the counters were taken."""
+    s = read_summary("atomics_seq64.txt")
+    if not s or s.get("kernel sources sha256[:16]") != source_sha(TRACE_SRCS):
+        return None
+    return float(s["line requests per traversal phase"])
 
 
 def measured_traffic():
@@ -117,8 +127,24 @@ def calibrate():
     e1.record()
     torch.cuda.synchronize()
     t2 = e0.elapsed_time(e1) / reps * 1e-3
+    # the same number of adds, but each aligned run of 16 consecutive indices
+    # covers one random 64-byte line (atomics are charged per line request)
+    lines = torch.randint(0, tgt.numel() // 16, (idx.numel() // 16, 1), device="cuda")
+    idx16 = (lines * 16 + torch.arange(16, device="cuda")).reshape(-1)
+    for _ in range(2):
+        tgt.scatter_add_(0, idx16, one)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        tgt.scatter_add_(0, idx16, one)
+    e1.record()
+    torch.cuda.synchronize()
+    t3 = e0.elapsed_time(e1) / reps * 1e-3
     out = {"copy_bytes_per_launch": 2 * n * 4, "copy_GBps": copy_gbs,
-           "scatter_atomics_per_launch": idx.numel(), "scatter_atomics_per_s": idx.numel() / t2}
+           "scatter_atomics_per_launch": idx.numel(), "scatter_atomics_per_s": idx.numel() / t2,
+           "line_scatter_lines_per_launch": idx16.numel() // 16,
+           "line_scatter_atomics_per_s": idx16.numel() / t3,
+           "line_scatter_lines_per_s": idx16.numel() / 16 / t3}
     print(json.dumps(out), flush=True)
 
 
@@ -285,14 +311,20 @@ def main():
             "frac": phases[dom]["gbps"] / HBM_PEAK_GBS,
             "traffic": measured_traffic() if dom == "trace" and args.traversal != 1 else None}
     if dom == "trace":
-        # co-reported: global pass updates per second against the measured
-        # rate of scattered int32 atomics (torch scatter_add on this GPU)
-        upd = avg["n_pass_updates"] / (phases["trace"]["avg_ms"] * 1e-3)
+        # co-reported atomic roofline: device atomics are charged per line
+        # request (TCC_ATOMIC), and random int32 scatter (torch scatter_add on
+        # this GPU) issues exactly one line request per add, so its rate is the
+        # measured line-request peak
+        t_tr = phases["trace"]["avg_ms"] * 1e-3
         cal = read_summary("calibration_mi355x.txt")
         peak = float(cal["scatter atomics per s"]) if cal else None
-        roof["atomics"] = {"achieved": upd, "peak": peak, "unit": "updates/s",
-                           "frac": upd / peak if peak else None,
-                           "updates_per_launch": avg["n_pass_updates"]}
+        lr = measured_line_requests() if args.traversal != 1 else None
+        roof["atomics"] = {"achieved": lr / t_tr if lr else None, "peak": peak,
+                           "unit": "line requests/s",
+                           "frac": lr / t_tr / peak if (lr and peak) else None,
+                           "line_requests_per_launch": lr,
+                           "updates_per_launch": avg["n_pass_updates"],
+                           "updates_per_s": avg["n_pass_updates"] / t_tr}
 
     out = {
         "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": K,

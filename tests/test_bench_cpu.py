@@ -1,0 +1,41 @@
+"""bench.py's host logic (no GPU): the committed profile summaries parse, and
+the contract for more than one GPU fails with a message."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_profile_summaries_parse():
+    """Keys may contain a colon ("sha256[:16]"); every number the bench reads
+    from a committed summary parses, and the hash field is a 16-digit hex."""
+    for name, keys in (("trace_seq64_traffic.txt", ["hbm bytes per launch",
+                                                     "algorithmic bytes per launch (8 x distinct passed voxels)"]),
+                       ("atomics_seq64.txt", ["line requests per traversal phase"]),
+                       ("calibration_mi355x.txt", ["copy GB/s", "scatter atomics per s"])):
+        s = bench.read_summary(name)
+        assert s is not None, name
+        for k in keys:
+            assert float(s[k]) > 0, (name, k)
+        if name != "calibration_mi355x.txt":
+            h = s["kernel sources sha256[:16]"]
+            assert len(h) == 16 and int(h, 16) >= 0
+
+
+def test_line_requests_below_updates():
+    """A line request carries at least one update: the recorded traversal
+    line requests cannot exceed its run-merged updates."""
+    s = bench.read_summary("atomics_seq64.txt")
+    lr = float(s["line requests per traversal phase"])
+    upd = float(s["pass updates per launch (run-merged, outside the sensor box)"])
+    assert 0 < lr <= upd
+
+
+def test_multi_gpu_request_exits_with_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "single GPU" in (r.stdout + r.stderr)
