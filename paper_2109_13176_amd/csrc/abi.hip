@@ -357,7 +357,8 @@ int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* p
                        uint32_t flags, const int32_t S[3], gvom::InsertArgs* a,
                        gvom::ClearArgs* plan, bool* full, bool single) {
   // ray block b writes its segments into the region of stripe b mod kStripes,
-  // sized for the most segments that stripe's points can produce
+  // sized for the most segments that stripe's waves can reserve (64 slots per
+  // segment index of a wave, full waves also for the partial last block)
   const int64_t bin_blocks = (n + gvom::kRayBinBlock - 1) / gvom::kRayBinBlock;
   const bool binned =
       single && m->traversal == 1 && m->bin_cnt && bin_blocks <= gvom::kMaxEnt;
@@ -369,9 +370,7 @@ int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* p
   for (int t = 0; t < gvom::kStripes; t++) {
     const int64_t blocks =
         ray_blocks > t ? (ray_blocks - t + gvom::kStripes - 1) / gvom::kStripes : 0;
-    int64_t pts = blocks * rb;
-    if (blocks && t == (ray_blocks - 1) % gvom::kStripes)
-      pts -= ray_blocks * rb - n;  // the last block is partial
+    const int64_t pts = blocks * rb;
     a->stripe_off[t] = need;
     a->stripe_cap[t] = pts * per_ray;
     need += a->stripe_cap[t];

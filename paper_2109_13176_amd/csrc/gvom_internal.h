@@ -79,7 +79,7 @@ struct InsertArgs {
   uint32_t* touch;             // distinct-voxel bitmaps [2][V/32] or null
   unsigned long long* part_rays;   // per ray block: nonfinite, range, hits, distinct hits
   unsigned long long* part_trace;  // per trace block: passes, distinct passes, updates, 0
-  int4* items;                 // ray segments {Qx, Qy, Qz, segment index}
+  int4* items;                 // ray segments {Qx, Qy, Qz, segment index}; index < 0: empty slot
   int64_t item_cap;
   int64_t stripe_off[kStripes];  // item region of each stripe of ray blocks
   int64_t stripe_cap[kStripes];

@@ -20,8 +20,11 @@ constexpr int kBlock = 256;
 // segment j holds the path voxels whose dominant coordinate lies j*seg_len ..
 // (j+1)*seg_len - 1 voxels from the sensor's.  Only segments that start
 // inside the window along the dominant axis are emitted.  A wave reserves
-// room for all its segments with one atomic and writes them segment-major,
-// so that consecutive items are the same segment of neighbouring rays.
+// 64 slots per segment index (up to its longest ray) and writes segment j of
+// lane i to slot 64 j + i, an empty item where the ray has no segment j: a
+// traversal wave then holds exactly one segment index of 64 neighbouring
+// rays, so their voxels share cache lines (fewer atomic line requests than
+// packed items, which let waves straddle two segment indices).
 template <bool DISTINCT>
 __device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
   __shared__ unsigned int wcount[kRayBlock / 64][5];
@@ -53,12 +56,10 @@ __device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
 
   // reserve and write the segments, segment-major within the wave: one
   // returning atomic per block, wave bases from the block's prefix
-  int total = nseg;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o);
   int maxseg = nseg;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) maxseg = max(maxseg, __shfl_xor(maxseg, o));
+  const int total = maxseg * 64;
   const int c0 = __popcll(__ballot(nonfinite));
   const int c1 = __popcll(__ballot(outrange));
   const int c2 = __popcll(__ballot(hit));
@@ -94,13 +95,8 @@ __device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
   __syncthreads();
   unsigned long long off = wbase[wv];
   for (int j = 0; j < maxseg; j++) {
-    const unsigned long long m = __ballot(nseg > j);
-    if (nseg > j) {
-      const unsigned long long pos =
-          off + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
-      a.items[pos] = make_int4(q[0], q[1], q[2], j);
-    }
-    off += __popcll(m);
+    a.items[off + lane] = nseg > j ? make_int4(q[0], q[1], q[2], j) : make_int4(0, 0, 0, -1);
+    off += 64;
   }
 }
 
@@ -182,7 +178,7 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
         if (it >= s_pre[t + step]) t += step;
       const int4 item = a.items[s_base[t] + it];
       const int32_t q[3] = {item.x, item.y, item.z};
-      const int j = item.w;
+      const int j = item.w < 0 ? 0 : item.w;  // w < 0: empty slot
       int32_t sv[3], n[3], sg[3], ad[3];
 #pragma unroll
       for (int k = 0; k < 3; k++) {
@@ -196,7 +192,7 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
       const int dom = dominant_axis(n);
       int32_t v[3] = {sv[0], sv[1], sv[2]};
       if (j > 0) entry_voxel(a.S, sg, ad, dom, sv[dom] + sg[dom] * j * a.seg_len, v);
-      bool inside = true;
+      bool inside = item.w >= 0;
       int32_t l[3];
 #pragma unroll
       for (int k = 0; k < 3; k++) {
