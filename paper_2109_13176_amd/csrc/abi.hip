@@ -332,20 +332,30 @@ int32_t check_insert(const map_t* m, const float* xyz_dev, int64_t n, const floa
 }
 
 // Grows a device buffer (synchronising first); false on allocation failure.
+// A regrow at least doubles the capacity (exactly `need` if that fails), so
+// scans of growing size reallocate O(log) times: a free synchronises the
+// device and would otherwise stall every step that sees a new largest scan.
 template <class T>
 bool grow(map_t* m, T** p, int64_t* cap, int64_t need, size_t elem) {
   if (need <= *cap) return true;
   if (hipStreamSynchronize(m->stream) != hipSuccess) return false;
+  const int64_t want = *cap > 0 && need < 2 * *cap ? 2 * *cap : need;
   (void)hipFree(*p);
   *p = nullptr;
   *cap = 0;
-  if (dmalloc(p, (size_t)need * elem) != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return false;
+  if (dmalloc(p, (size_t)want * elem) == hipSuccess) {
+    *cap = want;
+    return true;
   }
-  *cap = need;
-  return true;
+  (void)hipGetLastError();
+  *p = nullptr;
+  if (want > need && dmalloc(p, (size_t)need * elem) == hipSuccess) {
+    *cap = need;
+    return true;
+  }
+  (void)hipGetLastError();
+  *p = nullptr;
+  return false;
 }
 
 // Second half of an insert (after check_insert): grows the per-scan buffers,
@@ -835,11 +845,21 @@ int32_t batch_check(map_batch_t* b, const float* const* xyz_dev, const int64_t* 
     const int32_t s = check_insert(b->maps[i], xyz_dev[i], n[i], poses + 12 * i, flags[i], S[i]);
     if (s) return s;
   }
-  for (int i = 0; i < b->k; i++)
-    if (hipStreamSynchronize(b->maps[i]->stream) != hipSuccess) {
+  // work the caller enqueued on the maps' own streams finishes first (each
+  // distinct stream is waited for once)
+  hipStream_t seen[gvom::kMaxBatch];
+  int ns = 0;
+  for (int i = 0; i < b->k; i++) {
+    const hipStream_t st = b->maps[i]->stream;
+    bool dup = false;
+    for (int j = 0; j < ns && !dup; j++) dup = seen[j] == st;
+    if (dup) continue;
+    seen[ns++] = st;
+    if (hipStreamSynchronize(st) != hipSuccess) {
       batch_fail(b);
       return MAP_E_DEVICE;
     }
+  }
   return MAP_OK;
 }
 
