@@ -289,6 +289,7 @@ int32_t map_reset(map_t* m) {
   (void)hipGetLastError();
   m->sticky = MAP_OK;
   initial_origin(m);
+  m->lut_counted = false;
   m->last_points = 0;
   m->last_cleared = 0;
   m->last_distinct = false;
@@ -472,7 +473,8 @@ int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* p
   return MAP_OK;
 }
 
-void column_args(const map_t* m, const map_2d_t* out, gvom::ColumnArgs* ca) {
+// ranks: also write the table export's per-column ranks (single-map export)
+void column_args(const map_t* m, const map_2d_t* out, bool ranks, gvom::ColumnArgs* ca) {
   ca->d = m->d;
   ca->hits = m->hits;
   ca->passes = m->passes;
@@ -487,6 +489,8 @@ void column_args(const map_t* m, const map_2d_t* out, gvom::ColumnArgs* ca) {
   ca->density = out->density;
   ca->flags = out->flags;
   ca->hq = m->hq;
+  ca->colpre = ranks ? m->colpre : nullptr;
+  ca->block_base = ranks ? m->block_base : nullptr;
 }
 
 void surface_args(const map_t* m, const map_2d_t* out, gvom::SurfaceArgs* sa) {
@@ -533,6 +537,7 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
   gvom::InsertArgs a;
   gvom::ClearArgs plan;
   bool full = false;
+  m->lut_counted = false;
   const int pm0 = prof_begin(m, MAP_PROF_SCROLL);
   st = prepare_insert(m, xyz_dev, n, pose, flags, S, &a, &plan, &full, true);
   if (st) return st;
@@ -564,10 +569,11 @@ int32_t map_export_2d(map_t* m, const map_2d_t* out) {
   if (!m || !valid_2d(out)) return MAP_E_INVALID;
   if (m->sticky) return m->sticky;
   gvom::ColumnArgs ca;
-  column_args(m, out, &ca);
+  column_args(m, out, true, &ca);
   int pm = prof_begin(m, MAP_PROF_COLUMN);
   hipError_t e = gvom::launch_column(ca, m->stream);
   prof_end(m, pm);
+  m->lut_counted = e == hipSuccess;
   if (e == hipSuccess) {
     gvom::SurfaceArgs sa;
     surface_args(m, out, &sa);
@@ -586,7 +592,10 @@ int32_t map_export_voxels(map_t* m, int32_t* lut_dev, map_voxel_t* data_dev, int
   gvom::LutArgs a;
   lut_args(m, lut_dev, data_dev, cap, n_occupied_dev, &a);
   const int pm = prof_begin(m, MAP_PROF_LUT);
-  hipError_t e = gvom::launch_lut(a, m->stream);
+  // the ranks of a 2D export since the last change of the map are reused
+  // (the scan below turns block_base into prefixes: a later export recounts)
+  hipError_t e = gvom::launch_lut(a, m->lut_counted, m->stream);
+  m->lut_counted = false;
   prof_end(m, pm);
   for (int i = 0; i < 3; i++) origin_vox[i] = m->origin[i];
   return dev_status(m, e);
@@ -599,6 +608,7 @@ int32_t map_import_voxels(map_t* m, const int32_t* lut_dev, const map_voxel_t* d
   if (m->sticky) return m->sticky;
   for (int i = 0; i < 3; i++) m->origin[i] = origin_vox[i];
   set_ring(m);
+  m->lut_counted = false;
   int32_t err = 0;
   hipError_t e = hipMemsetAsync(m->err, 0, 4, m->stream);
   if (e == hipSuccess)
@@ -770,7 +780,8 @@ int32_t batch_prepare(map_batch_t* b, const float* const* xyz_dev, const int64_t
     const int32_t s = prepare_insert(m, xyz_dev[i], n[i], poses + 12 * i, flags[i], S[i],
                                      &t->ins[i], &t->clr[i], &full, false);
     if (s) return s;  // allocation failure
-    column_args(m, &out2d[i], &t->col[i]);
+    column_args(m, &out2d[i], false, &t->col[i]);
+    m->lut_counted = false;
     surface_args(m, &out2d[i], &t->sur[i]);
     const bool lut = lut_dev && lut_dev[i];
     if (lut) {

@@ -55,14 +55,37 @@ __device__ __forceinline__ int rank_below(const Mask128& m, int z) {
 // the occupied voxels n_lo..n_hi above the ground voxel; its density is
 // sum(hits) / sum(hits + passes); hard iff that ratio exceeds num/den
 // (compared exactly in integers), soft otherwise.
+// With a.colpre set it also does the table export's counting pass (the
+// occupied voxels of every column, ranked within its group of 64 columns;
+// see lut_count_body), from the occupancy mask it loads anyway.
+__device__ __forceinline__ void column_counts(const ColumnArgs& a, const int c, const int cnt) {
+  const int lane = __lane_id();
+  int incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(incl, o);
+    if (lane >= o) incl += u;
+  }
+  const int C = a.d.nx * a.d.ny;
+  if (c < C) a.colpre[c] = incl - cnt;
+  if (lane == 63 && (c >> 6) * 64 < C) a.block_base[c >> 6] = incl;
+}
+
 __device__ __forceinline__ void column_body(const ColumnArgs& a, const int blk) {
   const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
   const int c = blk * kBlock + threadIdx.x;
-  if (c >= nx * ny) return;
-  const int x = c / ny, y = c - x * ny;
-  const int sx = wrap_add(x + a.d.ro[0], nx), sy = wrap_add(y + a.d.ro[1], ny);
-  const int64_t scol = (int64_t)sx * ny + sy;
-  const Mask128 m = local_mask(a.occ, scol, a.d.W, nz, a.d.ro[2]);
+  const bool valid = c < nx * ny;
+  int sx = 0, sy = 0;
+  Mask128 m = {0ull, 0ull};
+  if (valid) {
+    const int x = c / ny, y = c - x * ny;
+    sx = wrap_add(x + a.d.ro[0], nx);
+    sy = wrap_add(y + a.d.ro[1], ny);
+    m = local_mask(a.occ, (int64_t)sx * ny + sy, a.d.W, nz, a.d.ro[2]);
+  }
+  // every lane of the wave takes part in the rank scan
+  if (a.colpre) column_counts(a, c, __popcll(m.lo) + __popcll(m.hi));
+  if (!valid) return;
   const int kg = lowest_bit(m);
   float height = __uint_as_float(kQNaN), density = __uint_as_float(kQNaN);
   int32_t hq = INT32_MIN;
@@ -721,14 +744,15 @@ hipError_t launch_surface(const SurfaceArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_lut(const LutArgs& a, hipStream_t s) {
+hipError_t launch_lut(const LutArgs& a, bool counted, hipStream_t s) {
   const int C = a.d.nx * a.d.ny;
   const int ng = (C + kGroup - 1) / kGroup;
   // b / nz == umulhi(b, ceil(2^32 / nz)) for every b < 2^20 (here b < 4 * 128)
   const uint32_t magic =
       a.d.nz > 1 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)a.d.nz - 1) / (uint64_t)a.d.nz) : 0u;
   const size_t lds = lut_lds(a.d.nz);
-  hipLaunchKernelGGL(k_lut_count, dim3((C + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+  if (!counted)
+    hipLaunchKernelGGL(k_lut_count, dim3((C + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_lut_scan, dim3(1), dim3(1024), 0, s, a.block_base, ng, a.n_occupied);
   dim3 g((a.d.nx + 3) / 4, (a.d.nby + 3) / 4);
   hipLaunchKernelGGL(k_lut_write, g, dim3(kBlock), lds, s, a, magic);

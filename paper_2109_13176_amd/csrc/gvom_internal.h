@@ -132,6 +132,8 @@ struct ColumnArgs {
   float* density;
   uint8_t* flags;
   int32_t* hq;            // ground height Q per local pixel, INT32_MIN = undefined
+  int32_t* colpre;        // null, or the table export's counting pass (see LutArgs)
+  int32_t* block_base;
 };
 
 struct SurfaceArgs {
@@ -229,7 +231,8 @@ hipError_t launch_rays_bin(const InsertArgs& a, bool distinct, hipStream_t s);
 hipError_t launch_trace_bin(const InsertArgs& a, bool distinct, hipStream_t s);
 hipError_t launch_column(const ColumnArgs& a, hipStream_t s);
 hipError_t launch_surface(const SurfaceArgs& a, hipStream_t s);
-hipError_t launch_lut(const LutArgs& a, hipStream_t s);
+// counted: the column pass already wrote colpre / block_base for this state
+hipError_t launch_lut(const LutArgs& a, bool counted, hipStream_t s);
 hipError_t launch_import(const Dims& d, const int32_t* lut, const map_voxel_t* data,
                          int64_t n_data, int32_t* hits, int32_t* passes, int32_t* minqz,
                          unsigned long long* occ, int32_t* err, hipStream_t s);

@@ -45,6 +45,9 @@ struct map_t {
   int64_t last_points, last_cleared;
   bool last_distinct;
   int32_t prof_mask;          // profiled phases (bit p = phase p)
+  // the last 2D export left the table export's per-column ranks (colpre,
+  // block_base) for the current map state; any change of the map clears it
+  bool lut_counted;
   struct Mark {
     int phase;
     hipEvent_t a, b;

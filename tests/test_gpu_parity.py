@@ -80,6 +80,26 @@ def test_sensor_box_near_window_edges(corner, distinct):
         pair.close()
 
 
+def test_table_export_reuses_2d_export_ranks():
+    """After a 2D export the table export reuses the per-column ranks the
+    column pass wrote; a second table export, or one after another insert,
+    counts again.  Every table against the oracle."""
+    rng = np.random.default_rng(4242)
+    pair = Pair(params(40, 36, 20, 0.3))
+    try:
+        for k in range(3):
+            pose = scenegen.pose12(_rot(rng.uniform(-np.pi, np.pi), 0.05, -0.03),
+                                   rng.uniform(-1, 1, 3) * 0.6)
+            assert pair.insert(_cloud(rng, 5000, 8.0), pose, 1) == 0  # MAP_RECENTER
+            if k == 1:
+                compare_voxels(pair)      # no 2D export since the insert: counted here
+            compare_2d(pair)              # writes the ranks
+            compare_voxels(pair)          # reuses them
+            compare_voxels(pair)          # the scan consumed them: counted again
+    finally:
+        pair.close()
+
+
 @pytest.mark.parametrize("traversal", [1, 2])
 def test_single_scan_16beam_scene(traversal):
     w = scenegen.single_scan_16beam(seed=1)
