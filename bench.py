@@ -140,7 +140,20 @@ def calibrate():
     e1.record()
     torch.cuda.synchronize()
     t3 = e0.elapsed_time(e1) / reps * 1e-3
+    # the same random adds into a 2 MiB array (L2-resident footprint)
+    small = torch.zeros(512 << 10, dtype=torch.int32, device="cuda")
+    idx_s = torch.randint(0, small.numel(), (idx.numel(),), device="cuda")
+    for _ in range(2):
+        small.scatter_add_(0, idx_s, one)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        small.scatter_add_(0, idx_s, one)
+    e1.record()
+    torch.cuda.synchronize()
+    t4 = e0.elapsed_time(e1) / reps * 1e-3
     out = {"copy_bytes_per_launch": 2 * n * 4, "copy_GBps": copy_gbs,
+           "scatter_l2_atomics_per_s": idx_s.numel() / t4,
            "scatter_atomics_per_launch": idx.numel(), "scatter_atomics_per_s": idx.numel() / t2,
            "line_scatter_lines_per_launch": idx16.numel() // 16,
            "line_scatter_atomics_per_s": idx16.numel() / t3,
@@ -293,6 +306,26 @@ def main():
     pcie_elapsed = time.perf_counter() - t0
     m.close()
 
+    # the narrower units: insert alone (points ingested) and insert + 2D
+    # export (a map update without the voxel table), each on a fresh map
+    def timed(fn):
+        mm = gvom.VoxelMap(params)
+        if args.traversal:
+            gvom.map_set_tuning(mm.h, traversal=args.traversal)
+        for k in range(W):
+            fn(mm, k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(W, W + K):
+            fn(mm, k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        mm.close()
+        return dt
+
+    t_insert = timed(lambda mm, k: mm.insert(scans[k], poses[k], flags))
+    t_insert_2d = timed(lambda mm, k: (mm.insert(scans[k], poses[k], flags), mm.export_2d()))
+
     n_points = sum(int(scans[k].shape[0]) for k in range(W, W + K))
     value = n_points / elapsed
     updates = K / elapsed
@@ -326,6 +359,19 @@ def main():
                            "updates_per_launch": avg["n_pass_updates"],
                            "updates_per_s": avg["n_pass_updates"] / t_tr}
 
+    # whole-path HBM fractions with the counted minimum bytes: the ray cast
+    # moves 12 N + 16 U_h + 8 U_p, the exports 4 V (table) + 12 M + 17 C
+    V = params["nx"] * params["ny"] * params["nz"]
+    C = params["nx"] * params["ny"]
+    n_scan = n_points / K
+    b_rc = 12 * n_scan + 16 * avg["n_distinct_hit"] + 8 * avg["n_distinct_pass"]
+    b_ex = 4 * V + 12 * n_occ + 17 * C
+    t_rc = t_insert / K
+    path_hbm = {"ray_cast": {"bytes": b_rc, "us": t_rc * 1e6,
+                             "frac": b_rc / t_rc / (HBM_PEAK_GBS * 1e9)},
+                "step": {"bytes": b_rc + b_ex, "us": elapsed / K * 1e6,
+                         "frac": (b_rc + b_ex) / (elapsed / K) / (HBM_PEAK_GBS * 1e9)}}
+
     out = {
         "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True,
@@ -336,7 +382,10 @@ def main():
                    "points_per_scan": int(scans[0].shape[0]), "map": [512, 512, 64],
                    "res_m": 0.2, "scans_timed": K},
         "updates_per_s": updates,
+        "insert_only_points_per_s": n_points / t_insert,
+        "insert_2d_updates_per_s": K / t_insert_2d,
         "pcie_inclusive_points_per_s": n_points / pcie_elapsed,
+        "path_hbm": path_hbm,
         "phases": phases,
         "per_scan": {"pass_incidences": avg["n_pass"], "distinct_passed": avg["n_distinct_pass"],
                      "distinct_hit": avg["n_distinct_hit"], "hits": avg["n_hits"],
