@@ -75,6 +75,7 @@ def lib():
         L.orc_import_voxels.argtypes = [P, P, P, ctypes.c_int64, P]
         L.orc_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
         L.orc_get_origin.argtypes = [P, P]
+        L.orc_combine.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(P), P]
         L.orc_transform_point.argtypes = [P, ctypes.c_float, P, P]
         L.orc_ray_voxels.argtypes = [P, P, P, ctypes.c_int64]
         L.orc_ray_voxels.restype = ctypes.c_int64
@@ -90,7 +91,7 @@ def lib():
         for f in ("orc_sgt_forward", "orc_sgt_loss_grad", "orc_sgt_fill"):
             getattr(L, f).restype = ctypes.c_int32
         for f in ("orc_derive", "orc_create", "orc_reset", "orc_insert_scan", "orc_export_2d",
-                  "orc_export_voxels", "orc_import_voxels", "orc_get_stats", "orc_get_origin",
+                  "orc_export_voxels", "orc_import_voxels", "orc_get_stats", "orc_get_origin", "orc_combine",
                   "orc_transform_point", "orc_surface"):
             getattr(L, f).restype = ctypes.c_int32
         _lib = L
@@ -214,3 +215,57 @@ class OracleMap:
         o = np.zeros(3, np.int32)
         lib().orc_get_origin(self._h, _ptr(o))
         return o
+
+
+class OracleBuffer:
+    """The map buffer of Sec. III-B and the combine step of Sec. III-D.
+
+    Pointcloud processing turns each scan into its own voxel map (III-C: a
+    fresh window, this scan's hits, misses and lowest returns only), exported
+    as (lookup table, data array, origin) and appended to the buffer; the
+    buffer keeps the ``depth`` most recent maps.  A scan pushed with RECENTER
+    gets a window centred on its sensor; otherwise it takes the window of the
+    most recent buffered map (several lidars feeding one map), or the initial
+    window while the buffer is empty.  ``combine`` writes the combination of
+    the buffered maps into an OracleMap (``orc_combine``).
+    """
+
+    def __init__(self, params: dict, depth: int):
+        if depth < 1:
+            raise ValueError("depth must be >= 1")
+        self.params = dict(params)
+        self.depth = depth
+        self.maps = []  # (lut, data, origin), oldest first
+        self._scan = OracleMap(params)
+
+    def close(self):
+        self._scan.close()
+
+    def push(self, xyz, pose, flags: int = 0) -> int:
+        m = self._scan
+        m.reset()
+        if not (flags & RECENTER) and self.maps:
+            V = m.nx * m.ny * m.nz
+            s = m.import_voxels(np.full(V, -1, np.int32), np.zeros((0, 3), np.int32),
+                                self.maps[-1][2])
+            assert s == OK
+        s = m.insert_scan(xyz, pose, flags & RECENTER)
+        if s:
+            return s
+        s, lut, data, _, origin = m.export_voxels()
+        assert s == OK
+        self.maps.append((lut, np.ascontiguousarray(data), origin.copy()))
+        if len(self.maps) > self.depth:
+            self.maps.pop(0)
+        return OK
+
+    def combine(self, out: OracleMap) -> int:
+        k = len(self.maps)
+        if k == 0:
+            return E_INVALID
+        P = ctypes.c_void_p
+        keep = [d if d.size else np.zeros((1, 3), np.int32) for _, d, _ in self.maps]
+        luts = (P * k)(*[lut.ctypes.data for lut, _, _ in self.maps])
+        datas = (P * k)(*[d.ctypes.data for d in keep])
+        origins = np.ascontiguousarray(np.stack([o for _, _, o in self.maps]), dtype=np.int32)
+        return lib().orc_combine(out._h, k, luts, datas, _ptr(origins))

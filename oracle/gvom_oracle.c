@@ -686,6 +686,52 @@ int32_t orc_import_voxels(orc_map* m, const int32_t* lut, const int32_t* data,
   return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* III-B / III-D: map processing starts by combining the buffered per-scan
+ * maps (each a III-A lookup table + data array + origin, in the format that
+ * orc_export_voxels writes) into one map.  The combined map takes the origin
+ * of the most recent buffered map, which is the last one given.  Every voxel
+ * of the combined window is looked up in each buffered map by offsetting its
+ * index with the difference of the two origins; where that map's window holds
+ * the voxel, hits and misses are added (the misses of a free voxel are
+ * -1 - lut) and, for an occupied entry, its lowest return takes part in the
+ * minimum.  Voxels that no buffered window holds are empty.  The window size
+ * of every buffered map is the one of `out`.                                */
+int32_t orc_combine(orc_map* out, int32_t k, const int32_t* const* luts,
+                    const int32_t* const* datas, const int32_t* origins) {
+  if (!out || k < 1 || !luts || !datas || !origins) return ORC_E_INVALID;
+  const int32_t* o = &origins[3 * (k - 1)];
+  for (int64_t x = 0; x < out->p.nx; x++)
+    for (int64_t y = 0; y < out->p.ny; y++)
+      for (int64_t z = 0; z < out->p.nz; z++) {
+        int32_t hits = 0, passes = 0, minqz = INT32_MAX;
+        for (int32_t j = 0; j < k; j++) {
+          const int32_t* oj = &origins[3 * j];
+          /* the same world voxel, in window coordinates of buffered map j */
+          const int64_t xj = o[0] + x - oj[0], yj = o[1] + y - oj[1], zj = o[2] + z - oj[2];
+          if (!inside(out, xj, yj, zj)) continue;
+          const int32_t e = luts[j][lin(out, xj, yj, zj)];
+          if (e >= 0) {
+            const int32_t* d = &datas[j][3 * (int64_t)e];
+            hits += d[0];
+            passes += d[1];
+            if (d[2] < minqz) minqz = d[2];
+          } else {
+            passes += -1 - e;
+          }
+        }
+        const int64_t i = lin(out, x, y, z);
+        out->hits[i] = hits;
+        out->passes[i] = passes;
+        out->minqz[i] = minqz;
+      }
+  out->origin[0] = o[0];
+  out->origin[1] = o[1];
+  out->origin[2] = o[2];
+  memset(&out->st, 0, sizeof(out->st));
+  return ORC_OK;
+}
+
 int32_t orc_get_stats(const orc_map* m, orc_stats* out) {
   if (!m || !out) return ORC_E_INVALID;
   *out = m->st;

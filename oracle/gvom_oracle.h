@@ -63,6 +63,9 @@ int32_t orc_export_voxels(orc_map* m, int32_t* lut, int32_t* data /* [cap][3] */
                           int64_t cap, int64_t* n_occupied, int32_t origin[3]);
 int32_t orc_import_voxels(orc_map* m, const int32_t* lut, const int32_t* data /* [n][3] */,
                           int64_t n_data, const int32_t origin[3]);
+int32_t orc_combine(orc_map* out, int32_t k, const int32_t* const* luts,
+                    const int32_t* const* datas /* [k] of [n][3] */,
+                    const int32_t* origins /* [k][3], oldest first */);
 int32_t orc_get_stats(const orc_map* m, orc_stats* out);
 int32_t orc_get_origin(const orc_map* m, int32_t origin[3]);
 
