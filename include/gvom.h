@@ -231,6 +231,57 @@ int32_t map_get_tuning(const map_t* m, map_tuning_t* out);
 int32_t map_profile_enable(map_t* m, int32_t phase_mask);
 int32_t map_profile_read(map_t* m, double ms[MAP_PROF_N], int64_t count[MAP_PROF_N]);
 
+/* ---- map buffer (Sec. III-B, III-C, III-D) --------------------------------
+ * The paper's own dataflow.  Pointcloud processing turns each scan into a
+ * voxel map of its own (a fresh window holding only that scan's hits, misses
+ * and lowest returns, stored as a Sec. III-A lookup table + data array +
+ * origin) and adds it to a buffer; map processing combines the buffered maps
+ * into one map and computes the 2D maps from it.  The two sides run
+ * asynchronously: pushes on the buffer's stream, the combine and the exports
+ * on the output map's stream, ordered by events (a combine waits for the
+ * pushes enqueued before it; a push waits for the combines enqueued before it,
+ * which read the slot it overwrites).  Several lidars feed one buffer by
+ * pushing their scans in turn. */
+typedef struct map_buffer_t map_buffer_t;
+
+/* Buffer of the `depth` (1..64) most recent per-scan maps of the window size
+ * and resolution in `p`, each slot holding a lookup table of the map's storage
+ * size (4 bytes per voxel) and a data array of 12 bytes per occupied voxel
+ * (grown to the largest scan pushed into it: a grow synchronises `stream`).
+ * Pushes are enqueued on `stream` (NULL: the default stream). */
+int32_t map_buffer_create(const map_params_t* p, int32_t depth, void* stream,
+                          map_buffer_t** out);
+/* Synchronises the buffer's stream and the combines still reading it. */
+int32_t map_buffer_destroy(map_buffer_t* b);
+/* Drops every buffered map and clears a sticky error (synchronises). */
+int32_t map_buffer_reset(map_buffer_t* b);
+
+/* Pointcloud processing of one scan (Sec. III-C) into the next slot,
+ * replacing the oldest map once `depth` are held.  Arguments as in
+ * map_insert_scan.  With MAP_RECENTER the scan's window is centred on its
+ * pose; without it the scan takes the window of the newest buffered map (the
+ * initial window while the buffer is empty), which is how a second lidar of
+ * the same vehicle joins the primary lidar's map.  Errors as map_insert_scan
+ * (the buffer is unchanged); MAP_E_OOM when a slot cannot grow. */
+int32_t map_buffer_push(map_buffer_t* b, const float* xyz_dev, int64_t n, const float pose[12],
+                        uint32_t flags);
+
+/* Map processing, first step (Sec. III-D): replaces the state of `out` with
+ * the combination of the buffered maps and sets its origin to the newest
+ * buffered map's.  Every voxel of the new window is located in each buffered
+ * map by the difference of the origins; where that map's window holds it,
+ * its hits and misses are added and its lowest return (occupied voxels) takes
+ * part in the minimum; voxels no buffered window holds are empty.  `out` must
+ * have the buffer's nx, ny, nz and res_m (its other parameters govern its own
+ * exports); map_export_2d / map_export_voxels then export the combined map.
+ * Enqueued on out's stream.  MAP_E_INVALID when the buffer is empty. */
+int32_t map_buffer_combine(map_buffer_t* b, map_t* out);
+
+/* Buffered maps (0..depth), or MAP_E_INVALID for a NULL buffer. */
+int32_t map_buffer_count(const map_buffer_t* b);
+/* Counters of the last push (as map_get_stats); synchronises the buffer's stream. */
+int32_t map_buffer_get_stats(map_buffer_t* b, map_stats_t* out);
+
 /* ---- batched serving (project extension, not in the paper) ---------------
  * Many vehicles' maps are stepped together: every stage of every map runs in
  * one persistent kernel per stage (grids sized to the device, walking the

@@ -38,6 +38,23 @@ void set_ring(map_t* m) {
   m->d.ro[2] = pos_mod(m->origin[2], m->p.nz);
 }
 
+}  // namespace
+
+namespace gvom {
+
+void set_origin(map_t* m, const int32_t o[3]) {
+  for (int i = 0; i < 3; i++) m->origin[i] = o[i];
+  set_ring(m);
+}
+
+void set_empty_origin(map_t* m, const int32_t o[3]) {
+  if (m->empty) set_origin(m, o);
+}
+
+}  // namespace gvom
+
+namespace {
+
 int32_t dev_status(map_t* m, hipError_t e) {
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -246,6 +263,7 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   }
   initial_origin(m);
   e = clear_all(m);
+  m->empty = true;
   if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, kStatsBytes, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) {
@@ -296,6 +314,7 @@ int32_t map_reset(map_t* m) {
   m->last_ray_blocks = 0;
   m->last_trace_blocks = 0;
   hipError_t e = clear_all(m);
+  m->empty = true;
   if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, kStatsBytes, m->stream);
   if (e == hipSuccess && m->bin_cnt)
     e = hipMemsetAsync(m->bin_cnt, 0, (size_t)m->nbins * 4, m->stream);
@@ -541,7 +560,9 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
   const int pm0 = prof_begin(m, MAP_PROF_SCROLL);
   st = prepare_insert(m, xyz_dev, n, pose, flags, S, &a, &plan, &full, true);
   if (st) return st;
-  hipError_t e = full ? clear_all(m) : gvom::launch_clear(plan, m->stream);
+  // an empty map moves its window without clearing anything
+  hipError_t e = m->empty ? hipSuccess : full ? clear_all(m) : gvom::launch_clear(plan, m->stream);
+  if (n > 0) m->empty = false;
   prof_end(m, pm0);
   const bool distinct = (flags & MAP_STATS_DISTINCT) != 0;
   m->last_distinct = distinct;
@@ -609,6 +630,7 @@ int32_t map_import_voxels(map_t* m, const int32_t* lut_dev, const map_voxel_t* d
   for (int i = 0; i < 3; i++) m->origin[i] = origin_vox[i];
   set_ring(m);
   m->lut_counted = false;
+  m->empty = false;
   int32_t err = 0;
   hipError_t e = hipMemsetAsync(m->err, 0, 4, m->stream);
   if (e == hipSuccess)
@@ -620,6 +642,7 @@ int32_t map_import_voxels(map_t* m, const int32_t* lut_dev, const map_voxel_t* d
   if (err) {
     initial_origin(m);
     e = clear_all(m);
+    m->empty = true;
     if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
     if (e != hipSuccess) return dev_status(m, e);
     return MAP_E_INVALID;
@@ -782,6 +805,7 @@ int32_t batch_prepare(map_batch_t* b, const float* const* xyz_dev, const int64_t
     if (s) return s;  // allocation failure
     column_args(m, &out2d[i], false, &t->col[i]);
     m->lut_counted = false;
+    m->empty = false;
     surface_args(m, &out2d[i], &t->sur[i]);
     const bool lut = lut_dev && lut_dev[i];
     if (lut) {

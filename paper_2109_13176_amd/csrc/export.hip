@@ -759,6 +759,11 @@ hipError_t launch_lut(const LutArgs& a, bool counted, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_scan_i32(int32_t* base, int nb, int64_t* total, hipStream_t s) {
+  hipLaunchKernelGGL(k_lut_scan, dim3(1), dim3(1024), 0, s, base, nb, total);
+  return hipGetLastError();
+}
+
 hipError_t launch_import(const Dims& d, const int32_t* lut, const map_voxel_t* data,
                          int64_t n_data, int32_t* hits, int32_t* passes, int32_t* minqz,
                          unsigned long long* occ, int32_t* err, hipStream_t s) {

@@ -237,5 +237,7 @@ hipError_t launch_import(const Dims& d, const int32_t* lut, const map_voxel_t* d
                          int64_t n_data, int32_t* hits, int32_t* passes, int32_t* minqz,
                          unsigned long long* occ, int32_t* err, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+// Exclusive prefix of base[0..nb) in place (one block); *total = the sum.
+hipError_t launch_scan_i32(int32_t* base, int nb, int64_t* total, hipStream_t s);
 
 }  // namespace gvom

@@ -48,10 +48,21 @@ struct map_t {
   // the last 2D export left the table export's per-column ranks (colpre,
   // block_base) for the current map state; any change of the map clears it
   bool lut_counted;
+  // every voxel is empty and every occupancy word zero (a recentring then
+  // needs no clears)
+  bool empty;
   struct Mark {
     int phase;
     hipEvent_t a, b;
   };
   std::vector<Mark> marks;
 };
+
+namespace gvom {
+// Sets the window origin (whole voxels) and its ring offsets; the voxel state
+// is not touched.
+void set_origin(map_t* m, const int32_t o[3]);
+// Same, for a map whose state is empty (no clears are needed).
+void set_empty_origin(map_t* m, const int32_t o[3]);
+}  // namespace gvom
 

@@ -64,6 +64,8 @@ EXPORTED = [
     "map_set_tuning", "map_get_tuning",
     "map_batch_create", "map_batch_destroy", "map_batch_step", "map_batch_latency",
     "map_batch_set_graph", "map_batch_autotune",
+    "map_buffer_create", "map_buffer_destroy", "map_buffer_reset", "map_buffer_push",
+    "map_buffer_combine", "map_buffer_count", "map_buffer_get_stats",
     "sgt_num_params", "sgt_create", "sgt_destroy", "sgt_get_params", "sgt_set_params",
     "sgt_set_norm", "sgt_features", "sgt_thin", "sgt_feature_sums", "sgt_forward",
     "sgt_loss_grad", "sgt_adam", "sgt_fill",
@@ -102,6 +104,13 @@ def lib() -> ctypes.CDLL:
         L.map_batch_set_graph.argtypes = [P, I32]
         L.map_batch_autotune.argtypes = [P, P, P, P, P, P, ctypes.c_char_p,
                                          ctypes.POINTER(map_tuning_t)]
+        L.map_buffer_create.argtypes = [ctypes.POINTER(map_params_t), I32, P, ctypes.POINTER(P)]
+        L.map_buffer_destroy.argtypes = [P]
+        L.map_buffer_reset.argtypes = [P]
+        L.map_buffer_push.argtypes = [P, P, I64, P, ctypes.c_uint32]
+        L.map_buffer_combine.argtypes = [P, P]
+        L.map_buffer_count.argtypes = [P]
+        L.map_buffer_get_stats.argtypes = [P, ctypes.POINTER(map_stats_t)]
         L.sgt_num_params.argtypes = []
         L.sgt_create.argtypes = [I32, I32, ctypes.c_uint64, P, ctypes.POINTER(P)]
         L.sgt_destroy.argtypes = [P]
@@ -429,6 +438,91 @@ class VoxelMap:
 
     def sync(self):
         self._check(map_sync(self.h), "map_sync")
+
+
+def map_buffer_create(params: dict, depth: int, stream=None):
+    """Returns (status, handle).  `stream` is a torch.cuda.Stream or None (current)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    h = ctypes.c_void_p()
+    s = lib().map_buffer_create(ctypes.byref(_params(params)), depth,
+                                ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+    return s, h
+
+
+def map_buffer_destroy(h) -> int:
+    return lib().map_buffer_destroy(h)
+
+
+def map_buffer_reset(h) -> int:
+    return lib().map_buffer_reset(h)
+
+
+def map_buffer_push(h, xyz, pose, flags: int = 0) -> int:
+    import torch
+    n = 0 if xyz is None else xyz.shape[0]
+    ptr = ctypes.c_void_p(0) if n == 0 else _dev(xyz, torch.float32, "xyz")
+    if n and (xyz.dim() != 2 or xyz.shape[1] != 3):
+        raise ValueError("xyz must be [n, 3]")
+    pose = np.ascontiguousarray(pose, dtype=np.float32).reshape(12)
+    return lib().map_buffer_push(h, ptr, n, pose.ctypes.data_as(ctypes.c_void_p), flags)
+
+
+def map_buffer_combine(h, out_map) -> int:
+    return lib().map_buffer_combine(h, out_map)
+
+
+def map_buffer_count(h) -> int:
+    return lib().map_buffer_count(h)
+
+
+def map_buffer_get_stats(h):
+    st = map_stats_t()
+    s = lib().map_buffer_get_stats(h, ctypes.byref(st))
+    return s, {k: getattr(st, k) for k, _ in map_stats_t._fields_}
+
+
+class ScanBuffer:
+    """Owns a map buffer (the paper's per-scan maps, Sec. III-B); pushes run on
+    `stream`, combines on the output map's stream."""
+
+    def __init__(self, params: dict, depth: int, stream=None):
+        self.params = dict(params)
+        self.depth = depth
+        s, self.h = map_buffer_create(params, depth, stream)
+        if s != MAP_OK:
+            raise RuntimeError(f"map_buffer_create: {map_status_str(s)}")
+
+    def close(self):
+        if self.h:
+            map_buffer_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def push(self, xyz, pose, flags=0):
+        s = map_buffer_push(self.h, xyz, pose, flags)
+        if s != MAP_OK:
+            raise RuntimeError(f"map_buffer_push: {map_status_str(s)}")
+
+    def combine(self, out: "VoxelMap"):
+        s = map_buffer_combine(self.h, out.h)
+        if s != MAP_OK:
+            raise RuntimeError(f"map_buffer_combine: {map_status_str(s)}")
+
+    def count(self) -> int:
+        return map_buffer_count(self.h)
+
+    def stats(self):
+        s, st = map_buffer_get_stats(self.h)
+        if s != MAP_OK:
+            raise RuntimeError(f"map_buffer_get_stats: {map_status_str(s)}")
+        return st
 
 
 def _out2d(out):
