@@ -76,6 +76,8 @@ def lib():
         L.orc_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
         L.orc_get_origin.argtypes = [P, P]
         L.orc_combine.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(P), P]
+        L.orc_export_density.argtypes = [P, P]
+        L.orc_costmap.argtypes = [P, P, P, P, ctypes.c_int64, P, P, P]
         L.orc_transform_point.argtypes = [P, ctypes.c_float, P, P]
         L.orc_ray_voxels.argtypes = [P, P, P, ctypes.c_int64]
         L.orc_ray_voxels.restype = ctypes.c_int64
@@ -92,6 +94,7 @@ def lib():
             getattr(L, f).restype = ctypes.c_int32
         for f in ("orc_derive", "orc_create", "orc_reset", "orc_insert_scan", "orc_export_2d",
                   "orc_export_voxels", "orc_import_voxels", "orc_get_stats", "orc_get_origin", "orc_combine",
+                  "orc_export_density", "orc_costmap",
                   "orc_transform_point", "orc_surface"):
             getattr(L, f).restype = ctypes.c_int32
         _lib = L
@@ -144,6 +147,26 @@ def surface(hq, defined, fit_n: int, res_m: float, search_d: int, tau_neg_q: int
     if s:
         raise ValueError(f"orc_surface status {s}")
     return slope, rough, sdef, neg
+
+
+COST_LAYERS = ("slope", "rough", "density", "positive", "hard", "soft", "negative", "unknown")
+
+
+def costmap(out2d: dict, weights: dict):
+    """Planner costmap of Sec. IV from a 2D export: (cost, magnitude) in double."""
+    sl = np.ascontiguousarray(out2d["slope"], dtype=np.float32).reshape(-1)
+    ro = np.ascontiguousarray(out2d["rough"], dtype=np.float32).reshape(-1)
+    de = np.ascontiguousarray(out2d["density"], dtype=np.float32).reshape(-1)
+    fl = np.ascontiguousarray(out2d["flags"], dtype=np.uint8).reshape(-1)
+    w = np.array([float(np.float32(weights.get(k, 0.0))) for k in COST_LAYERS], np.float64)
+    cost = np.zeros(sl.size, np.float64)
+    mag = np.zeros(sl.size, np.float64)
+    s = lib().orc_costmap(_ptr(sl), _ptr(ro), _ptr(de), _ptr(fl), sl.size, _ptr(w), _ptr(cost),
+                          _ptr(mag))
+    if s:
+        raise ValueError(f"orc_costmap status {s}")
+    shape = np.shape(out2d["slope"])
+    return cost.reshape(shape), mag.reshape(shape)
 
 
 class OracleMap:
@@ -205,6 +228,13 @@ class OracleMap:
         origin = np.ascontiguousarray(origin, dtype=np.int32).reshape(3)
         return lib().orc_import_voxels(self._h, _ptr(lut), _ptr(data), data.shape[0],
                                        _ptr(origin))
+
+    def export_density(self) -> np.ndarray:
+        out = np.zeros(self.nx * self.ny * self.nz, np.float32)
+        s = lib().orc_export_density(self._h, _ptr(out))
+        if s:
+            raise ValueError(f"orc_export_density status {s}")
+        return out
 
     def stats(self) -> dict:
         st = Stats()

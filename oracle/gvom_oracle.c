@@ -732,6 +732,54 @@ int32_t orc_combine(orc_map* out, int32_t k, const int32_t* const* luts,
   return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* The completed voxel map is an output of its own (Sec. I, Fig. 1, where it
+ * is drawn more opaque where denser; Sec. V).  Per voxel of the window, in
+ * lookup-table order: an occupied voxel has the density hits / (hits +
+ * passes) that III-D uses for obstacle bands; a voxel that rays only passed
+ * through has 0; a voxel no ray reached is unobserved (NaN).               */
+int32_t orc_export_density(orc_map* m, float* density) {
+  if (!m || !density) return ORC_E_INVALID;
+  for (int64_t i = 0; i < n_vox(m); i++) {
+    if (m->hits[i] >= 1)
+      density[i] = (float)((double)m->hits[i] / ((double)m->hits[i] + (double)m->passes[i]));
+    else if (m->passes[i] >= 1)
+      density[i] = 0.0f;
+    else
+      density[i] = qnan();
+  }
+  return ORC_OK;
+}
+
+/* Sec. IV: the planner's costmap gives each output map a weight; a pixel's
+ * cost is the weighted sum of its layers.  Layers, in the order of w[]:
+ * slope, roughness, density (each where defined, else no term), then the
+ * indicator layers positive obstacle, hard, soft, negative obstacle and
+ * unknown ground (height undefined), from the flag bits of the 2D export.
+ * cost[i] is the sum in double; mag[i] = sum of the terms' magnitudes. */
+int32_t orc_costmap(const float* slope, const float* rough, const float* density,
+                    const uint8_t* flags, int64_t n, const double w[8], double* cost,
+                    double* mag) {
+  if (!slope || !rough || !density || !flags || n < 0 || !w || !cost || !mag)
+    return ORC_E_INVALID;
+  for (int64_t i = 0; i < n; i++) {
+    const double layer[8] = {
+        isnan(slope[i]) ? 0.0 : (double)slope[i],
+        isnan(rough[i]) ? 0.0 : (double)rough[i],
+        isnan(density[i]) ? 0.0 : (double)density[i],
+        (flags[i] >> 1) & 1, (flags[i] >> 2) & 1, (flags[i] >> 3) & 1, (flags[i] >> 4) & 1,
+        (flags[i] & 1) ? 0.0 : 1.0};
+    double c = 0.0, a = 0.0;
+    for (int k = 0; k < 8; k++) {
+      c += w[k] * layer[k];
+      a += fabs(w[k] * layer[k]);
+    }
+    cost[i] = c;
+    mag[i] = a;
+  }
+  return ORC_OK;
+}
+
 int32_t orc_get_stats(const orc_map* m, orc_stats* out) {
   if (!m || !out) return ORC_E_INVALID;
   *out = m->st;

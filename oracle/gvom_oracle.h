@@ -66,6 +66,10 @@ int32_t orc_import_voxels(orc_map* m, const int32_t* lut, const int32_t* data /*
 int32_t orc_combine(orc_map* out, int32_t k, const int32_t* const* luts,
                     const int32_t* const* datas /* [k] of [n][3] */,
                     const int32_t* origins /* [k][3], oldest first */);
+int32_t orc_export_density(orc_map* m, float* density /* [nx*ny*nz] */);
+int32_t orc_costmap(const float* slope, const float* rough, const float* density,
+                    const uint8_t* flags, int64_t n, const double w[8], double* cost,
+                    double* mag);
 int32_t orc_get_stats(const orc_map* m, orc_stats* out);
 int32_t orc_get_origin(const orc_map* m, int32_t origin[3]);
 
