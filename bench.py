@@ -182,6 +182,121 @@ def cpu_baseline(seq, n_scans):
                       f"export_voxels, single-threaded C oracle ({dt:.1f} s)"}
 
 
+def voxel_outputs(args, params, scans, poses, flags):
+    """The voxel map's density export (one float per voxel) and the planner
+    costmap (weighted sum of the 2D layers), timed with HIP events on the
+    map's stream after the warm-up scans."""
+    import numpy as np
+    import torch
+    from paper_2109_13176_amd import gvom
+    m = gvom.VoxelMap(params)
+    for k in range(args.warmup + 1):
+        m.insert(scans[k], poses[k], flags)
+    m.export_2d()
+    w = {"slope": 2.0, "rough": 40.0, "density": 5.0, "positive": 1.0, "hard": 100.0,
+         "soft": 3.0, "negative": 50.0, "unknown": 7.0}
+    res = {}
+    for name, fn in (("density", m.export_density), ("costmap", lambda: m.costmap(w))):
+        fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(20)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        res[name + "_us"] = float(np.mean([a.elapsed_time(b) for a, b in ev])) * 1e3
+    m.close()
+    V = params["nx"] * params["ny"] * params["nz"]
+    C = params["nx"] * params["ny"]
+    # density reads hits and passes and writes one float per voxel; the
+    # costmap reads 4 floats + 1 flag byte and writes 1 float per pixel
+    res["density_bytes"] = 12 * V
+    res["density_gbps"] = 12 * V / (res["density_us"] * 1e-6) / 1e9
+    res["density_frac"] = res["density_gbps"] / HBM_PEAK_GBS
+    res["costmap_bytes"] = 21 * C
+    res["costmap_gbps"] = 21 * C / (res["costmap_us"] * 1e-6) / 1e9
+    return res
+
+
+def paper_dataflow(args, params, scans, poses, flags, depth=10):
+    """The paper's own dataflow (Sec. III-B to III-D) on the same scans: each
+    scan becomes a voxel map of its own in a buffer of the last `depth` (one
+    second of scans at 10 Hz); map processing combines the buffered maps and
+    exports the same outputs as the headline step.  Pushes run on a second
+    stream, the combine and the exports on the output map's stream."""
+    import numpy as np
+    import torch
+    from paper_2109_13176_amd import gvom
+    W, K = args.warmup, args.steps
+
+    def run(with_events):
+        side = torch.cuda.Stream()
+        buf = gvom.ScanBuffer(params, depth, side)
+        cm = gvom.VoxelMap(params)
+        ev = []
+        origins = []
+        t0 = None
+        for k in range(W + K):
+            if k == W:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            timed = with_events and k >= W
+            if timed:
+                p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                # the push waits for the previous combine; time the push alone
+                side.wait_stream(torch.cuda.current_stream())
+                p0.record(side)
+            buf.push(scans[k], poses[k], flags)
+            if timed:
+                p1.record(side)
+                # the combine waits for the push; time the combine kernel alone
+                torch.cuda.current_stream().wait_stream(side)
+                c0.record()
+            buf.combine(cm)
+            if timed:
+                c1.record()
+                ev.append((p0, p1, c0, c1))
+            cm.export_2d()
+            cm.export_voxels()
+            origins.append(cm.origin().copy())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        buf.close()
+        cm.close()
+        return dt, ev, origins
+
+    t_df, _, _ = run(False)
+    _, ev, origins = run(True)
+    push_us = float(np.mean([a.elapsed_time(b) for a, b, _, _ in ev])) * 1e3
+    comb_us = float(np.mean([c.elapsed_time(d) for _, _, c, d in ev])) * 1e3
+    n = np.array([params["nx"], params["ny"], params["nz"]])
+    V = int(n.prod())
+    C = int(n[0] * n[1])
+    words = (params["nz"] + 63) // 64
+    # voxels of the combined window that each buffered window holds, per step
+    overlap = []
+    for j in range(W, W + K):
+        o = origins[j]
+        overlap.append(sum(int(np.prod(np.maximum(0, n - np.abs(o - origins[i]))))
+                           for i in range(max(0, j - depth + 1), j + 1)))
+    ov = float(np.mean(overlap))
+
+    def combine_bytes(distinct_hit):
+        # lookup tables of the overlapping windows, the data entries of their
+        # occupied voxels (at most M per map), the combined state written
+        # (hits, passes, lowest return) and its occupancy words
+        b = 4 * ov + 12 * depth * distinct_hit + 12 * V + 8 * C * words
+        gbps = b / (comb_us * 1e-6) / 1e9
+        return {"bytes": b, "us": comb_us, "achieved_gbps": gbps, "peak_gbps": HBM_PEAK_GBS,
+                "frac": gbps / HBM_PEAK_GBS, "overlap_voxels": ov}
+
+    return {"depth": depth, "ms_per_step": t_df * 1e3 / K, "updates_per_s": K / t_df,
+            "points_per_s": sum(int(scans[k].shape[0]) for k in range(W, W + K)) / t_df,
+            "push_us": push_us, "combine_us": comb_us, "combine_bytes_fn": combine_bytes}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +441,9 @@ def main():
     t_insert = timed(lambda mm, k: mm.insert(scans[k], poses[k], flags))
     t_insert_2d = timed(lambda mm, k: (mm.insert(scans[k], poses[k], flags), mm.export_2d()))
 
+    dataflow = paper_dataflow(args, params, scans, poses, flags)
+    outputs = voxel_outputs(args, params, scans, poses, flags)
+
     n_points = sum(int(scans[k].shape[0]) for k in range(W, W + K))
     value = n_points / elapsed
     updates = K / elapsed
@@ -393,6 +511,10 @@ def main():
                      "pass_updates": avg["n_pass_updates"]},
         "roofline": roof,
     }
+    df_hbm = dataflow.pop("combine_bytes_fn")(avg["n_distinct_hit"])
+    dataflow["combine_hbm"] = df_hbm
+    out["paper_dataflow"] = dataflow
+    out["voxel_outputs"] = outputs
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(seq, args.cpu_scans)
     print(json.dumps(out), flush=True)

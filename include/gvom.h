@@ -174,6 +174,29 @@ int32_t map_export_2d(map_t* m, const map_2d_t* out_dev);
 int32_t map_export_voxels(map_t* m, int32_t* lut_dev, map_voxel_t* data_dev, int64_t cap,
                           int64_t* n_occupied_dev, int32_t origin_vox[3]);
 
+/* The voxel map itself as an output (Sec. I and Fig. 1, where denser voxels
+ * are drawn more opaque; Sec. V): density_dev is a device float[nx*ny*nz] in
+ * window-local linear order receiving, per voxel, hits / (hits + passes) for
+ * an occupied voxel (the density of Sec. III-D, computed in double and
+ * rounded once), 0 for a voxel rays only passed through, and the canonical
+ * quiet NaN 0x7FC00000 for a voxel no ray reached.  Does not synchronise. */
+int32_t map_export_density(map_t* m, float* density_dev);
+
+/* Planner costmap (Sec. IV): each output map gets a weight and a pixel's cost
+ * is the weighted sum of its layers.  Terms, added in this order in binary32:
+ * slope, rough, density (each only where defined, i.e. not NaN), then the
+ * weight of every flag layer the pixel has: positive obstacle, hard, soft,
+ * negative obstacle, and `unknown` where the height is undefined.  Weights
+ * must be finite (MAP_E_INVALID otherwise). */
+typedef struct {
+  float slope, rough, density, positive, hard, soft, negative, unknown;
+} map_cost_weights_t;
+
+/* in_dev: the 2D maps of m's window (as written by map_export_2d), cost_dev:
+ * device float[nx][ny].  Enqueued on m's stream; reads no voxel state. */
+int32_t map_costmap(map_t* m, const map_2d_t* in_dev, const map_cost_weights_t* w,
+                    float* cost_dev);
+
 /* Sets the map state from a lookup table and data array in the format above
  * (checkpoint / resume).  Every lut entry >= 0 must index data with hits >= 1,
  * and no entry may be INT32_MIN.  Synchronises; on invalid content the map

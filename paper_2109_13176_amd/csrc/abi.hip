@@ -622,6 +622,37 @@ int32_t map_export_voxels(map_t* m, int32_t* lut_dev, map_voxel_t* data_dev, int
   return dev_status(m, e);
 }
 
+int32_t map_export_density(map_t* m, float* density_dev) {
+  if (!m || !density_dev) return MAP_E_INVALID;
+  if (m->sticky) return m->sticky;
+  gvom::DensityArgs a;
+  a.d = m->d;
+  a.hits = m->hits;
+  a.passes = m->passes;
+  a.out = density_dev;
+  return dev_status(m, gvom::launch_density(a, m->stream));
+}
+
+int32_t map_costmap(map_t* m, const map_2d_t* in_dev, const map_cost_weights_t* w,
+                    float* cost_dev) {
+  if (!m || !valid_2d(in_dev) || !w || !cost_dev) return MAP_E_INVALID;
+  if (m->sticky) return m->sticky;
+  const float wv[8] = {w->slope, w->rough, w->density, w->positive,
+                       w->hard, w->soft, w->negative, w->unknown};
+  gvom::CostArgs a;
+  for (int i = 0; i < 8; i++) {
+    if (!isfinite(wv[i])) return MAP_E_INVALID;
+    a.w[i] = wv[i];
+  }
+  a.n = n_col(m);
+  a.slope = in_dev->slope;
+  a.rough = in_dev->rough;
+  a.density = in_dev->density;
+  a.flags = in_dev->flags;
+  a.cost = cost_dev;
+  return dev_status(m, gvom::launch_costmap(a, m->stream));
+}
+
 int32_t map_import_voxels(map_t* m, const int32_t* lut_dev, const map_voxel_t* data_dev,
                           int64_t n_data, const int32_t origin_vox[3]) {
   if (!m || !lut_dev || !origin_vox || n_data < 0 || (n_data > 0 && !data_dev))

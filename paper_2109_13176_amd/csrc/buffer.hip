@@ -29,6 +29,7 @@ namespace {
 
 constexpr int kBrickThreads = 256;  // one block per 4 x 4 brick of columns
 constexpr int kMaxDepth = 64;       // buffered maps per combine
+static_assert(kBrickThreads == 256, "a block of the count covers 16 bricks of 16 columns");
 
 struct SlotArgs {
   Dims d;
@@ -39,7 +40,8 @@ struct SlotArgs {
   int32_t* lut;                   // slot: lookup table in storage order
   map_voxel_t* data;              // slot: data array
   int64_t cap;
-  const int32_t* brick_base;      // exclusive prefix of the occupied voxels per brick
+  const int32_t* brick_cnt;       // occupied voxels per brick
+  const int32_t* group_base;      // exclusive prefix per group of 16 bricks
 };
 
 struct CombineArgs {
@@ -62,10 +64,13 @@ __device__ __forceinline__ void brick_xy(const Dims& d, int b, int& bx, int& by)
   by = b - bx * d.nby;
 }
 
-// Occupied voxels per brick: one lane per storage column, 16 lanes per brick.
+// Occupied voxels per brick (one lane per storage column, 16 lanes per brick)
+// and per group of 16 bricks (one block).
 __global__ __launch_bounds__(kBrickThreads) void k_slot_count(Dims d,
                                                               const unsigned long long* occ,
-                                                              int32_t* brick_cnt, int nbricks) {
+                                                              int32_t* brick_cnt,
+                                                              int32_t* group_cnt, int nbricks) {
+  __shared__ int32_t wsum[kBrickThreads / 64];
   const int64_t t = (int64_t)blockIdx.x * kBrickThreads + threadIdx.x;
   const int b = (int)(t >> 4), j = (int)(t & 15);
   int c = 0;
@@ -82,6 +87,17 @@ __global__ __launch_bounds__(kBrickThreads) void k_slot_count(Dims d,
 #pragma unroll
   for (int o = 8; o >= 1; o >>= 1) c += __shfl_xor(c, o);
   if (b < nbricks && j == 0) brick_cnt[b] = c;
+  int g = j == 0 ? c : 0;
+  g += __shfl_xor(g, 16);
+  g += __shfl_xor(g, 32);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = g;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int sum = 0;
+#pragma unroll
+    for (int w = 0; w < kBrickThreads / 64; w++) sum += wsum[w];
+    group_cnt[blockIdx.x] = sum;
+  }
 }
 
 // Moves the producer's state into the slot, brick by brick in storage order:
@@ -93,9 +109,18 @@ __global__ __launch_bounds__(kBrickThreads) void k_slot_count(Dims d,
 __global__ __launch_bounds__(kBrickThreads) void k_slot_write(SlotArgs a) {
   __shared__ unsigned long long mlo[16], mhi[16];
   __shared__ int32_t wtot[kBrickThreads / 64];
+  __shared__ int32_t sbase;
   const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
   int bx, by;
   brick_xy(a.d, b, bx, by);
+  if (t < 64) {
+    // rank base: the group's prefix plus the bricks of the group before b
+    const int first = b & ~15;
+    int c = t < 16 && first + t < b ? a.brick_cnt[first + t] : 0;
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) c += __shfl_xor(c, o);
+    if (t == 0) sbase = a.group_base[b >> 4] + c;
+  }
   if (t < 16) {
     const int sx = 4 * bx + (t & 3), sy = 4 * by + (t >> 2);
     unsigned long long lo = 0ull, hi = 0ull;
@@ -111,7 +136,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_slot_write(SlotArgs a) {
   const int nz = a.d.nz;
   const int items = nz * 4;
   const int64_t s_b = (int64_t)b * nz * 16;
-  int32_t run = a.brick_base[b];
+  int32_t run = sbase;
   for (int i0 = 0; i0 < items; i0 += kBrickThreads) {
     const int i = i0 + t;
     const int z = i >> 2, q = i & 3;
@@ -276,7 +301,8 @@ struct map_buffer_t {
   std::vector<Slot> slots;
   int32_t head;                 // slot of the next push
   int32_t count;                // buffered maps
-  int32_t* brick_cnt;           // per brick: occupied voxels, then their prefix
+  int32_t* brick_cnt;           // per brick: occupied voxels
+  int32_t* group_cnt;           // per 16 bricks: occupied voxels, then their prefix
   int64_t* n_occ;               // [depth] occupied voxels per slot (device)
   hipEvent_t pushed;            // recorded after every push
   std::vector<hipEvent_t> pending;  // combines that may still read the slots
@@ -333,6 +359,7 @@ int32_t map_buffer_create(const map_params_t* p, int32_t depth, void* stream,
   b->sticky = MAP_OK;
   const int64_t nb = gvom::n_bricks(prod->d);
   hipError_t e = hipMalloc((void**)&b->brick_cnt, (size_t)nb * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->group_cnt, (size_t)((nb + 15) / 16) * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&b->n_occ, (size_t)depth * 8);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->pushed, hipEventDisableTiming);
   else b->pushed = nullptr;
@@ -362,6 +389,7 @@ int32_t map_buffer_destroy(map_buffer_t* b) {
     (void)hipFree(s.data);
   }
   (void)hipFree(b->brick_cnt);
+  (void)hipFree(b->group_cnt);
   (void)hipFree(b->n_occ);
   if (b->pushed) (void)hipEventDestroy(b->pushed);
   map_destroy(b->prod);
@@ -429,11 +457,11 @@ int32_t map_buffer_push(map_buffer_t* b, const float* xyz_dev, int64_t n, const 
   }
   const gvom::Dims& d = m->d;
   const int64_t nb = gvom::n_bricks(d);
-  hipLaunchKernelGGL(gvom::k_slot_count,
-                     dim3((unsigned)((nb * 16 + gvom::kBrickThreads - 1) / gvom::kBrickThreads)),
-                     dim3(gvom::kBrickThreads), 0, b->stream, d, m->occ, b->brick_cnt, (int)nb);
+  const int ng = (int)((nb + 15) / 16);  // one block of the count per 16 bricks
+  hipLaunchKernelGGL(gvom::k_slot_count, dim3((unsigned)ng), dim3(gvom::kBrickThreads), 0,
+                     b->stream, d, m->occ, b->brick_cnt, b->group_cnt, (int)nb);
   e = hipGetLastError();
-  if (e == hipSuccess) e = gvom::launch_scan_i32(b->brick_cnt, (int)nb, b->n_occ + b->head, b->stream);
+  if (e == hipSuccess) e = gvom::launch_scan_i32(b->group_cnt, ng, b->n_occ + b->head, b->stream);
   if (e == hipSuccess) {
     gvom::SlotArgs a;
     a.d = d;
@@ -444,7 +472,8 @@ int32_t map_buffer_push(map_buffer_t* b, const float* xyz_dev, int64_t n, const 
     a.lut = s.lut;
     a.data = s.data;
     a.cap = s.cap;
-    a.brick_base = b->brick_cnt;
+    a.brick_cnt = b->brick_cnt;
+    a.group_base = b->group_cnt;
     hipLaunchKernelGGL(gvom::k_slot_write, dim3((unsigned)nb), dim3(gvom::kBrickThreads), 0,
                        b->stream, a);
     e = hipGetLastError();

@@ -536,6 +536,82 @@ __global__ __launch_bounds__(kBlock) void k_lut_write(LutArgs a, uint32_t nz_mag
   lut_write_body(a, nz_magic, blockIdx.x, blockIdx.y);  // brick row, group of 4 bricks
 }
 
+// Density of every voxel (the voxel-map output, Fig. 1), in window-local
+// table order: the storage region of the table export (4 x 16 columns) is
+// read in storage order, each voxel's density computed there and kept in LDS
+// rows in window-local z order; then every lane writes four consecutive
+// densities of one column.
+__global__ __launch_bounds__(kBlock) void k_density(DensityArgs a, uint32_t nz_magic) {
+  extern __shared__ __attribute__((aligned(16))) float lden[];  // [64][lut_row(nz)]
+  __shared__ int64_t sout[kRegCols];
+  const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, roz = a.d.ro[2];
+  const int nzp = lut_row(nz);
+  const int bxr = blockIdx.x, byr = blockIdx.y;
+  if (threadIdx.x < kRegCols) {
+    const int t = threadIdx.x;
+    const int sx = 4 * bxr + (t >> 4), sy = 16 * byr + (t & 15);
+    int64_t o = -1;
+    if (sx < nx && sy < ny) {
+      const int x = sx - a.d.ro[0] + (sx < a.d.ro[0] ? nx : 0);
+      const int y = sy - a.d.ro[1] + (sy < a.d.ro[1] ? ny : 0);
+      o = ((int64_t)x * ny + y) * nz;
+    }
+    sout[t] = o;
+  }
+  const int nbricks = min(4, a.d.nby - 4 * byr);
+  const int64_t r0 = col_base(a.d, 4 * bxr, 16 * byr);
+  const int total = nbricks * nz * 16;
+  for (int k = threadIdx.x; k < total; k += kBlock) {
+    const int bz = k >> 4, l16 = k & 15;
+    const int b = nz == 1 ? bz : (int)__umulhi((uint32_t)bz, nz_magic);
+    const int zs = bz - b * nz;
+    const int lz = zs >= roz ? zs - roz : zs - roz + nz;
+    const int slot = (l16 & 3) * 16 + 4 * b + (l16 >> 2);
+    const int32_t h = a.hits[r0 + k], p = a.passes[r0 + k];
+    float v;
+    if (h >= 1) v = (float)((double)h / ((double)h + (double)p));
+    else v = p >= 1 ? 0.0f : __uint_as_float(kQNaN);
+    lden[slot * nzp + lz] = v;
+  }
+  __syncthreads();
+  const int nq = (nz + 3) >> 2;
+  const int qsh = nq > 1 ? 32 - __clz(nq - 1) : 0;
+  const bool vec = (nz & 3) == 0 && ((uintptr_t)a.out & 15) == 0;
+  for (int i = threadIdx.x; i < (kRegCols << qsh); i += kBlock) {
+    const int t = i >> qsh, q = i & ((1 << qsh) - 1);
+    if (q >= nq || sout[t] < 0) continue;
+    const int z0 = 4 * q;
+    float* __restrict__ out = a.out + sout[t] + z0;
+    const float* src = lden + t * nzp + z0;
+    if (vec) {
+      typedef float v4f __attribute__((ext_vector_type(4)));
+      __builtin_nontemporal_store(*(const v4f*)src, (v4f*)out);
+    } else {
+      for (int e = 0; e < 4; e++)
+        if (z0 + e < nz) __builtin_nontemporal_store(src[e], out + e);
+    }
+  }
+}
+
+// Costmap: one lane per pixel, the weighted layers added in a fixed order
+// in binary32.
+__global__ __launch_bounds__(kBlock) void k_costmap(CostArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  const float sl = a.slope[i], ro = a.rough[i], de = a.density[i];
+  const uint32_t f = a.flags[i];
+  float c = 0.0f;
+  if (!isnan(sl)) c = c + a.w[0] * sl;
+  if (!isnan(ro)) c = c + a.w[1] * ro;
+  if (!isnan(de)) c = c + a.w[2] * de;
+  if (f & 2u) c = c + a.w[3];
+  if (f & 4u) c = c + a.w[4];
+  if (f & 8u) c = c + a.w[5];
+  if (f & 16u) c = c + a.w[6];
+  if (!(f & 1u)) c = c + a.w[7];
+  a.cost[i] = c;
+}
+
 // Import: one wave per window-local column; lane = local z.
 __global__ __launch_bounds__(kBlock) void k_import(Dims d, const int32_t* lut,
                                                    const map_voxel_t* data, int64_t n_data,
@@ -756,6 +832,19 @@ hipError_t launch_lut(const LutArgs& a, bool counted, hipStream_t s) {
   hipLaunchKernelGGL(k_lut_scan, dim3(1), dim3(1024), 0, s, a.block_base, ng, a.n_occupied);
   dim3 g((a.d.nx + 3) / 4, (a.d.nby + 3) / 4);
   hipLaunchKernelGGL(k_lut_write, g, dim3(kBlock), lds, s, a, magic);
+  return hipGetLastError();
+}
+
+hipError_t launch_density(const DensityArgs& a, hipStream_t s) {
+  dim3 g((a.d.nx + 3) / 4, (a.d.nby + 3) / 4);
+  hipLaunchKernelGGL(k_density, g, dim3(kBlock), lut_lds(a.d.nz), s, a, nz_magic(a.d.nz));
+  return hipGetLastError();
+}
+
+hipError_t launch_costmap(const CostArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_costmap, dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     a);
   return hipGetLastError();
 }
 

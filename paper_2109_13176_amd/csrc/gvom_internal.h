@@ -162,6 +162,23 @@ struct LutArgs {
   int64_t* n_occupied;
 };
 
+struct DensityArgs {
+  Dims d;
+  const int32_t* hits;
+  const int32_t* passes;
+  float* out;             // [nx*ny*nz], window-local table order
+};
+
+struct CostArgs {
+  int64_t n;              // pixels
+  const float* slope;
+  const float* rough;
+  const float* density;
+  const uint8_t* flags;
+  float w[8];             // slope, rough, density, positive, hard, soft, negative, unknown
+  float* cost;
+};
+
 struct ClearArgs {
   Dims d;
   int32_t* hits;
@@ -237,6 +254,8 @@ hipError_t launch_import(const Dims& d, const int32_t* lut, const map_voxel_t* d
                          int64_t n_data, int32_t* hits, int32_t* passes, int32_t* minqz,
                          unsigned long long* occ, int32_t* err, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_density(const DensityArgs& a, hipStream_t s);
+hipError_t launch_costmap(const CostArgs& a, hipStream_t s);
 // Exclusive prefix of base[0..nb) in place (one block); *total = the sum.
 hipError_t launch_scan_i32(int32_t* base, int nb, int64_t* total, hipStream_t s);
 

@@ -51,6 +51,13 @@ class map_tuning_t(ctypes.Structure):
                 ("traversal", ctypes.c_int32)]
 
 
+COST_LAYERS = ("slope", "rough", "density", "positive", "hard", "soft", "negative", "unknown")
+
+
+class map_cost_weights_t(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_float) for k in COST_LAYERS]
+
+
 class map_stats_t(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("n_points", "n_nonfinite", "n_range", "n_hits", "n_pass",
@@ -66,6 +73,7 @@ EXPORTED = [
     "map_batch_set_graph", "map_batch_autotune",
     "map_buffer_create", "map_buffer_destroy", "map_buffer_reset", "map_buffer_push",
     "map_buffer_combine", "map_buffer_count", "map_buffer_get_stats",
+    "map_export_density", "map_costmap",
     "sgt_num_params", "sgt_create", "sgt_destroy", "sgt_get_params", "sgt_set_params",
     "sgt_set_norm", "sgt_features", "sgt_thin", "sgt_feature_sums", "sgt_forward",
     "sgt_loss_grad", "sgt_adam", "sgt_fill",
@@ -104,6 +112,8 @@ def lib() -> ctypes.CDLL:
         L.map_batch_set_graph.argtypes = [P, I32]
         L.map_batch_autotune.argtypes = [P, P, P, P, P, P, ctypes.c_char_p,
                                          ctypes.POINTER(map_tuning_t)]
+        L.map_export_density.argtypes = [P, P]
+        L.map_costmap.argtypes = [P, ctypes.POINTER(map_2d_t), ctypes.POINTER(map_cost_weights_t), P]
         L.map_buffer_create.argtypes = [ctypes.POINTER(map_params_t), I32, P, ctypes.POINTER(P)]
         L.map_buffer_destroy.argtypes = [P]
         L.map_buffer_reset.argtypes = [P]
@@ -219,6 +229,18 @@ def map_import_voxels(h, lut, data, origin) -> int:
     origin = np.ascontiguousarray(origin, dtype=np.int32).reshape(3)
     return lib().map_import_voxels(h, _dev(lut, torch.int32, "lut"), dptr, n,
                                    origin.ctypes.data_as(ctypes.c_void_p))
+
+
+def map_export_density(h, density) -> int:
+    import torch
+    return lib().map_export_density(h, _dev(density, torch.float32, "density"))
+
+
+def map_costmap(h, out2d: dict, weights: dict, cost) -> int:
+    import torch
+    w = map_cost_weights_t(*[float(weights.get(k, 0.0)) for k in COST_LAYERS])
+    o = _out2d(out2d)
+    return lib().map_costmap(h, ctypes.byref(o), ctypes.byref(w), _dev(cost, torch.float32, "cost"))
 
 
 def map_get_stats(h):
@@ -427,6 +449,21 @@ class VoxelMap:
                                       self.n_occ)
         self._check(s, "map_export_voxels")
         return self.lut, self.data, self.n_occ, origin
+
+    def export_density(self):
+        import torch
+        if getattr(self, "density3d", None) is None:
+            self.density3d = torch.empty(self.lut.numel(), dtype=torch.float32, device=self.lut.device)
+        self._check(map_export_density(self.h, self.density3d), "map_export_density")
+        return self.density3d
+
+    def costmap(self, weights: dict, out2d=None):
+        import torch
+        out2d = self.out2d if out2d is None else out2d
+        if getattr(self, "cost", None) is None:
+            self.cost = torch.empty_like(self.out2d["height"])
+        self._check(map_costmap(self.h, out2d, weights, self.cost), "map_costmap")
+        return self.cost
 
     def stats(self):
         s, st = map_get_stats(self.h)
