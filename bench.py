@@ -196,16 +196,19 @@ def voxel_outputs(args, params, scans, poses, flags):
     w = {"slope": 2.0, "rough": 40.0, "density": 5.0, "positive": 1.0, "hard": 100.0,
          "soft": 3.0, "negative": 50.0, "unknown": 7.0}
     res = {}
+    reps = 20
     for name, fn in (("density", m.export_density), ("costmap", lambda: m.costmap(w))):
         fn()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(20)]
-        for a, b in ev:
-            a.record()
-            fn()
-            b.record()
+        # back-to-back launches between one event pair: the queue stays full,
+        # so launch gaps do not count
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        res[name + "_us"] = float(np.mean([a.elapsed_time(b) for a, b in ev])) * 1e3
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        res[name + "_us"] = a.elapsed_time(b) * 1e3 / reps
     m.close()
     V = params["nx"] * params["ny"] * params["nz"]
     C = params["nx"] * params["ny"]
