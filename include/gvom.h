@@ -268,7 +268,8 @@ int32_t map_profile_read(map_t* m, double ms[MAP_PROF_N], int64_t count[MAP_PROF
 typedef struct map_buffer_t map_buffer_t;
 
 /* Buffer of the `depth` (1..64) most recent per-scan maps of the window size
- * and resolution in `p`, each slot holding a lookup table of the map's storage
+ * and resolution in `p`, in depth + 1 slots (the map the last push evicted is
+ * kept until the next push), each holding a lookup table of the map's storage
  * size (4 bytes per voxel) and a data array of 12 bytes per occupied voxel
  * (grown to the largest scan pushed into it: a grow synchronises `stream`).
  * Pushes are enqueued on `stream` (NULL: the default stream). */
@@ -299,6 +300,15 @@ int32_t map_buffer_push(map_buffer_t* b, const float* xyz_dev, int64_t n, const 
  * exports); map_export_2d / map_export_voxels then export the combined map.
  * Enqueued on out's stream.  MAP_E_INVALID when the buffer is empty. */
 int32_t map_buffer_combine(map_buffer_t* b, map_t* out);
+
+/* Combine strategy (results are identical): with `enable` (the default) a
+ * combine into the same map as the previous combine of this buffer, made
+ * exactly one push later and with that map unchanged in between, updates it
+ * (adds the newest map, takes away the evicted one, recombines only the
+ * voxels whose minimum could change and those that entered the window)
+ * instead of combining every buffered map again; 0 always combines in full,
+ * as the paper describes. */
+int32_t map_buffer_set_incremental(map_buffer_t* b, int32_t enable);
 
 /* Buffered maps (0..depth), or MAP_E_INVALID for a NULL buffer. */
 int32_t map_buffer_count(const map_buffer_t* b);

@@ -9,6 +9,7 @@
 
 #include <stdio.h>
 
+#include <atomic>
 #include <new>
 #include <string>
 #include <vector>
@@ -49,6 +50,11 @@ void set_origin(map_t* m, const int32_t o[3]) {
 
 void set_empty_origin(map_t* m, const int32_t o[3]) {
   if (m->empty) set_origin(m, o);
+}
+
+uint64_t next_version() {
+  static std::atomic<uint64_t> counter{0};
+  return ++counter;
 }
 
 }  // namespace gvom
@@ -264,6 +270,7 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   initial_origin(m);
   e = clear_all(m);
   m->empty = true;
+  m->version = gvom::next_version();
   if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, kStatsBytes, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) {
@@ -308,6 +315,7 @@ int32_t map_reset(map_t* m) {
   m->sticky = MAP_OK;
   initial_origin(m);
   m->lut_counted = false;
+  m->version = gvom::next_version();
   m->last_points = 0;
   m->last_cleared = 0;
   m->last_distinct = false;
@@ -557,6 +565,7 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
   gvom::ClearArgs plan;
   bool full = false;
   m->lut_counted = false;
+  m->version = gvom::next_version();
   const int pm0 = prof_begin(m, MAP_PROF_SCROLL);
   st = prepare_insert(m, xyz_dev, n, pose, flags, S, &a, &plan, &full, true);
   if (st) return st;
@@ -662,6 +671,7 @@ int32_t map_import_voxels(map_t* m, const int32_t* lut_dev, const map_voxel_t* d
   set_ring(m);
   m->lut_counted = false;
   m->empty = false;
+  m->version = gvom::next_version();
   int32_t err = 0;
   hipError_t e = hipMemsetAsync(m->err, 0, 4, m->stream);
   if (e == hipSuccess)
@@ -837,6 +847,7 @@ int32_t batch_prepare(map_batch_t* b, const float* const* xyz_dev, const int64_t
     column_args(m, &out2d[i], false, &t->col[i]);
     m->lut_counted = false;
     m->empty = false;
+    m->version = gvom::next_version();
     surface_args(m, &out2d[i], &t->sur[i]);
     const bool lut = lut_dev && lut_dev[i];
     if (lut) {

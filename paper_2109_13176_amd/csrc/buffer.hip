@@ -201,6 +201,76 @@ __device__ __forceinline__ int32_t ring_to_local(int32_t s, int32_t ro, int32_t 
   return l < 0 ? l + n : l;
 }
 
+// Full combination of the voxels of one item selected by `mask`: sums over
+// every buffered map whose window holds the voxel (all four voxels of an item
+// share y and z, so the map's window test on those is done once).
+__device__ __forceinline__ void sum_maps(const CombineArgs& a, const int64_t s,
+                                         const int32_t gx[4], const int32_t gy,
+                                         const int32_t gz, const unsigned mask, int32_t h[4],
+                                         int32_t p[4], int32_t mq[4]) {
+  const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    if ((mask >> e) & 1u) {
+      h[e] = 0;
+      p[e] = 0;
+      mq[e] = INT32_MAX;
+    }
+  }
+  for (int k = 0; k < a.k; k++) {
+    if ((uint32_t)(gy - a.org[k][1]) >= (uint32_t)ny ||
+        (uint32_t)(gz - a.org[k][2]) >= (uint32_t)nz)
+      continue;
+    bool in[4], any = false;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      in[e] = ((mask >> e) & 1u) && (uint32_t)(gx[e] - a.org[k][0]) < (uint32_t)nx;
+      any |= in[e];
+    }
+    if (!any) continue;
+    const int4 v4 = *(const int4*)(a.lut[k] + s);
+    const int32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      if (!in[e]) continue;
+      if (v[e] >= 0) {
+        if (v[e] >= a.cap[k]) continue;
+        const map_voxel_t dv = a.data[k][v[e]];
+        h[e] += dv.hits;
+        p[e] += dv.passes;
+        mq[e] = min(mq[e], dv.min_qz);
+      } else {
+        p[e] += -1 - v[e];
+      }
+    }
+  }
+}
+
+// World coordinates of an item's voxels in the combined window.
+__device__ __forceinline__ unsigned item_world(const CombineArgs& a, const int bx, const int by,
+                                               const int z, const int q, int32_t gx[4],
+                                               int32_t& gy, int32_t& gz) {
+  const int sy = 4 * by + q;
+  gy = a.O[1] + ring_to_local(sy, a.d.ro[1], a.d.ny);
+  gz = a.O[2] + ring_to_local(z, a.d.ro[2], a.d.nz);
+  unsigned valid = 0u;
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    const int sx = 4 * bx + e;
+    if (sx < a.d.nx && sy < a.d.ny) valid |= 1u << e;
+    gx[e] = a.O[0] + ring_to_local(sx, a.d.ro[0], a.d.nx);
+  }
+  return valid;
+}
+
+__device__ __forceinline__ void set_occ(unsigned long long* mlo, unsigned long long* mhi,
+                                        const int j, const int z, const bool on) {
+  unsigned long long* w = z < 64 ? &mlo[j] : &mhi[j];
+  const unsigned long long bit = 1ull << (z & 63);
+  if (on) atomicOr(w, bit);
+  else atomicAnd(w, ~bit);
+}
+
 // The combined map's state, brick by brick: each item's four voxels are
 // located in world coordinates, looked up at the same storage index in every
 // buffered map whose window holds them, and summed; the occupancy words of
@@ -218,57 +288,17 @@ __global__ __launch_bounds__(kBrickThreads) void k_combine(const CombineArgs a) 
   for (int i = t; i < items; i += kBrickThreads) {
     const int z = i >> 2, q = i & 3;
     const int64_t s = s_b + 16 * z + 4 * q;
-    const int sy = 4 * by + q;
-    const int32_t gy = a.O[1] + ring_to_local(sy, a.d.ro[1], ny);
-    const int32_t gz = a.O[2] + ring_to_local(z, a.d.ro[2], nz);
-    int32_t gx[4];
-    bool valid[4];
-#pragma unroll
-    for (int e = 0; e < 4; e++) {
-      const int sx = 4 * bx + e;
-      valid[e] = sx < nx && sy < ny;
-      gx[e] = a.O[0] + ring_to_local(sx, a.d.ro[0], nx);
-    }
+    int32_t gx[4], gy, gz;
+    const unsigned valid = item_world(a, bx, by, z, q, gx, gy, gz);
     int32_t h[4] = {0, 0, 0, 0}, p[4] = {0, 0, 0, 0};
     int32_t mq[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
-    for (int k = 0; k < a.k; k++) {
-      if ((uint32_t)(gy - a.org[k][1]) >= (uint32_t)ny ||
-          (uint32_t)(gz - a.org[k][2]) >= (uint32_t)nz)
-        continue;
-      bool in[4], any = false;
-#pragma unroll
-      for (int e = 0; e < 4; e++) {
-        in[e] = valid[e] && (uint32_t)(gx[e] - a.org[k][0]) < (uint32_t)nx;
-        any |= in[e];
-      }
-      if (!any) continue;
-      const int4 v4 = *(const int4*)(a.lut[k] + s);
-      const int32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
-#pragma unroll
-      for (int e = 0; e < 4; e++) {
-        if (!in[e]) continue;
-        if (v[e] >= 0) {
-          if (v[e] >= a.cap[k]) continue;
-          const map_voxel_t dv = a.data[k][v[e]];
-          h[e] += dv.hits;
-          p[e] += dv.passes;
-          mq[e] = min(mq[e], dv.min_qz);
-        } else {
-          p[e] += -1 - v[e];
-        }
-      }
-    }
+    sum_maps(a, s, gx, gy, gz, valid, h, p, mq);
     *(int4*)(a.hits + s) = make_int4(h[0], h[1], h[2], h[3]);
     *(int4*)(a.passes + s) = make_int4(p[0], p[1], p[2], p[3]);
     *(int4*)(a.minqz + s) = make_int4(mq[0], mq[1], mq[2], mq[3]);
 #pragma unroll
-    for (int e = 0; e < 4; e++) {
-      if (h[e] > 0) {
-        const int j = 4 * q + e;
-        if (z < 64) atomicOr(&mlo[j], 1ull << z);
-        else atomicOr(&mhi[j], 1ull << (z - 64));
-      }
-    }
+    for (int e = 0; e < 4; e++)
+      if (h[e] > 0) set_occ(mlo, mhi, 4 * q + e, z, true);
   }
   __syncthreads();
   if (t < 16) {
@@ -281,6 +311,213 @@ __global__ __launch_bounds__(kBrickThreads) void k_combine(const CombineArgs a) 
   }
 }
 
+// Update of a combined map that holds the combination of the buffer as it
+// was one push ago: the buffer has since gained its newest map and lost at
+// most one map (evicted).  Hits and misses are sums, so a voxel of the old
+// window changes by the newest map's counts minus the evicted map's; voxels
+// where neither map has anything are not touched.  A minimum cannot be taken
+// back: where the evicted map's lowest return equals the combined minimum,
+// and for every voxel that entered with the new window, the voxel is
+// combined in full.  Same result as k_combine.
+struct IncArgs {
+  int32_t O_old[3];               // origin of the combination being updated
+  const int32_t* nw_lut;          // newest map (its window is the combined window)
+  const map_voxel_t* nw_data;
+  int64_t nw_cap;
+  int32_t has_ev;                 // a map was evicted by the newest push
+  const int32_t* ev_lut;
+  const map_voxel_t* ev_data;
+  int64_t ev_cap;
+  int32_t ev_org[3];
+};
+
+__global__ __launch_bounds__(kBrickThreads) void k_combine_inc(const CombineArgs a,
+                                                               const IncArgs u) {
+  const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
+  const int lane = threadIdx.x & 63;
+  // lane j holds buffered map j for the wave-wide recombination below
+  const int32_t* my_lut = nullptr;
+  const map_voxel_t* my_data = nullptr;
+  int64_t my_cap = 0;
+  int32_t my_org[3] = {0, 0, 0};
+  for (int k = 0; k < a.k; k++) {
+    if (lane == k) {
+      my_lut = a.lut[k];
+      my_data = a.data[k];
+      my_cap = a.cap[k];
+      my_org[0] = a.org[k][0];
+      my_org[1] = a.org[k][1];
+      my_org[2] = a.org[k][2];
+    }
+  }
+  const int per_brick = nz * 4;
+  const int n_items = (int)(a.d.vs >> 2);
+  const int stride = gridDim.x * kBrickThreads;
+  // a grid-stride walk over the items in storage order; the bound is uniform
+  // per block, so every lane reaches the wave-wide step.  The next item's two
+  // table entries are loaded before this item's state is read and written,
+  // so the walk keeps one round trip in flight per item, not two.
+  int4 n4_next = make_int4(-1, -1, -1, -1), e4_next = make_int4(-1, -1, -1, -1);
+  {
+    const int i0 = blockIdx.x * kBrickThreads + threadIdx.x;
+    if (i0 < n_items) {
+      n4_next = *(const int4*)(u.nw_lut + ((int64_t)i0 << 2));
+      if (u.has_ev) e4_next = *(const int4*)(u.ev_lut + ((int64_t)i0 << 2));
+    }
+  }
+  for (int base = blockIdx.x * kBrickThreads; base < n_items; base += stride) {
+    const int i = base + threadIdx.x;
+    const bool active = i < n_items;
+    const int ic = active ? i : 0;
+    const int4 n4 = n4_next, e4_all = e4_next;
+    {
+      const int in = i + stride;
+      n4_next = make_int4(-1, -1, -1, -1);
+      e4_next = make_int4(-1, -1, -1, -1);
+      if (in < n_items) {
+        n4_next = *(const int4*)(u.nw_lut + ((int64_t)in << 2));
+        if (u.has_ev) e4_next = *(const int4*)(u.ev_lut + ((int64_t)in << 2));
+      }
+    }
+    const int b = ic / per_brick;
+    const int r = ic - b * per_brick;
+    const int z = r >> 2, q = r & 3;
+    int bx, by;
+    brick_xy(a.d, b, bx, by);
+    const int64_t s = (int64_t)ic << 2;
+    int32_t gx[4], gy, gz;
+    const unsigned valid = item_world(a, bx, by, z, q, gx, gy, gz) & (active ? 15u : 0u);
+    const bool old_yz = (uint32_t)(gy - u.O_old[1]) < (uint32_t)ny &&
+                        (uint32_t)(gz - u.O_old[2]) < (uint32_t)nz;
+    const bool ev_yz = u.has_ev && (uint32_t)(gy - u.ev_org[1]) < (uint32_t)ny &&
+                       (uint32_t)(gz - u.ev_org[2]) < (uint32_t)nz;
+    const int4 e4 = ev_yz ? e4_all : make_int4(-1, -1, -1, -1);
+    const int32_t nw[4] = {n4.x, n4.y, n4.z, n4.w};
+    int32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
+    unsigned enter = 0u, upd = 0u, hit = 0u, evo = 0u;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      if ((uint32_t)(gx[e] - u.ev_org[0]) >= (uint32_t)nx) ev[e] = -1;
+      if (!((valid >> e) & 1u)) continue;
+      const bool in_old = old_yz && (uint32_t)(gx[e] - u.O_old[0]) < (uint32_t)nx;
+      if (!in_old) enter |= 1u << e;
+      else if (ev[e] >= 0) evo |= 1u << e;
+      else if (ev[e] != -1 || nw[e] != -1) upd |= 1u << e;
+      if (nw[e] >= 0) hit |= 1u << e;
+    }
+    // only misses change where neither map has a return: hits and lowest
+    // return are read and written where a map has one or the voxel is
+    // combined in full
+    const unsigned hm = enter | evo | (upd & hit);
+    int32_t h[4] = {0, 0, 0, 0}, p[4] = {0, 0, 0, 0}, mq[4] = {0, 0, 0, 0};
+    if (enter | evo | upd) {
+      const int4 p4 = *(const int4*)(a.passes + s);
+      p[0] = p4.x; p[1] = p4.y; p[2] = p4.z; p[3] = p4.w;
+    }
+    if (hm) {
+      const int4 h4 = *(const int4*)(a.hits + s);
+      const int4 m4 = *(const int4*)(a.minqz + s);
+      h[0] = h4.x; h[1] = h4.y; h[2] = h4.z; h[3] = h4.w;
+      mq[0] = m4.x; mq[1] = m4.y; mq[2] = m4.z; mq[3] = m4.w;
+    }
+    const int32_t h_old[4] = {h[0], h[1], h[2], h[3]};
+    map_voxel_t evd[4];
+    unsigned coop = 0u;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      if (!((evo >> e) & 1u)) continue;
+      // the evicted map's lowest return is above the combined minimum: the
+      // minimum stays, its counts come off; otherwise the voxel is combined
+      // again from every map
+      if (ev[e] < u.ev_cap) evd[e] = u.ev_data[ev[e]];
+      if (ev[e] < u.ev_cap && evd[e].min_qz > mq[e]) upd |= 1u << e;
+      else coop |= 1u << e;
+    }
+    // voxels that entered with the window: dense (whole slabs), each lane
+    // combines its own
+    if (enter) sum_maps(a, s, gx, gy, gz, enter, h, p, mq);
+    // voxels whose minimum went with the evicted map: scattered, so the wave
+    // combines them one at a time with one lane per buffered map
+    unsigned long long lanes = __ballot(coop != 0u);
+    while (lanes) {
+      const int L = __ffsll((long long)lanes) - 1;
+      lanes &= lanes - 1;
+      const unsigned cm = (unsigned)__builtin_amdgcn_readlane((int)coop, L);
+      const int iL = __builtin_amdgcn_readlane(ic, L);
+      const int gyL = __builtin_amdgcn_readlane(gy, L);
+      const int gzL = __builtin_amdgcn_readlane(gz, L);
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        if (!((cm >> e) & 1u)) continue;
+        const int gxL = __builtin_amdgcn_readlane(gx[e], L);
+        int32_t hh = 0, pp = 0, mm = INT32_MAX;
+        if (lane < a.k && (uint32_t)(gxL - my_org[0]) < (uint32_t)nx &&
+            (uint32_t)(gyL - my_org[1]) < (uint32_t)ny &&
+            (uint32_t)(gzL - my_org[2]) < (uint32_t)nz) {
+          const int32_t v = my_lut[((int64_t)iL << 2) + e];
+          if (v >= 0) {
+            if (v < my_cap) {
+              const map_voxel_t dv = my_data[v];
+              hh = dv.hits;
+              pp = dv.passes;
+              mm = dv.min_qz;
+            }
+          } else {
+            pp = -1 - v;
+          }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+          hh += __shfl_xor(hh, o);
+          pp += __shfl_xor(pp, o);
+          mm = min(mm, __shfl_xor(mm, o));
+        }
+        if (lane == L) {
+          h[e] = hh;
+          p[e] = pp;
+          mq[e] = mm;
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      if (!((upd >> e) & 1u)) continue;
+      if (ev[e] >= 0) {
+        h[e] -= evd[e].hits;
+        p[e] -= evd[e].passes;
+      } else if (ev[e] < -1) {
+        p[e] -= -1 - ev[e];
+      }
+      if (nw[e] >= 0) {
+        if (nw[e] < u.nw_cap) {
+          const map_voxel_t dv = u.nw_data[nw[e]];
+          h[e] += dv.hits;
+          p[e] += dv.passes;
+          mq[e] = min(mq[e], dv.min_qz);
+        }
+      } else {
+        p[e] += -1 - nw[e];
+      }
+    }
+    if (enter | evo | upd) *(int4*)(a.passes + s) = make_int4(p[0], p[1], p[2], p[3]);
+    if (hm) {
+      *(int4*)(a.hits + s) = make_int4(h[0], h[1], h[2], h[3]);
+      *(int4*)(a.minqz + s) = make_int4(mq[0], mq[1], mq[2], mq[3]);
+      // occupancy bit = hits >= 1; flip it only where that changed (the old
+      // bit of an entering voxel belongs to the voxel that left)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        if (!((hm >> e) & 1u) || (h_old[e] > 0) == (h[e] > 0)) continue;
+        unsigned long long* w =
+            a.occ + ((int64_t)(4 * bx + e) * ny + (4 * by + q)) * a.d.W + (z >> 6);
+        const unsigned long long bit = 1ull << (z & 63);
+        if (h[e] > 0) atomicOr(w, bit);
+        else atomicAnd(w, ~bit);
+      }
+    }
+  }
+}
+
 int64_t n_bricks(const Dims& d) { return (int64_t)((d.nx + 3) / 4) * d.nby; }
 
 }  // namespace
@@ -289,7 +526,9 @@ int64_t n_bricks(const Dims& d) { return (int64_t)((d.nx + 3) / 4) * d.nby; }
 
 struct map_buffer_t {
   map_params_t p;
-  int32_t depth;
+  int32_t depth;                // buffered maps
+  int32_t ring;                 // slots = depth + 1: the map the last push evicted
+                                // stays readable until the next push
   hipStream_t stream;           // producer stream: pushes run here
   map_t* prod;                  // producer map, empty between pushes
   struct Slot {
@@ -298,15 +537,20 @@ struct map_buffer_t {
     int64_t cap;
     int32_t origin[3];
   };
-  std::vector<Slot> slots;
-  int32_t head;                 // slot of the next push
-  int32_t count;                // buffered maps
+  std::vector<Slot> slots;      // push j lives in slot j mod ring
+  int64_t npush;                // pushes since create / reset
   int32_t* brick_cnt;           // per brick: occupied voxels
   int32_t* group_cnt;           // per 16 bricks: occupied voxels, then their prefix
-  int64_t* n_occ;               // [depth] occupied voxels per slot (device)
+  int64_t* n_occ;               // [ring] occupied voxels per slot (device)
   hipEvent_t pushed;            // recorded after every push
   std::vector<hipEvent_t> pending;  // combines that may still read the slots
   std::vector<hipEvent_t> pool;
+  // the last combine: a combine into the same, unchanged map one push later
+  // updates it instead of combining every buffered map again
+  bool incremental;
+  map_t* last_out;
+  uint64_t last_version;
+  int64_t last_npush;
   int32_t sticky;
 };
 
@@ -330,7 +574,11 @@ hipError_t wait_combines(map_buffer_t* b) {
   return e;
 }
 
-int32_t newest(const map_buffer_t* b) { return (b->head + b->depth - 1) % b->depth; }
+int32_t held(const map_buffer_t* b) {
+  return (int32_t)(b->npush < b->depth ? b->npush : b->depth);
+}
+
+map_buffer_t::Slot& slot_of(map_buffer_t* b, int64_t push) { return b->slots[push % b->ring]; }
 
 }  // namespace
 
@@ -351,19 +599,21 @@ int32_t map_buffer_create(const map_params_t* p, int32_t depth, void* stream,
   }
   b->p = *p;
   b->depth = depth;
+  b->ring = depth + 1;
   b->stream = (hipStream_t)stream;
   b->prod = prod;
-  b->slots.assign(depth, map_buffer_t::Slot{nullptr, nullptr, 0, {0, 0, 0}});
-  b->head = 0;
-  b->count = 0;
+  b->slots.assign(b->ring, map_buffer_t::Slot{nullptr, nullptr, 0, {0, 0, 0}});
+  b->npush = 0;
+  b->incremental = true;
+  b->last_out = nullptr;
   b->sticky = MAP_OK;
   const int64_t nb = gvom::n_bricks(prod->d);
   hipError_t e = hipMalloc((void**)&b->brick_cnt, (size_t)nb * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&b->group_cnt, (size_t)((nb + 15) / 16) * 4);
-  if (e == hipSuccess) e = hipMalloc((void**)&b->n_occ, (size_t)depth * 8);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->n_occ, (size_t)b->ring * 8);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->pushed, hipEventDisableTiming);
   else b->pushed = nullptr;
-  for (int i = 0; i < depth && e == hipSuccess; i++) {
+  for (int i = 0; i < b->ring && e == hipSuccess; i++) {
     e = hipMalloc((void**)&b->slots[i].lut, (size_t)prod->d.vs * 4);
     if (e != hipSuccess) b->slots[i].lut = nullptr;
   }
@@ -407,10 +657,16 @@ int32_t map_buffer_reset(map_buffer_t* b) {
   }
   b->pending.clear();
   (void)hipGetLastError();
-  b->head = 0;
-  b->count = 0;
+  b->npush = 0;
+  b->last_out = nullptr;
   b->sticky = MAP_OK;
   return map_reset(b->prod);
+}
+
+int32_t map_buffer_set_incremental(map_buffer_t* b, int32_t enable) {
+  if (!b) return MAP_E_INVALID;
+  b->incremental = enable != 0;
+  return MAP_OK;
 }
 
 int32_t map_buffer_push(map_buffer_t* b, const float* xyz_dev, int64_t n, const float pose[12],
@@ -420,8 +676,8 @@ int32_t map_buffer_push(map_buffer_t* b, const float* xyz_dev, int64_t n, const 
   map_t* m = b->prod;
   // a scan that is not recentred takes the newest buffered window
   int32_t o[3];
-  if (b->count > 0) {
-    const map_buffer_t::Slot& nw = b->slots[newest(b)];
+  if (b->npush > 0) {
+    const map_buffer_t::Slot& nw = slot_of(b, b->npush - 1);
     o[0] = nw.origin[0];
     o[1] = nw.origin[1];
     o[2] = nw.origin[2];
@@ -434,7 +690,8 @@ int32_t map_buffer_push(map_buffer_t* b, const float* xyz_dev, int64_t n, const 
   hipError_t e = wait_combines(b);
   if (e != hipSuccess) return buf_fail(b, e);
   // a fresh window holds at most one occupied voxel per point
-  map_buffer_t::Slot& s = b->slots[b->head];
+  const int32_t si = (int32_t)(b->npush % b->ring);
+  map_buffer_t::Slot& s = b->slots[si];
   const int64_t need = n < m->d.vs ? (n > 0 ? n : 1) : m->d.vs;
   if (need > s.cap) {
     e = hipStreamSynchronize(b->stream);
@@ -461,7 +718,7 @@ int32_t map_buffer_push(map_buffer_t* b, const float* xyz_dev, int64_t n, const 
   hipLaunchKernelGGL(gvom::k_slot_count, dim3((unsigned)ng), dim3(gvom::kBrickThreads), 0,
                      b->stream, d, m->occ, b->brick_cnt, b->group_cnt, (int)nb);
   e = hipGetLastError();
-  if (e == hipSuccess) e = gvom::launch_scan_i32(b->group_cnt, ng, b->n_occ + b->head, b->stream);
+  if (e == hipSuccess) e = gvom::launch_scan_i32(b->group_cnt, ng, b->n_occ + si, b->stream);
   if (e == hipSuccess) {
     gvom::SlotArgs a;
     a.d = d;
@@ -488,11 +745,11 @@ int32_t map_buffer_push(map_buffer_t* b, const float* xyz_dev, int64_t n, const 
   }
   m->empty = true;
   m->lut_counted = false;
+  m->version = gvom::next_version();
   s.origin[0] = m->origin[0];
   s.origin[1] = m->origin[1];
   s.origin[2] = m->origin[2];
-  b->head = (b->head + 1) % b->depth;
-  if (b->count < b->depth) b->count++;
+  b->npush++;
   return MAP_OK;
 }
 
@@ -503,7 +760,7 @@ int32_t map_buffer_combine(map_buffer_t* b, map_t* out) {
   if (out->p.nx != b->p.nx || out->p.ny != b->p.ny || out->p.nz != b->p.nz ||
       out->p.res_m != b->p.res_m)
     return MAP_E_INVALID;
-  if (b->count == 0) return MAP_E_INVALID;
+  if (b->npush == 0) return MAP_E_INVALID;
   hipEvent_t ev = nullptr;
   if (!b->pool.empty()) {
     ev = b->pool.back();
@@ -512,17 +769,35 @@ int32_t map_buffer_combine(map_buffer_t* b, map_t* out) {
     (void)hipGetLastError();
     return MAP_E_DEVICE;
   }
+  // `out` still holds this buffer's combination of one push ago
+  const bool inc = b->incremental && b->last_out == out && out->version == b->last_version &&
+                   b->npush == b->last_npush + 1;
+  gvom::IncArgs u;
+  if (inc) {
+    for (int i = 0; i < 3; i++) u.O_old[i] = out->origin[i];
+    const map_buffer_t::Slot& nw = slot_of(b, b->npush - 1);
+    u.nw_lut = nw.lut;
+    u.nw_data = nw.data;
+    u.nw_cap = nw.cap;
+    const int64_t evicted = b->npush - 1 - b->depth;  // push that left the buffer
+    u.has_ev = evicted >= 0;
+    const map_buffer_t::Slot& es = slot_of(b, evicted >= 0 ? evicted : 0);
+    u.ev_lut = es.lut;
+    u.ev_data = es.data;
+    u.ev_cap = es.cap;
+    for (int i = 0; i < 3; i++) u.ev_org[i] = es.origin[i];
+  }
   hipError_t e = hipStreamWaitEvent(out->stream, b->pushed, 0);
-  const map_buffer_t::Slot& nw = b->slots[newest(b)];
+  const map_buffer_t::Slot& nw = slot_of(b, b->npush - 1);
   gvom::set_origin(out, nw.origin);
   out->lut_counted = false;
   out->empty = false;
   gvom::CombineArgs a;
   a.d = out->d;
   for (int i = 0; i < 3; i++) a.O[i] = nw.origin[i];
-  a.k = b->count;
-  for (int j = 0; j < b->count; j++) {
-    const map_buffer_t::Slot& s = b->slots[(b->head + b->depth - b->count + j) % b->depth];
+  a.k = held(b);
+  for (int j = 0; j < a.k; j++) {
+    const map_buffer_t::Slot& s = slot_of(b, b->npush - a.k + j);
     a.lut[j] = s.lut;
     a.data[j] = s.data;
     a.cap[j] = s.cap;
@@ -533,22 +808,36 @@ int32_t map_buffer_combine(map_buffer_t* b, map_t* out) {
   a.minqz = out->minqz;
   a.occ = out->occ;
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(gvom::k_combine, dim3((unsigned)gvom::n_bricks(out->d)),
-                       dim3(gvom::kBrickThreads), 0, out->stream, a);
+    const dim3 blk(gvom::kBrickThreads);
+    if (inc) {
+      // eight blocks per CU walk the items
+      const int64_t items = out->d.vs / 4;
+      int64_t grid = (items + gvom::kBrickThreads - 1) / gvom::kBrickThreads;
+      if (grid > (int64_t)out->n_cu * 8) grid = (int64_t)out->n_cu * 8;
+      hipLaunchKernelGGL(gvom::k_combine_inc, dim3((unsigned)grid), blk, 0, out->stream, a, u);
+    } else {
+      hipLaunchKernelGGL(gvom::k_combine, dim3((unsigned)gvom::n_bricks(out->d)), blk, 0,
+                         out->stream, a);
+    }
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipEventRecord(ev, out->stream);
+  out->version = gvom::next_version();
   if (e != hipSuccess) {
     b->pool.push_back(ev);
     (void)hipGetLastError();
     out->sticky = MAP_E_DEVICE;
+    b->last_out = nullptr;
     return MAP_E_DEVICE;
   }
   b->pending.push_back(ev);
+  b->last_out = out;
+  b->last_version = out->version;
+  b->last_npush = b->npush;
   return MAP_OK;
 }
 
-int32_t map_buffer_count(const map_buffer_t* b) { return b ? b->count : MAP_E_INVALID; }
+int32_t map_buffer_count(const map_buffer_t* b) { return b ? held(b) : MAP_E_INVALID; }
 
 int32_t map_buffer_get_stats(map_buffer_t* b, map_stats_t* out) {
   if (!b) return MAP_E_INVALID;

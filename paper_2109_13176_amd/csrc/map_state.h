@@ -51,6 +51,9 @@ struct map_t {
   // every voxel is empty and every occupancy word zero (a recentring then
   // needs no clears)
   bool empty;
+  // a fresh value (from a process-wide counter) whenever the voxel state may
+  // change: a combine can tell that a map still holds its previous result
+  uint64_t version;
   struct Mark {
     int phase;
     hipEvent_t a, b;
@@ -64,5 +67,7 @@ namespace gvom {
 void set_origin(map_t* m, const int32_t o[3]);
 // Same, for a map whose state is empty (no clears are needed).
 void set_empty_origin(map_t* m, const int32_t o[3]);
+// Next value of the process-wide state version counter (never 0).
+uint64_t next_version();
 }  // namespace gvom
 

@@ -761,6 +761,7 @@ int32_t sgt_thin(map_t* m, const uint8_t* thin_dev) {
   if (m->sticky) return m->sticky;
   const int64_t C = (int64_t)m->p.nx * m->p.ny;
   m->lut_counted = false;
+  m->version = gvom::next_version();
   hipLaunchKernelGGL(k_thin, dim3(blocks_for(C)), dim3(256), 0, m->stream, m->d, thin_dev, m->hits,
                      m->passes, m->minqz, m->occ);
   return st_of(hipGetLastError());

@@ -73,7 +73,7 @@ EXPORTED = [
     "map_batch_set_graph", "map_batch_autotune",
     "map_buffer_create", "map_buffer_destroy", "map_buffer_reset", "map_buffer_push",
     "map_buffer_combine", "map_buffer_count", "map_buffer_get_stats",
-    "map_export_density", "map_costmap",
+    "map_export_density", "map_costmap", "map_buffer_set_incremental",
     "sgt_num_params", "sgt_create", "sgt_destroy", "sgt_get_params", "sgt_set_params",
     "sgt_set_norm", "sgt_features", "sgt_thin", "sgt_feature_sums", "sgt_forward",
     "sgt_loss_grad", "sgt_adam", "sgt_fill",
@@ -120,6 +120,7 @@ def lib() -> ctypes.CDLL:
         L.map_buffer_push.argtypes = [P, P, I64, P, ctypes.c_uint32]
         L.map_buffer_combine.argtypes = [P, P]
         L.map_buffer_count.argtypes = [P]
+        L.map_buffer_set_incremental.argtypes = [P, I32]
         L.map_buffer_get_stats.argtypes = [P, ctypes.POINTER(map_stats_t)]
         L.sgt_num_params.argtypes = []
         L.sgt_create.argtypes = [I32, I32, ctypes.c_uint64, P, ctypes.POINTER(P)]
@@ -510,6 +511,10 @@ def map_buffer_combine(h, out_map) -> int:
     return lib().map_buffer_combine(h, out_map)
 
 
+def map_buffer_set_incremental(h, enable: bool) -> int:
+    return lib().map_buffer_set_incremental(h, 1 if enable else 0)
+
+
 def map_buffer_count(h) -> int:
     return lib().map_buffer_count(h)
 
@@ -554,6 +559,11 @@ class ScanBuffer:
 
     def count(self) -> int:
         return map_buffer_count(self.h)
+
+    def set_incremental(self, enable: bool):
+        s = map_buffer_set_incremental(self.h, enable)
+        if s != MAP_OK:
+            raise RuntimeError(f"map_buffer_set_incremental: {map_status_str(s)}")
 
     def stats(self):
         s, st = map_buffer_get_stats(self.h)

@@ -167,3 +167,105 @@ def test_64beam_sequence_full_size():
         assert n > 20000
     finally:
         bp.close()
+
+
+def test_incremental_and_full_combines_interleaved():
+    """Every way a combine can follow the previous one: one push later into
+    the same unchanged map (updated in place), several pushes later, no push,
+    another output map, an output map changed in between, a window jump; each
+    result is compared with the oracle."""
+    from paper_2109_13176_amd import gvom
+    rng = np.random.default_rng(14)
+    P = params(40, 40, 24, 0.4)
+    bp = BufPair(P, depth=3)
+    g2, o2 = gvom.VoxelMap(P), oracle.OracleMap(P)
+    view2 = types.SimpleNamespace(g=g2, o=o2, params=bp.params)
+    t = [0.0, 0.0, 0.0]
+
+    def push(step=(0.45, 0.2, 0.05), flags=1):
+        t[0] += step[0]
+        t[1] += step[1]
+        t[2] += step[2]
+        pose = scenegen.pose12(scenegen.rot_zyx(rng.uniform(-0.5, 0.5), 0.03, -0.02), t)
+        assert bp.push(_cloud(rng, 5000, 9.0), pose, flags) == 0
+
+    def combine_second():
+        assert gvom.map_buffer_combine(bp.g.h, g2.h) == bp.o.combine(o2) == 0
+        compare_voxels(view2)
+        compare_2d(view2)
+
+    try:
+        for k in range(5):           # first combine in full, then updates, evictions from k = 3
+            push()
+            assert bp.combine() == 0
+            bp.compare()
+        push()
+        push(flags=0)                # two pushes (a second lidar) before one combine
+        assert bp.combine() == 0
+        bp.compare()
+        assert bp.combine() == 0     # no push since the last combine
+        bp.compare()
+        push()
+        combine_second()             # another output map
+        push()
+        assert bp.combine() == 0     # the first map was not the last output
+        bp.compare()
+        push()
+        assert bp.combine() == 0     # updated in place again
+        bp.compare()
+        extra = _cloud(rng, 800, 5.0)
+        bp.gm.insert(torch.as_tensor(extra, device="cuda"), scenegen.pose12(np.eye(3), t), 0)
+        assert bp.om.insert_scan(extra, scenegen.pose12(np.eye(3), t), 0) == 0
+        push()
+        assert bp.combine() == 0     # the output map changed in between
+        bp.compare()
+        push(step=(60.0, -20.0, 1.0))  # the window jumps: every voxel enters
+        assert bp.combine() == 0
+        bp.compare()
+        for k in range(3):
+            push()
+            assert bp.combine() == 0
+            bp.compare()
+    finally:
+        g2.close()
+        o2.close()
+        bp.close()
+
+
+def test_incremental_equals_full_combine_full_size():
+    """Thirteen scans of the 64-beam sequence through two buffers of depth
+    10, one updating its output map, one combining in full every time: the
+    outputs are bit-identical after every step (three evictions), and equal
+    the oracle's at the end."""
+    from paper_2109_13176_amd import gvom
+    seq = scenegen.sequence_64beam(seed=2, n_scans=13, device="cuda")
+    prm = seq["params"]
+    inc = BufPair(prm, depth=10)
+    full = gvom.ScanBuffer(prm, 10)
+    full.set_incremental(False)
+    fm = gvom.VoxelMap(prm)
+    try:
+        fl = gvom.MAP_RECENTER | gvom.MAP_FIRING(64)
+        for k in range(13):
+            print(f"64-beam step {k}", flush=True)
+            xyz = seq["scans"][k].contiguous()
+            assert gvom.map_buffer_push(inc.g.h, xyz, seq["poses"][k], fl) == 0
+            full.push(xyz, seq["poses"][k], fl)
+            assert gvom.map_buffer_combine(inc.g.h, inc.gm.h) == 0
+            full.combine(fm)
+            a = inc.gm.export_voxels()
+            lut_a, data_a, n_a = a[0].clone(), a[1].clone(), int(a[2].item())
+            b = fm.export_voxels()
+            assert n_a == int(b[2].item()) and np.array_equal(a[3], b[3])
+            assert torch.equal(lut_a, b[0]) and torch.equal(data_a[:n_a], b[1][:n_a])
+            oa, ob = inc.gm.export_2d(), fm.export_2d()
+            for key in oa:
+                assert torch.equal(oa[key].view(torch.uint8), ob[key].view(torch.uint8)), key
+        for k in range(13):
+            assert inc.o.push(seq["scans"][k].cpu().numpy(), seq["poses"][k], oracle.RECENTER) == 0
+        assert inc.o.combine(inc.om) == 0
+        assert inc.compare() > 20000
+    finally:
+        fm.close()
+        full.close()
+        inc.close()
