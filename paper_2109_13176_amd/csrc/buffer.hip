@@ -104,8 +104,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_slot_count(Dims d,
 // item (level z, quarter q) holds the four storage voxels of columns
 // 4q .. 4q+3 of the brick at z, so items are in storage order and the rank of
 // an occupied voxel is the brick's base plus a block scan of the item counts.
-// Every passes word is zeroed; hits and lowest return only where occupied
-// (they are empty elsewhere).
+// Every non-zero passes word is zeroed; hits and lowest return only where
+// occupied (they are empty elsewhere).
 __global__ __launch_bounds__(kBrickThreads) void k_slot_write(SlotArgs a) {
   __shared__ unsigned long long mlo[16], mhi[16];
   __shared__ int32_t wtot[kBrickThreads / 64];
@@ -190,7 +190,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_slot_write(SlotArgs a) {
         }
       }
       *(int4*)(a.lut + s) = make_int4(v[0], v[1], v[2], v[3]);
-      *(int4*)(a.passes + s) = make_int4(0, 0, 0, 0);
+      // only the few voxels rays passed need clearing
+      if (p.x | p.y | p.z | p.w) *(int4*)(a.passes + s) = make_int4(0, 0, 0, 0);
     }
     __syncthreads();  // wtot is rewritten by the next round
   }
