@@ -169,15 +169,16 @@ def test_64beam_sequence_full_size():
         bp.close()
 
 
-def test_incremental_and_full_combines_interleaved():
+@pytest.mark.parametrize("depth", [1, 3])
+def test_incremental_and_full_combines_interleaved(depth):
     """Every way a combine can follow the previous one: one push later into
     the same unchanged map (updated in place), several pushes later, no push,
     another output map, an output map changed in between, a window jump; each
     result is compared with the oracle."""
     from paper_2109_13176_amd import gvom
-    rng = np.random.default_rng(14)
+    rng = np.random.default_rng(14 + depth)
     P = params(40, 40, 24, 0.4)
-    bp = BufPair(P, depth=3)
+    bp = BufPair(P, depth=depth)
     g2, o2 = gvom.VoxelMap(P), oracle.OracleMap(P)
     view2 = types.SimpleNamespace(g=g2, o=o2, params=bp.params)
     t = [0.0, 0.0, 0.0]
@@ -269,3 +270,21 @@ def test_incremental_equals_full_combine_full_size():
         fm.close()
         full.close()
         inc.close()
+
+
+def test_three_lidar_frame_full_size():
+    """One frame of the three-lidar workload on 1024 x 1024 x 96 through a
+    buffer: the 128-beam scan recentres, the two 32-beam scans take its
+    window (three maps of one frame, combined)."""
+    from paper_2109_13176_amd import gvom
+    fr = scenegen.multi_lidar_frames(seed=3, n_frames=1, device="cuda")
+    bp = BufPair(fr["params"], depth=3)
+    try:
+        for xyz, pose, fl, fw in zip(fr["scans"], fr["poses"], fr["flags"], fr["firing"]):
+            print(f"three-lidar push of {xyz.shape[0]} points", flush=True)
+            assert bp.push(xyz, pose, fl, firing=fw) == 0
+        assert bp.g.count() == 3
+        assert bp.combine() == 0
+        assert bp.compare() > 10000
+    finally:
+        bp.close()
