@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "gvom_internal.h"
@@ -544,7 +545,9 @@ struct map_buffer_t {
   int32_t* group_cnt;           // per 16 bricks: occupied voxels, then their prefix
   int64_t* n_occ;               // [ring] occupied voxels per slot (device)
   hipEvent_t pushed;            // recorded after every push
-  std::vector<hipEvent_t> pending;  // combines that may still read the slots
+  // combines that may still read the slots: the latest event per output
+  // stream (work on one stream completes in order)
+  std::vector<std::pair<hipStream_t, hipEvent_t>> pending;
   std::vector<hipEvent_t> pool;
   // the last combine: a combine into the same, unchanged map one push later
   // updates it instead of combining every buffered map again
@@ -567,9 +570,9 @@ int32_t buf_fail(map_buffer_t* b, hipError_t e) {
 // Orders the producer stream after every combine that may still read a slot.
 hipError_t wait_combines(map_buffer_t* b) {
   hipError_t e = hipSuccess;
-  for (hipEvent_t ev : b->pending) {
-    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, ev, 0);
-    b->pool.push_back(ev);
+  for (const auto& pe : b->pending) {
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, pe.second, 0);
+    b->pool.push_back(pe.second);
   }
   b->pending.clear();
   return e;
@@ -630,9 +633,9 @@ int32_t map_buffer_create(const map_params_t* p, int32_t depth, void* stream,
 int32_t map_buffer_destroy(map_buffer_t* b) {
   if (!b) return MAP_OK;
   (void)hipStreamSynchronize(b->stream);
-  for (hipEvent_t ev : b->pending) {
-    (void)hipEventSynchronize(ev);
-    (void)hipEventDestroy(ev);
+  for (const auto& pe : b->pending) {
+    (void)hipEventSynchronize(pe.second);
+    (void)hipEventDestroy(pe.second);
   }
   for (hipEvent_t ev : b->pool) (void)hipEventDestroy(ev);
   for (auto& s : b->slots) {
@@ -652,9 +655,9 @@ int32_t map_buffer_destroy(map_buffer_t* b) {
 int32_t map_buffer_reset(map_buffer_t* b) {
   if (!b) return MAP_E_INVALID;
   (void)hipStreamSynchronize(b->stream);
-  for (hipEvent_t ev : b->pending) {
-    (void)hipEventSynchronize(ev);
-    b->pool.push_back(ev);
+  for (const auto& pe : b->pending) {
+    (void)hipEventSynchronize(pe.second);
+    b->pool.push_back(pe.second);
   }
   b->pending.clear();
   (void)hipGetLastError();
@@ -831,7 +834,15 @@ int32_t map_buffer_combine(map_buffer_t* b, map_t* out) {
     b->last_out = nullptr;
     return MAP_E_DEVICE;
   }
-  b->pending.push_back(ev);
+  bool replaced = false;
+  for (auto& pe : b->pending) {
+    if (pe.first == out->stream) {
+      b->pool.push_back(pe.second);  // implied by the new event on the same stream
+      pe.second = ev;
+      replaced = true;
+    }
+  }
+  if (!replaced) b->pending.emplace_back(out->stream, ev);
   b->last_out = out;
   b->last_version = out->version;
   b->last_npush = b->npush;

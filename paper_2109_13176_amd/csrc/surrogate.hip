@@ -397,7 +397,9 @@ template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_bwd_data(const float* __restrict__ dz,
                                                   const uint16_t* __restrict__ w,
                                                   const uint16_t* __restrict__ x,
-                                                  float* __restrict__ dprev, int H, int W) {
+                                                  float* __restrict__ dprev,
+                                                  uint16_t* __restrict__ dph,
+                                                  uint16_t* __restrict__ dpl, int H, int W) {
   __shared__ float sdz[18 * 18 * COUT];
   __shared__ float sw[COUT * 9 * CIN];
   const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
@@ -425,8 +427,116 @@ __global__ __launch_bounds__(256) void k_bwd_data(const float* __restrict__ dz,
     }
   }
   const uint16_t* xp = x + ((int64_t)r * W + c) * CIN;
-  float* o = dprev + ((int64_t)r * W + c) * CIN;
-  for (int k = 0; k < CIN; k++) o[k] = from_bf16(xp[k]) > 0.0f ? acc[k] : 0.0f;
+  const int64_t o = ((int64_t)r * W + c) * CIN;
+  static_assert(CIN % 8 == 0, "bf16 pairs are stored 8 channels at a time");
+  for (int k0 = 0; k0 < CIN; k0 += 8) {
+    uint32_t hw[4], lw[4];
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+      float v2[2];
+      uint16_t hi[2], lo[2];
+#pragma unroll
+      for (int j = 0; j < 2; j++) {
+        v2[j] = from_bf16(xp[k0 + k + j]) > 0.0f ? acc[k0 + k + j] : 0.0f;
+        dprev[o + k0 + k + j] = v2[j];
+        // the bf16 pair the matrix-core kernels of the layer below read
+        hi[j] = to_bf16(v2[j]);
+        lo[j] = to_bf16(v2[j] - from_bf16(hi[j]));
+      }
+      hw[k / 2] = (uint32_t)hi[0] | ((uint32_t)hi[1] << 16);
+      lw[k / 2] = (uint32_t)lo[0] | ((uint32_t)lo[1] << 16);
+    }
+    *(uint4*)(dph + o + k0) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+    *(uint4*)(dpl + o + k0) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+  }
+}
+
+// Input gradient of a 32 -> 32 layer on matrix cores.  The transposed
+// convolution is a forward convolution of dz with W'[ci][t][co] =
+// W[co][8 - t][ci] (tap t reads dz at p + offset(t); offset(8 - t) =
+// -offset(t)), masked by the ReLU of the layer below.  dz enters as two bf16
+// parts, hi = bf16(dz) and lo = bf16(dz - hi), each through the same
+// instructions into one fp32 accumulator, so the product keeps about 16 bits
+// of dz beyond bf16.  Layout and operand lanes as k_conv_mfma (CIN = 32); the
+// tile is staged twice (hi, then lo) through one LDS array.
+template <int TR>
+__global__ __launch_bounds__(TR * 64) void k_bwd_data_mfma(const uint16_t* __restrict__ dzh,
+                                                           const uint16_t* __restrict__ dzl,
+                                                           const uint16_t* __restrict__ w,
+                                                           const uint16_t* __restrict__ x,
+                                                           float* __restrict__ dprev,
+                                                           uint16_t* __restrict__ dph,
+                                                           uint16_t* __restrict__ dpl, int H,
+                                                           int W) {
+  constexpr int C = 32, PS = C + kPad, NT = TR * 64, Q = C / 8;
+  __shared__ __attribute__((aligned(16))) uint16_t sx[(TR + 2) * (kTC + 2) * PS];
+  __shared__ __attribute__((aligned(16))) uint16_t sw[32 * 9 * PS];
+  const int r0 = blockIdx.y * TR, c0 = blockIdx.x * kTC;
+  // row ci * 9 + t of the transposed weights: W[co][8 - t][ci] over co
+  for (int i = threadIdx.x; i < 32 * 9 * C; i += NT) {
+    const int row = i / C, co = i - row * C;
+    const int ci = row / 9, t = row - ci * 9;
+    sw[row * PS + co] = w[(co * 9 + (8 - t)) * C + ci];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  v4f acc[2][4];
+  for (int m = 0; m < 2; m++)
+    for (int n = 0; n < 4; n++) acc[m][n] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int part = 0; part < 2; part++) {
+    const uint16_t* src = part ? dzl : dzh;
+    for (int i = threadIdx.x; i < (TR + 2) * (kTC + 2) * Q; i += NT) {
+      const int pix = i / Q, cq = i - pix * Q;
+      const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
+      const int gr = r0 + tr - 1, gc = c0 + tc - 1;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (gr >= 0 && gr < H && gc >= 0 && gc < W)
+        v = *(const uint4*)(src + ((int64_t)gr * W + gc) * C + cq * 8);
+      *(uint4*)(sx + pix * PS + cq * 8) = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tap = 0; tap < 9; tap++) {
+      const int dy = tap / 3, dx = tap - dy * 3;
+      const v8bf a0 = *(const v8bf*)(sw + (lr * 9 + tap) * PS + 8 * lk);
+      const v8bf a1 = *(const v8bf*)(sw + ((16 + lr) * 9 + tap) * PS + 8 * lk);
+#pragma unroll
+      for (int nt = 0; nt < 4; nt++) {
+        const int pc = nt * 16 + lr;
+        const v8bf b = *(const v8bf*)(sx + ((wv + dy) * (kTC + 2) + pc + dx) * PS + 8 * lk);
+        acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc[0][nt], 0, 0, 0);
+        acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc[1][nt], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // the tile is restaged for the low part
+  }
+  const int r = r0 + wv;
+  if (r >= H) return;
+#pragma unroll
+  for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++) {
+      const int col = c0 + nt * 16 + lr;
+      if (col >= W) continue;
+      const int ci0 = mt * 16 + 4 * lk;
+      const int64_t o = ((int64_t)r * W + col) * C + ci0;
+      const uint2 xm = *(const uint2*)(x + o);
+      const uint16_t xs[4] = {(uint16_t)(xm.x & 0xFFFFu), (uint16_t)(xm.x >> 16),
+                              (uint16_t)(xm.y & 0xFFFFu), (uint16_t)(xm.y >> 16)};
+      float v[4];
+      uint16_t hi[4], lo[4];
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        v[e] = from_bf16(xs[e]) > 0.0f ? acc[mt][nt][e] : 0.0f;
+        hi[e] = to_bf16(v[e]);
+        lo[e] = to_bf16(v[e] - from_bf16(hi[e]));
+      }
+      *(float4*)(dprev + o) = make_float4(v[0], v[1], v[2], v[3]);
+      *(uint2*)(dph + o) = make_uint2((uint32_t)hi[0] | ((uint32_t)hi[1] << 16),
+                                      (uint32_t)hi[2] | ((uint32_t)hi[3] << 16));
+      *(uint2*)(dpl + o) = make_uint2((uint32_t)lo[0] | ((uint32_t)lo[1] << 16),
+                                      (uint32_t)lo[2] | ((uint32_t)lo[3] << 16));
+    }
 }
 
 // Weight and bias gradient partials of one 16 x 16 pixel tile:
@@ -590,6 +700,7 @@ struct sgt_net_t {
   uint16_t* act[kNL];  // input of each layer (bf16)
   float* out;
   float *dz0, *dz1;    // fp32 gradient images (up to 32 channels)
+  uint16_t *dzh[2], *dzl[2];  // the same as bf16 pairs hi + lo (32 channels)
   float* part;         // weight-gradient partials, one per 16 x 16 tile
   double* mid;         // partials summed over groups of kRedGroup tiles
   int part_blocks;
@@ -680,6 +791,10 @@ int32_t sgt_create(int32_t H, int32_t W, uint64_t seed, void* stream, sgt_net_t*
   al((void**)&n->out, P * 2 * 4);
   al((void**)&n->dz0, P * 32 * 4);
   al((void**)&n->dz1, P * 32 * 4);
+  for (int k = 0; k < 2; k++) {
+    al((void**)&n->dzh[k], P * 32 * 2);
+    al((void**)&n->dzl[k], P * 32 * 2);
+  }
   al((void**)&n->part, (size_t)n->part_blocks * maxlp * 4);
   al((void**)&n->mid, (size_t)((n->part_blocks + kRedGroup - 1) / kRedGroup) * maxlp * 8);
   al((void**)&n->lpart, (size_t)4096 * 2 * 8);
@@ -722,6 +837,10 @@ int32_t sgt_destroy(sgt_net_t* n) {
   void* ps[] = {n->master, n->m, n->v, n->grad, n->out, n->dz0, n->dz1, n->part, n->mid,
                 n->lpart, n->scal, n->mean, n->stdv};
   for (void* p : ps) (void)hipFree(p);
+  for (int k = 0; k < 2; k++) {
+    (void)hipFree(n->dzh[k]);
+    (void)hipFree(n->dzl[k]);
+  }
   for (int l = 0; l < kNL; l++) {
     (void)hipFree(n->wbf[l]);
     (void)hipFree(n->bias[l]);
@@ -842,6 +961,8 @@ int32_t sgt_loss_grad(sgt_net_t* n, const float* feat_dev, const float* label_de
   dim3 g16((W + 15) / 16, (H + 15) / 16);
   float* dz = n->dz0;
   float* dp = n->dz1;
+  int hb = 0;  // bf16 pair holding dz (set by the layer above)
+  dim3 g8((W + kTC - 1) / kTC, (H + 7) / 8);
   for (int l = kNL - 1; l >= 0; l--) {
     const int64_t lp = layer_params(l);
     if (l == 4)
@@ -857,9 +978,13 @@ int32_t sgt_loss_grad(sgt_net_t* n, const float* feat_dev, const float* label_de
                        n->scal, n->grad + n->off[l]);
     if (l == 0) break;
     if (l == 4)
-      hipLaunchKernelGGL((k_bwd_data<32, 2>), g16, dim3(256), 0, n->stream, dz, n->wbf[l], n->act[l], dp, H, W);
+      hipLaunchKernelGGL((k_bwd_data<32, 2>), g16, dim3(256), 0, n->stream, dz, n->wbf[l],
+                         n->act[l], dp, n->dzh[hb], n->dzl[hb], H, W);
     else
-      hipLaunchKernelGGL((k_bwd_data<32, 32>), g16, dim3(256), 0, n->stream, dz, n->wbf[l], n->act[l], dp, H, W);
+      hipLaunchKernelGGL((k_bwd_data_mfma<8>), g8, dim3(512), 0, n->stream, n->dzh[hb],
+                         n->dzl[hb], n->wbf[l], n->act[l], dp, n->dzh[hb ^ 1], n->dzl[hb ^ 1],
+                         H, W);
+    if (l != 4) hb ^= 1;
     float* t = dz;
     dz = dp;
     dp = t;
