@@ -598,6 +598,127 @@ __global__ __launch_bounds__(256) void k_bwd_weight(const float* __restrict__ dz
   }
 }
 
+// Weight and bias gradient partials on matrix cores, one per block of TR
+// rows x 64 pixels: dW[co][ci][t] = sum_p dz[p][co] x[p + offset(t)][ci] is
+// one GEMM per tap with A = dz^T (row = output channel), B = shifted x
+// (column = input channel) and K = pixels.  Both are staged transposed
+// (channel-major, pixels contiguous) so that a lane's 8 consecutive K values
+// are one 16-byte LDS read; x is staged once per column shift dx (taps of
+// equal dx share the copy).  dz enters as the bf16 pair hi + lo written by
+// the input-gradient kernel of the layer above.  Wave w takes input-channel
+// tile w % (CIN / 16) and every (TR * CIN / 16 / 4)-th row from w / (CIN /
+// 16), so a wave keeps 9 x 2 accumulator tiles; the waves' results are
+// summed in LDS in wave order (deterministic) before the partial is written.
+constexpr int kWRS = kTC + 8;  // LDS row stride (bf16) of the transposed tiles
+
+template <int CIN, int TR>
+__global__ __launch_bounds__(TR * 64) void k_bwd_weight_mfma(const uint16_t* __restrict__ dzh,
+                                                             const uint16_t* __restrict__ dzl,
+                                                             const uint16_t* __restrict__ x,
+                                                             float* __restrict__ part, int H,
+                                                             int W) {
+  constexpr int CO = 32, NT = TR * 64, NCT = CIN / 16;
+  constexpr int NW = CO * CIN * 9;
+  constexpr int NWAVE = TR, RSTEP = NWAVE / NCT;  // waves; row step of a wave
+  static_assert(NWAVE % NCT == 0, "waves split evenly over the channel tiles");
+  static_assert(2 * CO * TR * kWRS * 2 >= NW * 4, "the wave sum reuses the dz tile");
+  __shared__ __attribute__((aligned(16))) uint16_t sdz[2 * CO * TR * kWRS];  // [hi/lo][co][row][col]
+  __shared__ __attribute__((aligned(16))) uint16_t sx[CIN * (TR + 2) * kWRS];  // [ci][row][col]
+  __shared__ float sbias[CO];
+  const int r0 = blockIdx.y * TR, c0 = blockIdx.x * kTC;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int i = threadIdx.x; i < 2 * TR * kTC * (CO / 8); i += NT) {
+    const int cg = i % (CO / 8);
+    int rest = i / (CO / 8);
+    const int col = rest % kTC;
+    rest /= kTC;
+    const int row = rest % TR, hl = rest / TR;
+    const int gr = r0 + row, gc = c0 + col;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (gr < H && gc < W) v = *(const uint4*)((hl ? dzl : dzh) + ((int64_t)gr * W + gc) * CO + cg * 8);
+    const uint32_t q[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+      sdz[((hl * CO + cg * 8 + k) * TR + row) * kWRS + col] = (uint16_t)(q[k >> 1] >> (16 * (k & 1)));
+  }
+  const int nt = wv % NCT, row0 = wv / NCT;
+  v4f acc[9][2];
+#pragma unroll
+  for (int t = 0; t < 9; t++)
+#pragma unroll
+    for (int m = 0; m < 2; m++) acc[t][m] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int dx = 0; dx < 3; dx++) {
+    __syncthreads();  // the previous copy of x has been read
+    for (int i = threadIdx.x; i < (TR + 2) * kTC * (CIN / 8); i += NT) {
+      const int cg = i % (CIN / 8);
+      const int rest = i / (CIN / 8);
+      const int col = rest % kTC, row = rest / kTC;
+      const int gr = r0 + row - 1, gc = c0 + col + dx - 1;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (gr >= 0 && gr < H && gc >= 0 && gc < W)
+        v = *(const uint4*)(x + ((int64_t)gr * W + gc) * CIN + cg * 8);
+      const uint32_t q[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 8; k++)
+        sx[((cg * 8 + k) * (TR + 2) + row) * kWRS + col] = (uint16_t)(q[k >> 1] >> (16 * (k & 1)));
+    }
+    __syncthreads();
+    for (int row = row0; row < TR; row += RSTEP) {
+#pragma unroll
+      for (int dy = 0; dy < 3; dy++) {
+        const int tap = dy * 3 + dx;
+#pragma unroll
+        for (int ks = 0; ks < kTC / 32; ks++) {
+          const v8bf b =
+              *(const v8bf*)(sx + ((nt * 16 + lr) * (TR + 2) + row + dy) * kWRS + ks * 32 + 8 * lk);
+#pragma unroll
+          for (int hl = 0; hl < 2; hl++)
+#pragma unroll
+            for (int mt = 0; mt < 2; mt++) {
+              const v8bf a =
+                  *(const v8bf*)(sdz + ((hl * CO + mt * 16 + lr) * TR + row) * kWRS + ks * 32 + 8 * lk);
+              acc[tap][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[tap][mt], 0, 0, 0);
+            }
+        }
+      }
+    }
+  }
+  // bias: the block's sum of dz (hi + lo) per output channel
+  if (threadIdx.x < CO) {
+    float sb = 0.0f;
+    for (int row = 0; row < TR; row++)
+      for (int col = 0; col < kTC; col++)
+        sb += from_bf16(sdz[((0 * CO + threadIdx.x) * TR + row) * kWRS + col]) +
+              from_bf16(sdz[((1 * CO + threadIdx.x) * TR + row) * kWRS + col]);
+    sbias[threadIdx.x] = sb;
+  }
+  __syncthreads();
+  float* red = (float*)sdz;  // [co][ci][tap]
+  for (int i = threadIdx.x; i < NW; i += NT) red[i] = 0.0f;
+  __syncthreads();
+  for (int w = 0; w < NWAVE; w++) {
+    if (wv == w) {
+#pragma unroll
+      for (int t = 0; t < 9; t++)
+#pragma unroll
+        for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+          for (int e = 0; e < 4; e++) {
+            const int co = mt * 16 + 4 * lk + e, ci = nt * 16 + lr;
+            const int idx = (co * CIN + ci) * 9 + t;
+            red[idx] += acc[t][mt][e];
+          }
+    }
+    __syncthreads();
+  }
+  const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+  float* out = part + (int64_t)blk * (NW + CO);
+  for (int i = threadIdx.x; i < NW; i += NT) out[i] = red[i];
+  if (threadIdx.x < CO) out[NW + threadIdx.x] = sbias[threadIdx.x];
+}
+
 // Two-stage fixed-order (deterministic) reduction of the weight-gradient
 // partials: stage 1 sums groups of kRedGroup consecutive tiles per parameter
 // (grid.y = group), stage 2 sums the groups and scales by 1 / count.
@@ -772,7 +893,11 @@ int32_t sgt_create(int32_t H, int32_t W, uint64_t seed, void* stream, sgt_net_t*
     o += layer_params(l);
   }
   const int64_t P = (int64_t)H * W;
+  // partial slots: the larger of the 16 x 16-tile VALU kernel's count and
+  // the 4-row x 64-pixel matrix-core kernel's
   n->part_blocks = ((W + 15) / 16) * ((H + 15) / 16);
+  const int mfma_blocks = ((W + kTC - 1) / kTC) * ((H + 3) / 4);
+  if (mfma_blocks > n->part_blocks) n->part_blocks = mfma_blocks;
   int64_t maxlp = 0;
   for (int l = 0; l < kNL; l++) maxlp = layer_params(l) > maxlp ? layer_params(l) : maxlp;
   hipError_t e = hipSuccess;
@@ -965,15 +1090,25 @@ int32_t sgt_loss_grad(sgt_net_t* n, const float* feat_dev, const float* label_de
   dim3 g8((W + kTC - 1) / kTC, (H + 7) / 8);
   for (int l = kNL - 1; l >= 0; l--) {
     const int64_t lp = layer_params(l);
-    if (l == 4)
+    // weight gradients: the 2-channel output layer on the VALU, the others on
+    // matrix cores (dz of those comes as the bf16 pair of the layer above)
+    int nb;
+    if (l == 4) {
       hipLaunchKernelGGL((k_bwd_weight<32, 2>), g16, dim3(256), 0, n->stream, dz, n->act[l], n->part, H, W);
-    else if (l == 0)
-      hipLaunchKernelGGL((k_bwd_weight<16, 32>), g16, dim3(256), 0, n->stream, dz, n->act[l], n->part, H, W);
-    else
-      hipLaunchKernelGGL((k_bwd_weight<32, 32>), g16, dim3(256), 0, n->stream, dz, n->act[l], n->part, H, W);
-    const int ng = (n->part_blocks + kRedGroup - 1) / kRedGroup;
+      nb = (int)(g16.x * g16.y);
+    } else {
+      const dim3 gw((W + kTC - 1) / kTC, (H + 3) / 4);
+      if (l == 0)
+        hipLaunchKernelGGL((k_bwd_weight_mfma<16, 4>), gw, dim3(256), 0, n->stream, n->dzh[hb],
+                           n->dzl[hb], n->act[l], n->part, H, W);
+      else
+        hipLaunchKernelGGL((k_bwd_weight_mfma<32, 4>), gw, dim3(256), 0, n->stream, n->dzh[hb],
+                           n->dzl[hb], n->act[l], n->part, H, W);
+      nb = (int)(gw.x * gw.y);
+    }
+    const int ng = (nb + kRedGroup - 1) / kRedGroup;
     hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for(lp), ng), dim3(256), 0, n->stream, n->part,
-                       n->part_blocks, lp, n->mid);
+                       nb, lp, n->mid);
     hipLaunchKernelGGL(k_reduce_mid, dim3(blocks_for(lp)), dim3(256), 0, n->stream, n->mid, ng, lp,
                        n->scal, n->grad + n->off[l]);
     if (l == 0) break;
