@@ -429,23 +429,27 @@ __global__ __launch_bounds__(256) void k_bwd_data(const float* __restrict__ dz,
   const uint16_t* xp = x + ((int64_t)r * W + c) * CIN;
   const int64_t o = ((int64_t)r * W + c) * CIN;
   static_assert(CIN % 8 == 0, "bf16 pairs are stored 8 channels at a time");
+#pragma unroll
   for (int k0 = 0; k0 < CIN; k0 += 8) {
+    const uint4 xq = *(const uint4*)(xp + k0);
+    const uint32_t xw[4] = {xq.x, xq.y, xq.z, xq.w};
+    float v[8];
     uint32_t hw[4], lw[4];
 #pragma unroll
-    for (int k = 0; k < 8; k += 2) {
-      float v2[2];
-      uint16_t hi[2], lo[2];
-#pragma unroll
-      for (int j = 0; j < 2; j++) {
-        v2[j] = from_bf16(xp[k0 + k + j]) > 0.0f ? acc[k0 + k + j] : 0.0f;
-        dprev[o + k0 + k + j] = v2[j];
-        // the bf16 pair the matrix-core kernels of the layer below read
-        hi[j] = to_bf16(v2[j]);
-        lo[j] = to_bf16(v2[j] - from_bf16(hi[j]));
-      }
-      hw[k / 2] = (uint32_t)hi[0] | ((uint32_t)hi[1] << 16);
-      lw[k / 2] = (uint32_t)lo[0] | ((uint32_t)lo[1] << 16);
+    for (int k = 0; k < 8; k++) {
+      const uint16_t xb = (uint16_t)(xw[k >> 1] >> (16 * (k & 1)));
+      v[k] = from_bf16(xb) > 0.0f ? acc[k0 + k] : 0.0f;
     }
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+      // the bf16 pair the matrix-core kernels of the layer below read
+      const uint16_t h0 = to_bf16(v[k]), h1 = to_bf16(v[k + 1]);
+      const uint16_t l0 = to_bf16(v[k] - from_bf16(h0)), l1 = to_bf16(v[k + 1] - from_bf16(h1));
+      hw[k / 2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      lw[k / 2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    }
+    *(float4*)(dprev + o + k0) = make_float4(v[0], v[1], v[2], v[3]);
+    *(float4*)(dprev + o + k0 + 4) = make_float4(v[4], v[5], v[6], v[7]);
     *(uint4*)(dph + o + k0) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
     *(uint4*)(dpl + o + k0) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
   }
@@ -537,65 +541,6 @@ __global__ __launch_bounds__(TR * 64) void k_bwd_data_mfma(const uint16_t* __res
       *(uint2*)(dpl + o) = make_uint2((uint32_t)lo[0] | ((uint32_t)lo[1] << 16),
                                       (uint32_t)lo[2] | ((uint32_t)lo[3] << 16));
     }
-}
-
-// Weight and bias gradient partials of one 16 x 16 pixel tile:
-// dW[co][ci][tap] += dz[p][co] x[p + tap][ci], db[co] += dz[p][co].
-// Thread t: ci = t % CIN, output channels (t / CIN) * G .. + G - 1.
-template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_bwd_weight(const float* __restrict__ dz,
-                                                    const uint16_t* __restrict__ x,
-                                                    float* __restrict__ part, int H, int W) {
-  constexpr int G = (COUT * CIN + 255) / 256;  // output channels per thread
-  __shared__ float sdz[256 * COUT];
-  __shared__ float sx[18 * 18 * CIN];
-  const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
-  for (int i = threadIdx.x; i < 256 * COUT; i += 256) {
-    const int pix = i / COUT, co = i - pix * COUT;
-    const int gr = r0 + pix / 16, gc = c0 + pix % 16;
-    sdz[i] = (gr < H && gc < W) ? dz[((int64_t)gr * W + gc) * COUT + co] : 0.0f;
-  }
-  for (int i = threadIdx.x; i < 18 * 18 * CIN; i += 256) {
-    const int pix = i / CIN, ci = i - pix * CIN;
-    const int gr = r0 + pix / 18 - 1, gc = c0 + pix % 18 - 1;
-    sx[i] = (gr >= 0 && gr < H && gc >= 0 && gc < W) ? from_bf16(x[((int64_t)gr * W + gc) * CIN + ci]) : 0.0f;
-  }
-  __syncthreads();
-  const int nblk = gridDim.x * gridDim.y;
-  const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-  const int64_t nparam = (int64_t)COUT * CIN * 9 + COUT;
-  float* out = part + (int64_t)blk * nparam;
-  (void)nblk;
-  const int ci = threadIdx.x % CIN, cog = threadIdx.x / CIN;
-  if (cog * G < COUT) {
-    float acc[G][9];
-    for (int g = 0; g < G; g++)
-      for (int t = 0; t < 9; t++) acc[g][t] = 0.0f;
-    for (int p = 0; p < 256; p++) {
-      const int pr = p / 16, pc = p % 16;
-      float xv[9];
-#pragma unroll
-      for (int t = 0; t < 9; t++) xv[t] = sx[((pr + t / 3) * 18 + pc + t % 3) * CIN + ci];
-#pragma unroll
-      for (int g = 0; g < G; g++) {
-        const int co = cog * G + g;
-        if (co >= COUT) break;
-        const float d = sdz[p * COUT + co];
-#pragma unroll
-        for (int t = 0; t < 9; t++) acc[g][t] = __builtin_fmaf(d, xv[t], acc[g][t]);
-      }
-    }
-    for (int g = 0; g < G; g++) {
-      const int co = cog * G + g;
-      if (co >= COUT) break;
-      for (int t = 0; t < 9; t++) out[((int64_t)co * CIN + ci) * 9 + t] = acc[g][t];
-    }
-  }
-  if (threadIdx.x < COUT) {
-    float b = 0.0f;
-    for (int p = 0; p < 256; p++) b += sdz[p * COUT + threadIdx.x];
-    out[(int64_t)COUT * CIN * 9 + threadIdx.x] = b;
-  }
 }
 
 // Weight and bias gradient partials on matrix cores, one per block of TR
@@ -717,6 +662,62 @@ __global__ __launch_bounds__(TR * 64) void k_bwd_weight_mfma(const uint16_t* __r
   float* out = part + (int64_t)blk * (NW + CO);
   for (int i = threadIdx.x; i < NW; i += NT) out[i] = red[i];
   if (threadIdx.x < CO) out[NW + threadIdx.x] = sbias[threadIdx.x];
+}
+
+// Weight and bias gradient partials of the 2-channel output layer, one per
+// 16 x 16 pixel tile: thread t takes input channel t % 32 and the 32 pixels
+// of group t / 32, and the 8 groups are summed in LDS in group order.
+__global__ __launch_bounds__(256) void k_bwd_weight_out(const float* __restrict__ dz,
+                                                        const uint16_t* __restrict__ x,
+                                                        float* __restrict__ part, int H, int W) {
+  constexpr int CIN = 32, COUT = 2, NW = COUT * CIN * 9;
+  __shared__ float sdz[256 * COUT];
+  __shared__ float sx[18 * 18 * CIN];
+  __shared__ float red[8][NW];
+  const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
+  for (int i = threadIdx.x; i < 256 * COUT; i += 256) {
+    const int pix = i / COUT, co = i - pix * COUT;
+    const int gr = r0 + pix / 16, gc = c0 + pix % 16;
+    sdz[i] = (gr < H && gc < W) ? dz[((int64_t)gr * W + gc) * COUT + co] : 0.0f;
+  }
+  for (int i = threadIdx.x; i < 18 * 18 * CIN; i += 256) {
+    const int pix = i / CIN, ci = i - pix * CIN;
+    const int gr = r0 + pix / 18 - 1, gc = c0 + pix % 18 - 1;
+    sx[i] = (gr >= 0 && gr < H && gc >= 0 && gc < W) ? from_bf16(x[((int64_t)gr * W + gc) * CIN + ci]) : 0.0f;
+  }
+  __syncthreads();
+  const int ci = threadIdx.x & 31, pg = threadIdx.x >> 5;
+  float acc[COUT][9];
+#pragma unroll
+  for (int c = 0; c < COUT; c++)
+#pragma unroll
+    for (int t = 0; t < 9; t++) acc[c][t] = 0.0f;
+  for (int p = pg * 32; p < pg * 32 + 32; p++) {
+    const int pr = p / 16, pc = p % 16;
+    const float d0 = sdz[p * COUT], d1 = sdz[p * COUT + 1];
+#pragma unroll
+    for (int t = 0; t < 9; t++) {
+      const float xv = sx[((pr + t / 3) * 18 + pc + t % 3) * CIN + ci];
+      acc[0][t] = __builtin_fmaf(d0, xv, acc[0][t]);
+      acc[1][t] = __builtin_fmaf(d1, xv, acc[1][t]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < COUT; c++)
+#pragma unroll
+    for (int t = 0; t < 9; t++) red[pg][(c * CIN + ci) * 9 + t] = acc[c][t];
+  __syncthreads();
+  float* out = part + (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * (NW + COUT);
+  for (int i = threadIdx.x; i < NW; i += 256) {
+    float sum = 0.0f;
+    for (int g = 0; g < 8; g++) sum += red[g][i];
+    out[i] = sum;
+  }
+  if (threadIdx.x < COUT) {
+    float b = 0.0f;
+    for (int p = 0; p < 256; p++) b += sdz[p * COUT + threadIdx.x];
+    out[NW + threadIdx.x] = b;
+  }
 }
 
 // Two-stage fixed-order (deterministic) reduction of the weight-gradient
@@ -1094,7 +1095,7 @@ int32_t sgt_loss_grad(sgt_net_t* n, const float* feat_dev, const float* label_de
     // matrix cores (dz of those comes as the bf16 pair of the layer above)
     int nb;
     if (l == 4) {
-      hipLaunchKernelGGL((k_bwd_weight<32, 2>), g16, dim3(256), 0, n->stream, dz, n->act[l], n->part, H, W);
+      hipLaunchKernelGGL(k_bwd_weight_out, g16, dim3(256), 0, n->stream, dz, n->act[l], n->part, H, W);
       nb = (int)(g16.x * g16.y);
     } else {
       const dim3 gw((W + kTC - 1) / kTC, (H + 3) / 4);
