@@ -639,10 +639,10 @@ def bench_surrogate(args):
            "config": {"workload": "features of a thinned 64-beam single-scan map, 512x512, "
                                   "conv3x3 16-32-32-32-32-2", "pixels": n},
            "train_step_ms": t_train * 1e3,
-           # a training step = forward + input gradients + weight gradients,
-           # three convolutions' worth of MACs per layer (the loss and Adam
-           # are negligible): 3 x the forward's FLOP
-           "train_tflop_per_s": 3 * flops / t_train / 1e12,
+           # a training step = forward + weight gradients (as many MACs as
+           # the forward) + input gradients (the same, less the first layer,
+           # whose input needs none); the loss and Adam are negligible
+           "train_tflop_per_s": (3 * flops - 2 * 9 * 16 * 32 * n) / t_train / 1e12,
            "roofline": {"kernel": "forward (5 convolutions)", "bound": "mfma",
                         "achieved": flops / t_fwd / 1e12, "peak": peak, "unit": "TFLOP/s",
                         "frac": flops / t_fwd / 1e12 / peak, "traffic": None,
