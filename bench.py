@@ -330,7 +330,7 @@ def main():
         print(source_sha(TRACE_SRCS))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(independent maps would shard one per GPU with no exchange).", file=sys.stderr)
         sys.exit(2)
 
