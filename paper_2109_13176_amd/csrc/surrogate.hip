@@ -735,13 +735,20 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const float* part, int nb,
   mid[(int64_t)blockIdx.y * np + o] = s;
 }
 
+// Stage 2: a block takes 64 parameters (one per lane); wave w sums the
+// groups w, w + 4, ... in order, and the four sums are added in a fixed order.
 __global__ __launch_bounds__(256) void k_reduce_mid(const double* mid, int ng, int64_t np,
                                                     const double* scal, float* grad) {
-  const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (o >= np) return;
+  __shared__ double ws[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t o = (int64_t)blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int g = 0; g < ng; g++) s += mid[(int64_t)g * np + o];
-  grad[o] = (float)(s * scal[1]);
+  if (o < np)
+    for (int g = w; g < ng; g += 4) s += mid[(int64_t)g * np + o];
+  ws[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && o < np)
+    grad[o] = (float)(((ws[0][lane] + ws[1][lane]) + (ws[2][lane] + ws[3][lane])) * scal[1]);
 }
 
 // Adam on the fp32 master weights; the bf16 copy is repacked afterwards.
@@ -1110,7 +1117,7 @@ int32_t sgt_loss_grad(sgt_net_t* n, const float* feat_dev, const float* label_de
     const int ng = (nb + kRedGroup - 1) / kRedGroup;
     hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for(lp), ng), dim3(256), 0, n->stream, n->part,
                        nb, lp, n->mid);
-    hipLaunchKernelGGL(k_reduce_mid, dim3(blocks_for(lp)), dim3(256), 0, n->stream, n->mid, ng, lp,
+    hipLaunchKernelGGL(k_reduce_mid, dim3((unsigned)((lp + 63) / 64)), dim3(256), 0, n->stream, n->mid, ng, lp,
                        n->scal, n->grad + n->off[l]);
     if (l == 0) break;
     if (l == 4)
