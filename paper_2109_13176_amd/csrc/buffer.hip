@@ -333,11 +333,227 @@ struct IncArgs {
   int32_t ev_org[3];
 };
 
-__global__ __launch_bounds__(kBrickThreads) void k_combine_inc(const CombineArgs a,
-                                                               const IncArgs u) {
+// One item of the update (all lanes of a wave call it together: the evicted
+// minima are recombined wave-wide).  n4 / e4_all: the item's entries in the
+// newest and the evicted map's tables.
+__device__ __forceinline__ void inc_item(const CombineArgs& a, const IncArgs& u, const int i,
+                                         const bool active, const int lane,
+                                         const int32_t* my_lut, const map_voxel_t* my_data,
+                                         const int64_t my_cap, const int32_t* my_org,
+                                         const int4 n4, const int4 e4_all) {
   const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
+  const int per_brick = nz * 4;
+  const int ic = active ? i : 0;
+  const int b = ic / per_brick;
+  const int r = ic - b * per_brick;
+  const int z = r >> 2, q = r & 3;
+  int bx, by;
+  brick_xy(a.d, b, bx, by);
+  const int64_t s = (int64_t)ic << 2;
+  int32_t gx[4], gy, gz;
+  const unsigned valid = item_world(a, bx, by, z, q, gx, gy, gz) & (active ? 15u : 0u);
+  const bool old_yz = (uint32_t)(gy - u.O_old[1]) < (uint32_t)ny &&
+                      (uint32_t)(gz - u.O_old[2]) < (uint32_t)nz;
+  const bool ev_yz = u.has_ev && (uint32_t)(gy - u.ev_org[1]) < (uint32_t)ny &&
+                     (uint32_t)(gz - u.ev_org[2]) < (uint32_t)nz;
+  const int4 e4 = ev_yz ? e4_all : make_int4(-1, -1, -1, -1);
+  const int32_t nw[4] = {n4.x, n4.y, n4.z, n4.w};
+  int32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
+  unsigned enter = 0u, upd = 0u, hit = 0u, evo = 0u;
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    if ((uint32_t)(gx[e] - u.ev_org[0]) >= (uint32_t)nx) ev[e] = -1;
+    if (!((valid >> e) & 1u)) continue;
+    const bool in_old = old_yz && (uint32_t)(gx[e] - u.O_old[0]) < (uint32_t)nx;
+    if (!in_old) enter |= 1u << e;
+    else if (ev[e] >= 0) evo |= 1u << e;
+    else if (ev[e] != -1 || nw[e] != -1) upd |= 1u << e;
+    if (nw[e] >= 0) hit |= 1u << e;
+  }
+  // only misses change where neither map has a return: hits and lowest
+  // return are read and written where a map has one or the voxel is
+  // combined in full
+  const unsigned hm = enter | evo | (upd & hit);
+  int32_t h[4] = {0, 0, 0, 0}, p[4] = {0, 0, 0, 0}, mq[4] = {0, 0, 0, 0};
+  if (enter | evo | upd) {
+    const int4 p4 = *(const int4*)(a.passes + s);
+    p[0] = p4.x; p[1] = p4.y; p[2] = p4.z; p[3] = p4.w;
+  }
+  if (hm) {
+    const int4 h4 = *(const int4*)(a.hits + s);
+    const int4 m4 = *(const int4*)(a.minqz + s);
+    h[0] = h4.x; h[1] = h4.y; h[2] = h4.z; h[3] = h4.w;
+    mq[0] = m4.x; mq[1] = m4.y; mq[2] = m4.z; mq[3] = m4.w;
+  }
+  const int32_t h_old[4] = {h[0], h[1], h[2], h[3]};
+  map_voxel_t evd[4];
+  unsigned coop = 0u;
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    if (!((evo >> e) & 1u)) continue;
+    // the evicted map's lowest return is above the combined minimum: the
+    // minimum stays, its counts come off; otherwise the voxel is combined
+    // again from every map
+    if (ev[e] < u.ev_cap) evd[e] = u.ev_data[ev[e]];
+    if (ev[e] < u.ev_cap && evd[e].min_qz > mq[e]) upd |= 1u << e;
+    else coop |= 1u << e;
+  }
+  // voxels that entered with the window: dense (whole slabs), each lane
+  // combines its own
+  if (enter) sum_maps(a, s, gx, gy, gz, enter, h, p, mq);
+  // voxels whose minimum went with the evicted map: scattered, so the wave
+  // combines them one at a time with one lane per buffered map
+  unsigned long long lanes = __ballot(coop != 0u);
+  while (lanes) {
+    const int L = __ffsll((long long)lanes) - 1;
+    lanes &= lanes - 1;
+    const unsigned cm = (unsigned)__builtin_amdgcn_readlane((int)coop, L);
+    const int iL = __builtin_amdgcn_readlane(ic, L);
+    const int gyL = __builtin_amdgcn_readlane(gy, L);
+    const int gzL = __builtin_amdgcn_readlane(gz, L);
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      if (!((cm >> e) & 1u)) continue;
+      const int gxL = __builtin_amdgcn_readlane(gx[e], L);
+      int32_t hh = 0, pp = 0, mm = INT32_MAX;
+      if (lane < a.k && (uint32_t)(gxL - my_org[0]) < (uint32_t)nx &&
+          (uint32_t)(gyL - my_org[1]) < (uint32_t)ny &&
+          (uint32_t)(gzL - my_org[2]) < (uint32_t)nz) {
+        const int32_t v = my_lut[((int64_t)iL << 2) + e];
+        if (v >= 0) {
+          if (v < my_cap) {
+            const map_voxel_t dv = my_data[v];
+            hh = dv.hits;
+            pp = dv.passes;
+            mm = dv.min_qz;
+          }
+        } else {
+          pp = -1 - v;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        hh += __shfl_xor(hh, o);
+        pp += __shfl_xor(pp, o);
+        mm = min(mm, __shfl_xor(mm, o));
+      }
+      if (lane == L) {
+        h[e] = hh;
+        p[e] = pp;
+        mq[e] = mm;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    if (!((upd >> e) & 1u)) continue;
+    if (ev[e] >= 0) {
+      h[e] -= evd[e].hits;
+      p[e] -= evd[e].passes;
+    } else if (ev[e] < -1) {
+      p[e] -= -1 - ev[e];
+    }
+    if (nw[e] >= 0) {
+      if (nw[e] < u.nw_cap) {
+        const map_voxel_t dv = u.nw_data[nw[e]];
+        h[e] += dv.hits;
+        p[e] += dv.passes;
+        mq[e] = min(mq[e], dv.min_qz);
+      }
+    } else {
+      p[e] += -1 - nw[e];
+    }
+  }
+  if (enter | evo | upd) *(int4*)(a.passes + s) = make_int4(p[0], p[1], p[2], p[3]);
+  if (hm) {
+    *(int4*)(a.hits + s) = make_int4(h[0], h[1], h[2], h[3]);
+    *(int4*)(a.minqz + s) = make_int4(mq[0], mq[1], mq[2], mq[3]);
+    // occupancy bit = hits >= 1; flip it only where that changed (the old
+    // bit of an entering voxel belongs to the voxel that left)
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      if (!((hm >> e) & 1u) || (h_old[e] > 0) == (h[e] > 0)) continue;
+      unsigned long long* w =
+          a.occ + ((int64_t)(4 * bx + e) * ny + (4 * by + q)) * a.d.W + (z >> 6);
+      const unsigned long long bit = 1ull << (z & 63);
+      if (h[e] > 0) atomicOr(w, bit);
+      else atomicAnd(w, ~bit);
+    }
+  }
+}
+
+// Classification of an item for the update: does any voxel change (entered
+// the window, or the newest or the evicted map has something there)?
+__device__ __forceinline__ bool inc_changed(const CombineArgs& a, const IncArgs& u, const int i,
+                                            const int4 n4, const int4 e4_all) {
+  const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
+  const int per_brick = nz * 4;
+  const int b = i / per_brick;
+  const int r = i - b * per_brick;
+  const int z = r >> 2, q = r & 3;
+  int bx, by;
+  brick_xy(a.d, b, bx, by);
+  int32_t gx[4], gy, gz;
+  const unsigned valid = item_world(a, bx, by, z, q, gx, gy, gz);
+  const bool old_yz = (uint32_t)(gy - u.O_old[1]) < (uint32_t)ny &&
+                      (uint32_t)(gz - u.O_old[2]) < (uint32_t)nz;
+  const bool ev_yz = u.has_ev && (uint32_t)(gy - u.ev_org[1]) < (uint32_t)ny &&
+                     (uint32_t)(gz - u.ev_org[2]) < (uint32_t)nz;
+  const int32_t nw[4] = {n4.x, n4.y, n4.z, n4.w};
+  const int32_t ev4[4] = {e4_all.x, e4_all.y, e4_all.z, e4_all.w};
+  bool changed = false;
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    if (!((valid >> e) & 1u)) continue;
+    const int32_t ev = ev_yz && (uint32_t)(gx[e] - u.ev_org[0]) < (uint32_t)nx ? ev4[e] : -1;
+    const bool in_old = old_yz && (uint32_t)(gx[e] - u.O_old[0]) < (uint32_t)nx;
+    changed |= !in_old || ev != -1 || nw[e] != -1;
+  }
+  return changed;
+}
+
+// Pass 1 of the update: stream both tables once and list the items that
+// change, per block (block b's list holds the items of its grid-stride walk,
+// at most `cap`).
+__global__ __launch_bounds__(kBrickThreads) void k_inc_find(const CombineArgs a, const IncArgs u,
+                                                            int32_t* __restrict__ list,
+                                                            int32_t* __restrict__ cnt,
+                                                            const int cap) {
+  __shared__ int32_t scount;
+  if (threadIdx.x == 0) scount = 0;
+  __syncthreads();
   const int lane = threadIdx.x & 63;
-  // lane j holds buffered map j for the wave-wide recombination below
+  const int n_items = (int)(a.d.vs >> 2);
+  const int stride = gridDim.x * kBrickThreads;
+  int32_t* mine = list + (int64_t)blockIdx.x * cap;
+  for (int base = blockIdx.x * kBrickThreads; base < n_items; base += stride) {
+    const int i = base + threadIdx.x;
+    bool changed = false;
+    if (i < n_items) {
+      const int4 n4 = *(const int4*)(u.nw_lut + ((int64_t)i << 2));
+      const int4 e4 = u.has_ev ? *(const int4*)(u.ev_lut + ((int64_t)i << 2))
+                               : make_int4(-1, -1, -1, -1);
+      changed = inc_changed(a, u, i, n4, e4);
+    }
+    const unsigned long long m = __ballot(changed);
+    int wbase = 0;
+    if (lane == 0 && m) wbase = atomicAdd(&scount, __popcll(m));
+    wbase = __shfl(wbase, 0);
+    if (changed) mine[wbase + __popcll(m & ((1ull << lane) - 1ull))] = i;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[blockIdx.x] = scount;
+}
+
+// Pass 2: every listed item updated (the list order does not matter: items
+// are disjoint, and occupancy bits are flipped by atomics).
+__global__ __launch_bounds__(kBrickThreads) void k_combine_inc(const CombineArgs a,
+                                                               const IncArgs u,
+                                                               const int32_t* __restrict__ list,
+                                                               const int32_t* __restrict__ cnt,
+                                                               const int cap) {
+  const int lane = threadIdx.x & 63;
+  // lane j holds buffered map j for the wave-wide recombination
   const int32_t* my_lut = nullptr;
   const map_voxel_t* my_data = nullptr;
   int64_t my_cap = 0;
@@ -352,171 +568,19 @@ __global__ __launch_bounds__(kBrickThreads) void k_combine_inc(const CombineArgs
       my_org[2] = a.org[k][2];
     }
   }
-  const int per_brick = nz * 4;
-  const int n_items = (int)(a.d.vs >> 2);
-  const int stride = gridDim.x * kBrickThreads;
-  // a grid-stride walk over the items in storage order; the bound is uniform
-  // per block, so every lane reaches the wave-wide step.  The next item's two
-  // table entries are loaded before this item's state is read and written,
-  // so the walk keeps one round trip in flight per item, not two.
-  int4 n4_next = make_int4(-1, -1, -1, -1), e4_next = make_int4(-1, -1, -1, -1);
-  {
-    const int i0 = blockIdx.x * kBrickThreads + threadIdx.x;
-    if (i0 < n_items) {
-      n4_next = *(const int4*)(u.nw_lut + ((int64_t)i0 << 2));
-      if (u.has_ev) e4_next = *(const int4*)(u.ev_lut + ((int64_t)i0 << 2));
+  const int c = cnt[blockIdx.x];
+  const int32_t* mine = list + (int64_t)blockIdx.x * cap;
+  // the bound is uniform per block, so every lane reaches the wave-wide step
+  for (int j0 = 0; j0 < c; j0 += kBrickThreads) {
+    const int j = j0 + threadIdx.x;
+    const bool active = j < c;
+    const int i = active ? mine[j] : 0;
+    int4 n4 = make_int4(-1, -1, -1, -1), e4 = make_int4(-1, -1, -1, -1);
+    if (active) {
+      n4 = *(const int4*)(u.nw_lut + ((int64_t)i << 2));
+      if (u.has_ev) e4 = *(const int4*)(u.ev_lut + ((int64_t)i << 2));
     }
-  }
-  for (int base = blockIdx.x * kBrickThreads; base < n_items; base += stride) {
-    const int i = base + threadIdx.x;
-    const bool active = i < n_items;
-    const int ic = active ? i : 0;
-    const int4 n4 = n4_next, e4_all = e4_next;
-    {
-      const int in = i + stride;
-      n4_next = make_int4(-1, -1, -1, -1);
-      e4_next = make_int4(-1, -1, -1, -1);
-      if (in < n_items) {
-        n4_next = *(const int4*)(u.nw_lut + ((int64_t)in << 2));
-        if (u.has_ev) e4_next = *(const int4*)(u.ev_lut + ((int64_t)in << 2));
-      }
-    }
-    const int b = ic / per_brick;
-    const int r = ic - b * per_brick;
-    const int z = r >> 2, q = r & 3;
-    int bx, by;
-    brick_xy(a.d, b, bx, by);
-    const int64_t s = (int64_t)ic << 2;
-    int32_t gx[4], gy, gz;
-    const unsigned valid = item_world(a, bx, by, z, q, gx, gy, gz) & (active ? 15u : 0u);
-    const bool old_yz = (uint32_t)(gy - u.O_old[1]) < (uint32_t)ny &&
-                        (uint32_t)(gz - u.O_old[2]) < (uint32_t)nz;
-    const bool ev_yz = u.has_ev && (uint32_t)(gy - u.ev_org[1]) < (uint32_t)ny &&
-                       (uint32_t)(gz - u.ev_org[2]) < (uint32_t)nz;
-    const int4 e4 = ev_yz ? e4_all : make_int4(-1, -1, -1, -1);
-    const int32_t nw[4] = {n4.x, n4.y, n4.z, n4.w};
-    int32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
-    unsigned enter = 0u, upd = 0u, hit = 0u, evo = 0u;
-#pragma unroll
-    for (int e = 0; e < 4; e++) {
-      if ((uint32_t)(gx[e] - u.ev_org[0]) >= (uint32_t)nx) ev[e] = -1;
-      if (!((valid >> e) & 1u)) continue;
-      const bool in_old = old_yz && (uint32_t)(gx[e] - u.O_old[0]) < (uint32_t)nx;
-      if (!in_old) enter |= 1u << e;
-      else if (ev[e] >= 0) evo |= 1u << e;
-      else if (ev[e] != -1 || nw[e] != -1) upd |= 1u << e;
-      if (nw[e] >= 0) hit |= 1u << e;
-    }
-    // only misses change where neither map has a return: hits and lowest
-    // return are read and written where a map has one or the voxel is
-    // combined in full
-    const unsigned hm = enter | evo | (upd & hit);
-    int32_t h[4] = {0, 0, 0, 0}, p[4] = {0, 0, 0, 0}, mq[4] = {0, 0, 0, 0};
-    if (enter | evo | upd) {
-      const int4 p4 = *(const int4*)(a.passes + s);
-      p[0] = p4.x; p[1] = p4.y; p[2] = p4.z; p[3] = p4.w;
-    }
-    if (hm) {
-      const int4 h4 = *(const int4*)(a.hits + s);
-      const int4 m4 = *(const int4*)(a.minqz + s);
-      h[0] = h4.x; h[1] = h4.y; h[2] = h4.z; h[3] = h4.w;
-      mq[0] = m4.x; mq[1] = m4.y; mq[2] = m4.z; mq[3] = m4.w;
-    }
-    const int32_t h_old[4] = {h[0], h[1], h[2], h[3]};
-    map_voxel_t evd[4];
-    unsigned coop = 0u;
-#pragma unroll
-    for (int e = 0; e < 4; e++) {
-      if (!((evo >> e) & 1u)) continue;
-      // the evicted map's lowest return is above the combined minimum: the
-      // minimum stays, its counts come off; otherwise the voxel is combined
-      // again from every map
-      if (ev[e] < u.ev_cap) evd[e] = u.ev_data[ev[e]];
-      if (ev[e] < u.ev_cap && evd[e].min_qz > mq[e]) upd |= 1u << e;
-      else coop |= 1u << e;
-    }
-    // voxels that entered with the window: dense (whole slabs), each lane
-    // combines its own
-    if (enter) sum_maps(a, s, gx, gy, gz, enter, h, p, mq);
-    // voxels whose minimum went with the evicted map: scattered, so the wave
-    // combines them one at a time with one lane per buffered map
-    unsigned long long lanes = __ballot(coop != 0u);
-    while (lanes) {
-      const int L = __ffsll((long long)lanes) - 1;
-      lanes &= lanes - 1;
-      const unsigned cm = (unsigned)__builtin_amdgcn_readlane((int)coop, L);
-      const int iL = __builtin_amdgcn_readlane(ic, L);
-      const int gyL = __builtin_amdgcn_readlane(gy, L);
-      const int gzL = __builtin_amdgcn_readlane(gz, L);
-#pragma unroll
-      for (int e = 0; e < 4; e++) {
-        if (!((cm >> e) & 1u)) continue;
-        const int gxL = __builtin_amdgcn_readlane(gx[e], L);
-        int32_t hh = 0, pp = 0, mm = INT32_MAX;
-        if (lane < a.k && (uint32_t)(gxL - my_org[0]) < (uint32_t)nx &&
-            (uint32_t)(gyL - my_org[1]) < (uint32_t)ny &&
-            (uint32_t)(gzL - my_org[2]) < (uint32_t)nz) {
-          const int32_t v = my_lut[((int64_t)iL << 2) + e];
-          if (v >= 0) {
-            if (v < my_cap) {
-              const map_voxel_t dv = my_data[v];
-              hh = dv.hits;
-              pp = dv.passes;
-              mm = dv.min_qz;
-            }
-          } else {
-            pp = -1 - v;
-          }
-        }
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-          hh += __shfl_xor(hh, o);
-          pp += __shfl_xor(pp, o);
-          mm = min(mm, __shfl_xor(mm, o));
-        }
-        if (lane == L) {
-          h[e] = hh;
-          p[e] = pp;
-          mq[e] = mm;
-        }
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 4; e++) {
-      if (!((upd >> e) & 1u)) continue;
-      if (ev[e] >= 0) {
-        h[e] -= evd[e].hits;
-        p[e] -= evd[e].passes;
-      } else if (ev[e] < -1) {
-        p[e] -= -1 - ev[e];
-      }
-      if (nw[e] >= 0) {
-        if (nw[e] < u.nw_cap) {
-          const map_voxel_t dv = u.nw_data[nw[e]];
-          h[e] += dv.hits;
-          p[e] += dv.passes;
-          mq[e] = min(mq[e], dv.min_qz);
-        }
-      } else {
-        p[e] += -1 - nw[e];
-      }
-    }
-    if (enter | evo | upd) *(int4*)(a.passes + s) = make_int4(p[0], p[1], p[2], p[3]);
-    if (hm) {
-      *(int4*)(a.hits + s) = make_int4(h[0], h[1], h[2], h[3]);
-      *(int4*)(a.minqz + s) = make_int4(mq[0], mq[1], mq[2], mq[3]);
-      // occupancy bit = hits >= 1; flip it only where that changed (the old
-      // bit of an entering voxel belongs to the voxel that left)
-#pragma unroll
-      for (int e = 0; e < 4; e++) {
-        if (!((hm >> e) & 1u) || (h_old[e] > 0) == (h[e] > 0)) continue;
-        unsigned long long* w =
-            a.occ + ((int64_t)(4 * bx + e) * ny + (4 * by + q)) * a.d.W + (z >> 6);
-        const unsigned long long bit = 1ull << (z & 63);
-        if (h[e] > 0) atomicOr(w, bit);
-        else atomicAnd(w, ~bit);
-      }
-    }
+    inc_item(a, u, i, active, lane, my_lut, my_data, my_cap, my_org, n4, e4);
   }
 }
 
@@ -552,6 +616,9 @@ struct map_buffer_t {
   // the last combine: a combine into the same, unchanged map one push later
   // updates it instead of combining every buffered map again
   bool incremental;
+  int32_t* inc_list;            // the update's per-block lists of changed items
+  int32_t* inc_cnt;             // [inc_grid] listed items per block
+  int inc_grid, inc_cap;        // blocks of the update passes; list slots per block
   map_t* last_out;
   uint64_t last_version;
   int64_t last_npush;
@@ -609,12 +676,23 @@ int32_t map_buffer_create(const map_params_t* p, int32_t depth, void* stream,
   b->slots.assign(b->ring, map_buffer_t::Slot{nullptr, nullptr, 0, {0, 0, 0}});
   b->npush = 0;
   b->incremental = true;
+  {
+    const int64_t items = prod->d.vs / 4;
+    int64_t grid = (items + gvom::kBrickThreads - 1) / gvom::kBrickThreads;
+    if (grid > (int64_t)prod->n_cu * 8) grid = (int64_t)prod->n_cu * 8;
+    const int64_t rounds = (items + grid * gvom::kBrickThreads - 1) / (grid * gvom::kBrickThreads);
+    b->inc_grid = (int)grid;
+    b->inc_cap = (int)(rounds * gvom::kBrickThreads);
+  }
   b->last_out = nullptr;
   b->sticky = MAP_OK;
   const int64_t nb = gvom::n_bricks(prod->d);
   hipError_t e = hipMalloc((void**)&b->brick_cnt, (size_t)nb * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&b->group_cnt, (size_t)((nb + 15) / 16) * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&b->n_occ, (size_t)b->ring * 8);
+  if (e == hipSuccess)
+    e = hipMalloc((void**)&b->inc_list, (size_t)b->inc_grid * b->inc_cap * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->inc_cnt, (size_t)b->inc_grid * 4);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->pushed, hipEventDisableTiming);
   else b->pushed = nullptr;
   for (int i = 0; i < b->ring && e == hipSuccess; i++) {
@@ -645,6 +723,8 @@ int32_t map_buffer_destroy(map_buffer_t* b) {
   (void)hipFree(b->brick_cnt);
   (void)hipFree(b->group_cnt);
   (void)hipFree(b->n_occ);
+  (void)hipFree(b->inc_list);
+  (void)hipFree(b->inc_cnt);
   if (b->pushed) (void)hipEventDestroy(b->pushed);
   map_destroy(b->prod);
   (void)hipGetLastError();
@@ -814,11 +894,12 @@ int32_t map_buffer_combine(map_buffer_t* b, map_t* out) {
   if (e == hipSuccess) {
     const dim3 blk(gvom::kBrickThreads);
     if (inc) {
-      // eight blocks per CU walk the items
-      const int64_t items = out->d.vs / 4;
-      int64_t grid = (items + gvom::kBrickThreads - 1) / gvom::kBrickThreads;
-      if (grid > (int64_t)out->n_cu * 8) grid = (int64_t)out->n_cu * 8;
-      hipLaunchKernelGGL(gvom::k_combine_inc, dim3((unsigned)grid), blk, 0, out->stream, a, u);
+      // list the changed items while streaming both tables, then update them
+      const dim3 g((unsigned)b->inc_grid);
+      hipLaunchKernelGGL(gvom::k_inc_find, g, blk, 0, out->stream, a, u, b->inc_list, b->inc_cnt,
+                         b->inc_cap);
+      hipLaunchKernelGGL(gvom::k_combine_inc, g, blk, 0, out->stream, a, u, b->inc_list,
+                         b->inc_cnt, b->inc_cap);
     } else {
       hipLaunchKernelGGL(gvom::k_combine, dim3((unsigned)gvom::n_bricks(out->d)), blk, 0,
                          out->stream, a);
