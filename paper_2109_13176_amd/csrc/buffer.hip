@@ -37,7 +37,7 @@ struct SlotArgs {
   int32_t* hits;                  // producer state, left empty
   int32_t* passes;
   int32_t* minqz;
-  const unsigned long long* occ;
+  unsigned long long* occ;        // read, then cleared (each block owns its brick's columns)
   int32_t* lut;                   // slot: lookup table in storage order
   map_voxel_t* data;              // slot: data array
   int64_t cap;
@@ -106,7 +106,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_slot_count(Dims d,
 // 4q .. 4q+3 of the brick at z, so items are in storage order and the rank of
 // an occupied voxel is the brick's base plus a block scan of the item counts.
 // Every non-zero passes word is zeroed; hits and lowest return only where
-// occupied (they are empty elsewhere).
+// occupied (they are empty elsewhere); the brick's occupancy words are
+// cleared once read.
 __global__ __launch_bounds__(kBrickThreads) void k_slot_write(SlotArgs a) {
   __shared__ unsigned long long mlo[16], mhi[16];
   __shared__ int32_t wtot[kBrickThreads / 64];
@@ -128,7 +129,11 @@ __global__ __launch_bounds__(kBrickThreads) void k_slot_write(SlotArgs a) {
     if (sx < a.d.nx && sy < a.d.ny) {
       const int64_t col = ((int64_t)sx * a.d.ny + sy) * a.d.W;
       lo = a.occ[col];
-      if (a.d.W > 1) hi = a.occ[col + 1];
+      a.occ[col] = 0ull;
+      if (a.d.W > 1) {
+        hi = a.occ[col + 1];
+        a.occ[col + 1] = 0ull;
+      }
     }
     mlo[t] = lo;
     mhi[t] = hi;
@@ -819,9 +824,6 @@ int32_t map_buffer_push(map_buffer_t* b, const float* xyz_dev, int64_t n, const 
                        b->stream, a);
     e = hipGetLastError();
   }
-  if (e == hipSuccess)
-    e = gvom::launch_fill_i32((int32_t*)m->occ, 0, (int64_t)m->p.nx * m->p.ny * d.W * 2,
-                              b->stream);
   if (e == hipSuccess) e = hipEventRecord(b->pushed, b->stream);
   if (e != hipSuccess) {
     m->sticky = MAP_E_DEVICE;
