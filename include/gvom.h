@@ -167,12 +167,21 @@ int32_t map_export_2d(map_t* m, const map_2d_t* out_dev);
  *             -1 - passes.
  *  data_dev:  device map_voxel_t[cap] in rank order; ranks >= cap are not
  *             written (cap may be 0 with data_dev NULL).
- *  n_occupied_dev: device int64 receiving the number of occupied voxels M;
- *             the caller detects truncation by M > cap.
+ *  n_occupied: host int64 receiving the number of occupied voxels M; written
+ *             also when the data array is too small.
  *  origin_vox: host int32[3], receives the window origin (world voxel).
- * Does not synchronise. */
+ * Synchronises the map's stream (to read M).  Returns MAP_E_CAPACITY when
+ * cap < M: the table and the first cap entries are written and *n_occupied
+ * holds M. */
 int32_t map_export_voxels(map_t* m, int32_t* lut_dev, map_voxel_t* data_dev, int64_t cap,
-                          int64_t* n_occupied_dev, int32_t origin_vox[3]);
+                          int64_t* n_occupied, int32_t origin_vox[3]);
+
+/* The same export without waiting: M goes to the DEVICE int64
+ * n_occupied_dev (valid once the stream has been synchronised) and a data
+ * array that is too small is not reported (the caller compares M with cap).
+ * For pipelines that keep the host off the critical path. */
+int32_t map_export_voxels_async(map_t* m, int32_t* lut_dev, map_voxel_t* data_dev, int64_t cap,
+                                int64_t* n_occupied_dev, int32_t origin_vox[3]);
 
 /* The voxel map itself as an output (Sec. I and Fig. 1, where denser voxels
  * are drawn more opaque; Sec. V): density_dev is a device float[nx*ny*nz] in

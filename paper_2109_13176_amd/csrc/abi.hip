@@ -250,6 +250,7 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   if (e == hipSuccess) e = dmalloc(&m->colpre, C * 4);
   if (e == hipSuccess) e = dmalloc(&m->stats, kStatsBytes);
   if (e == hipSuccess) e = dmalloc(&m->err, 4);
+  if (e == hipSuccess) e = dmalloc(&m->nocc, 8);
   if (e == hipSuccess) e = dmalloc(&m->part_trace, m->part_trace_cap * 32);
   if (e == hipSuccess) e = dmalloc(&m->box_rep, (int64_t)gvom::kBoxReps * gvom::kBoxCells * 4);
   if (e == hipSuccess)
@@ -295,6 +296,7 @@ int32_t map_destroy(map_t* m) {
   (void)hipFree(m->colpre);
   (void)hipFree(m->stats);
   (void)hipFree(m->err);
+  (void)hipFree(m->nocc);
   (void)hipFree(m->touch);
   (void)hipFree(m->items);
   (void)hipFree(m->part_rays);
@@ -614,8 +616,8 @@ int32_t map_export_2d(map_t* m, const map_2d_t* out) {
   return dev_status(m, e);
 }
 
-int32_t map_export_voxels(map_t* m, int32_t* lut_dev, map_voxel_t* data_dev, int64_t cap,
-                          int64_t* n_occupied_dev, int32_t origin_vox[3]) {
+int32_t map_export_voxels_async(map_t* m, int32_t* lut_dev, map_voxel_t* data_dev, int64_t cap,
+                                int64_t* n_occupied_dev, int32_t origin_vox[3]) {
   if (!m || !lut_dev || !n_occupied_dev || !origin_vox || cap < 0 || (cap > 0 && !data_dev))
     return MAP_E_INVALID;
   if (m->sticky) return m->sticky;
@@ -629,6 +631,20 @@ int32_t map_export_voxels(map_t* m, int32_t* lut_dev, map_voxel_t* data_dev, int
   prof_end(m, pm);
   for (int i = 0; i < 3; i++) origin_vox[i] = m->origin[i];
   return dev_status(m, e);
+}
+
+int32_t map_export_voxels(map_t* m, int32_t* lut_dev, map_voxel_t* data_dev, int64_t cap,
+                          int64_t* n_occupied, int32_t origin_vox[3]) {
+  if (!m || !n_occupied) return MAP_E_INVALID;
+  int32_t s = map_export_voxels_async(m, lut_dev, data_dev, cap, m->nocc, origin_vox);
+  if (s) return s;
+  int64_t count = 0;
+  hipError_t e = hipMemcpyAsync(&count, m->nocc, 8, hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  s = dev_status(m, e);
+  if (s) return s;
+  *n_occupied = count;
+  return count > cap ? MAP_E_CAPACITY : MAP_OK;
 }
 
 int32_t map_export_density(map_t* m, float* density_dev) {

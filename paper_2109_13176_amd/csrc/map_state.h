@@ -22,6 +22,7 @@ struct map_t {
   int32_t* colpre;
   unsigned long long* stats;  // 8 counters
   int32_t* err;
+  int64_t* nocc;              // occupied-voxel count of a synchronous table export
   uint32_t* touch;            // distinct-voxel bitmaps, allocated on first use
   int4* items;                // ray segments of the current insert
   int64_t item_cap;

@@ -66,7 +66,7 @@ class map_stats_t(ctypes.Structure):
 
 EXPORTED = [
     "map_params_validate", "map_create", "map_destroy", "map_reset", "map_insert_scan",
-    "map_export_2d", "map_export_voxels", "map_import_voxels", "map_get_stats",
+    "map_export_2d", "map_export_voxels", "map_export_voxels_async", "map_import_voxels", "map_get_stats",
     "map_get_origin", "map_sync", "map_status_str", "map_profile_enable", "map_profile_read",
     "map_set_tuning", "map_get_tuning",
     "map_batch_create", "map_batch_destroy", "map_batch_step", "map_batch_latency",
@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
         L.map_insert_scan.argtypes = [P, P, I64, P, ctypes.c_uint32]
         L.map_export_2d.argtypes = [P, ctypes.POINTER(map_2d_t)]
         L.map_export_voxels.argtypes = [P, P, P, I64, P, P]
+        L.map_export_voxels_async.argtypes = [P, P, P, I64, P, P]
         L.map_import_voxels.argtypes = [P, P, P, I64, P]
         L.map_get_stats.argtypes = [P, ctypes.POINTER(map_stats_t)]
         L.map_get_origin.argtypes = [P, P]
@@ -211,15 +212,29 @@ def map_export_2d(h, out: dict) -> int:
     return lib().map_export_2d(h, ctypes.byref(o))
 
 
-def map_export_voxels(h, lut, data, n_occupied):
-    """lut int32[V], data int32[cap, 3] (or None), n_occupied int64[1]; -> (status, origin)."""
+def map_export_voxels(h, lut, data):
+    """lut int32[V], data int32[cap, 3] (or None); -> (status, n_occupied, origin).
+    Synchronises; status MAP_E_CAPACITY when cap < n_occupied."""
     import torch
     cap = 0 if data is None else data.shape[0]
     dptr = ctypes.c_void_p(0) if data is None else _dev(data, torch.int32, "data")
     origin = np.zeros(3, np.int32)
+    n_occ = ctypes.c_int64(-1)
     s = lib().map_export_voxels(h, _dev(lut, torch.int32, "lut"), dptr, cap,
-                                _dev(n_occupied, torch.int64, "n_occupied"),
-                                origin.ctypes.data_as(ctypes.c_void_p))
+                                ctypes.byref(n_occ), origin.ctypes.data_as(ctypes.c_void_p))
+    return s, int(n_occ.value), origin
+
+
+def map_export_voxels_async(h, lut, data, n_occupied):
+    """As map_export_voxels without waiting: n_occupied is a device int64[1]
+    tensor written on the stream; -> (status, origin)."""
+    import torch
+    cap = 0 if data is None else data.shape[0]
+    dptr = ctypes.c_void_p(0) if data is None else _dev(data, torch.int32, "data")
+    origin = np.zeros(3, np.int32)
+    s = lib().map_export_voxels_async(h, _dev(lut, torch.int32, "lut"), dptr, cap,
+                                      _dev(n_occupied, torch.int64, "n_occupied"),
+                                      origin.ctypes.data_as(ctypes.c_void_p))
     return s, origin
 
 
@@ -440,15 +455,28 @@ class VoxelMap:
         self._check(map_export_2d(self.h, self.out2d), "map_export_2d")
         return self.out2d
 
-    def export_voxels(self, cap: int | None = None):
+    def _data_for(self, cap):
         import torch
-        V = self.lut.numel()
-        cap = V if cap is None else cap
-        if self.data is None or self.data.shape[0] != cap:
+        if self.data is None or self.data.shape[0] != max(cap, 1):
             self.data = torch.empty((max(cap, 1), 3), dtype=torch.int32, device=self.lut.device)
-        s, origin = map_export_voxels(self.h, self.lut, self.data[:cap] if cap else None,
-                                      self.n_occ)
-        self._check(s, "map_export_voxels")
+        return self.data[:cap] if cap else None
+
+    def export_voxels(self, cap: int | None = None):
+        """-> (lut, data, n_occupied: int, origin); synchronises.  With a cap
+        below the occupied count the status MAP_E_CAPACITY is kept in
+        self.last_export_status instead of raising."""
+        cap = self.lut.numel() if cap is None else cap
+        s, n, origin = map_export_voxels(self.h, self.lut, self._data_for(cap))
+        self.last_export_status = s
+        if s != MAP_E_CAPACITY:
+            self._check(s, "map_export_voxels")
+        return self.lut, self.data, n, origin
+
+    def export_voxels_async(self, cap: int | None = None):
+        """-> (lut, data, n_occupied device int64[1], origin); no wait."""
+        cap = self.lut.numel() if cap is None else cap
+        s, origin = map_export_voxels_async(self.h, self.lut, self._data_for(cap), self.n_occ)
+        self._check(s, "map_export_voxels_async")
         return self.lut, self.data, self.n_occ, origin
 
     def export_density(self):

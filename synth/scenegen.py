@@ -14,7 +14,9 @@ Scene recipe (all sizes in metres):
   vegetation clusters of points uniform in a sphere of radius 1.5 centred
              1.5 above the terrain, each point a small sphere (soft obstacles);
   pits       2 x 2 footprint, flat floor 1 below the terrain at the centre,
-             vertical walls (negative obstacles).
+             vertical walls (negative obstacles);
+  ramps      optional linear rises along x (steps and cliffs of the small
+             semantic scenes).
 Lidar: beams at fixed elevations, azimuth-major point order (one firing of
 all beams per azimuth step), range noise N(0, sigma) along the ray, NaN for
 beams with no return within the maximum range.  Points are returned in the
@@ -43,6 +45,7 @@ class Scene:
     spheres: np.ndarray = field(default_factory=lambda: np.zeros((0, 4)))  # cx,cy,cz,r
     clusters: np.ndarray = field(default_factory=lambda: np.zeros((0, 5)))  # cx,cy,cz,R,first idx
     cluster_end: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
+    ramps: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))   # x0, x1, dz
 
     # -------------------------------------------------------------- terrain
     def terrain_np(self, x, y):
@@ -54,6 +57,8 @@ class Scene:
         A, L = self.relief
         if A:
             h = h + A * np.sin(2 * np.pi * x / L) * np.cos(2 * np.pi * y / L)
+        for x0, x1, dz in self.ramps:
+            h = h + dz * np.clip((x - x0) / (x1 - x0), 0.0, 1.0)
         return h
 
     def ground_np(self, x, y):
@@ -72,6 +77,8 @@ def _torch_ground(scene: Scene, x, y, consts):
     A, L = scene.relief
     if A:
         h = h + A * torch.sin(2 * math.pi * x / L) * torch.cos(2 * math.pi * y / L)
+    for x0, x1, dz in scene.ramps:
+        h = h + dz * torch.clamp((x - x0) / (x1 - x0), 0.0, 1.0)
     for p in consts["pits"]:
         inside = (x >= p[0]) & (x < p[1]) & (y >= p[2]) & (y < p[3])
         h = torch.where(inside, p[4], h)
@@ -358,10 +365,13 @@ def _rebase(sc: Scene, dz: float) -> Scene:
     return sc
 
 
-def sequence_64beam(seed=2, n_scans=100, device="cpu", n_az=2048, n_beams=64):
+def sequence_64beam(seed=2, n_scans=100, device="cpu", n_az=2048, n_beams=64, n_sim=None):
     """64-beam x 2048 scans (131,072 points, 100 m, sigma 0.02 m) along a spline at
     4.5 m/s, one scan per 0.1 s, yaw noise 0.1 deg; 300 x 300 m scene with 40 boxes,
-    60 vegetation clusters and 10 pits; 512 x 512 x 64 map at 0.2 m, recentred."""
+    60 vegetation clusters and 10 pits; 512 x 512 x 64 map at 0.2 m, recentred.
+    The scene and trajectory are those of the n_scans-scan sequence; only the first
+    n_sim scans (default all) are simulated, so a shorter run sees exactly the
+    first scans of the full one."""
     s_traj, s_noise = np.random.SeedSequence(seed).spawn(2)
     r_noise = np.random.default_rng(s_noise)
     base = make_scene(seed + 1000, 300.0, 0, 0, 0)
@@ -369,17 +379,20 @@ def sequence_64beam(seed=2, n_scans=100, device="cpu", n_az=2048, n_beams=64):
     sc = make_scene(seed + 1000, 300.0, 40, 60, 10, keep_clear=(path, 3.0))
     true, mapper, _ = trajectory(sc, np.random.default_rng(s_traj), n_scans, 0.45, 1.5, 0.1,
                                  300.0)
+    n_sim = n_scans if n_sim is None else min(n_sim, n_scans)
     dirs = lidar_dirs(n_beams, -16.6, 16.6, n_az, device)
-    scans = [simulate_scan(sc, R, t, dirs, 100.0, 0.02, r_noise) for R, t in true]
-    return dict(params=params_for(512, 512, 64, 0.2, 32), scans=scans, poses=mapper,
-                flags=[1] * n_scans, firing=n_beams, scene=sc)
+    scans = [simulate_scan(sc, R, t, dirs, 100.0, 0.02, r_noise) for R, t in true[:n_sim]]
+    return dict(params=params_for(512, 512, 64, 0.2, 32), scans=scans, poses=mapper[:n_sim],
+                flags=[1] * n_sim, firing=n_beams, scene=sc)
 
 
-def multi_lidar_frames(seed=3, n_frames=50, device="cpu"):
+def multi_lidar_frames(seed=3, n_frames=50, device="cpu", n_sim=None):
     """One 128-beam x 2048 lidar at (0, 0, 1.8) plus two 32-beam x 1024 lidars at
     (+-0.7, 0.9, 1.2) pitched 10 deg down; 12 m/s; dense vegetation (100..2000
     points per cubic metre, element radius 0.02 m); relief keeps slopes below 35 deg;
-    1024 x 1024 x 96 map at 0.1 m.  Each frame = three inserts (primary recentres)."""
+    1024 x 1024 x 96 map at 0.1 m.  Each frame = three inserts (primary recentres).
+    Scene and trajectory are those of n_frames frames; the first n_sim frames
+    (default all) are simulated."""
     s_traj, s_noise, s_dens = np.random.SeedSequence(seed).spawn(3)
     r_noise, r_dens = np.random.default_rng(s_noise), np.random.default_rng(s_dens)
 
@@ -397,7 +410,8 @@ def multi_lidar_frames(seed=3, n_frames=50, device="cpu"):
               (rot_zyx(0.0, math.radians(10), 0.0), np.array([0.7, 0.9, 1.2]), 32, -16, 16, 1024),
               (rot_zyx(0.0, math.radians(10), 0.0), np.array([-0.7, 0.9, 1.2]), 32, -16, 16, 1024)]
     scans, poses, flags, firing = [], [], [], []
-    for (Rv, tv), pm in zip(true, mapper):
+    n_sim = n_frames if n_sim is None else min(n_sim, n_frames)
+    for (Rv, tv), pm in zip(true[:n_sim], mapper[:n_sim]):
         Rm = pm.reshape(3, 4)[:, :3].astype(np.float64)
         tm = pm.reshape(3, 4)[:, 3].astype(np.float64)
         for k, (Rs, ts, nb, lo, hi, naz) in enumerate(mounts):
@@ -418,13 +432,15 @@ def small_random_cloud(seed: int, n: int, extent: float, device="cpu"):
     return torch.as_tensor(p, device=device)
 
 
-def batch_of_vehicles(n_maps=32, n_steps=10, seed0=400, device="cpu", n_beams=64):
+def batch_of_vehicles(n_maps=32, n_steps=100, seed0=400, device="cpu", n_beams=64, n_sim=None):
     """Independent vehicles for batched serving: map i uses scene seed seed0 + i,
     its scan size N_i is drawn log-uniformly in [20k, 330k] points per step
     (n_beams x round(N_i / n_beams) azimuths), its grid uniformly from
     {256 x 256 x 48 at 0.4 m, 512 x 512 x 64 at 0.2 m}; 4.5 m/s, one scan per
-    0.1 s, 100 m range, sigma 0.02 m."""
+    0.1 s, 100 m range, sigma 0.02 m.  Scenes and trajectories are those of
+    n_steps steps; the first n_sim steps (default all) are simulated."""
     out = []
+    n_sim = n_steps if n_sim is None else min(n_sim, n_steps)
     for i in range(n_maps):
         s_traj, s_noise, s_pick = np.random.SeedSequence(seed0 + i).spawn(3)
         rp = np.random.default_rng(s_pick)
@@ -437,12 +453,13 @@ def batch_of_vehicles(n_maps=32, n_steps=10, seed0=400, device="cpu", n_beams=64
                                      300.0)
         r_noise = np.random.default_rng(s_noise)
         scans = []
-        for (R, t) in true:
+        for (R, t) in true[:n_sim]:
             n_pts = float(np.exp(rp.uniform(np.log(20000), np.log(330000))))
             n_az = max(1, int(round(n_pts / n_beams)))
             dirs = lidar_dirs(n_beams, -16.6, 16.6, n_az, device)
             scans.append(simulate_scan(sc, R, t, dirs, 100.0, 0.02, r_noise))
-        out.append(dict(params=params_for(*grid), scans=scans, poses=mapper, firing=n_beams))
+        out.append(dict(params=params_for(*grid), scans=scans, poses=mapper[:n_sim],
+                        firing=n_beams))
     return out
 
 
@@ -463,3 +480,76 @@ def surrogate_sequence(seed: int, n_scans: int = 20, device="cpu", n_beams=32, n
     scans = [simulate_scan(sc, R, t, dirs, 50.0, 0.02, r_noise) for R, t in true]
     return dict(params=params_for(128, 128, 32, 0.4, 16), scans=scans, poses=mapper,
                 firing=n_beams)
+
+
+# ---------------------------------------------------------------- small semantic scenes
+
+
+def _window_params(nx, nz, res):
+    return params_for(nx, nx, nz, res, nz // 2)
+
+
+def column_centre_plane(nx=32, nz=16, res=0.5, z0=-1.75, slope_x=0.0):
+    """One point at the centre of every column of the initial window (world =
+    sensor frame, identity pose) on the plane z = z0 + slope_x * x.  With a
+    power-of-two voxel edge and these values every coordinate is exact in
+    binary32 and in the Q16 grid."""
+    p = _window_params(nx, nz, res)
+    i = np.arange(nx)
+    c = (i - nx // 2 + 0.5) * res
+    X, Y = np.meshgrid(c, c, indexing="ij")
+    Z = z0 + slope_x * X
+    pts = np.stack([X, Y, Z], -1).reshape(-1, 3).astype(np.float32)
+    return dict(params=p, scans=[torch.as_tensor(pts)], poses=[pose12(np.eye(3), np.zeros(3))],
+                flags=[0], firing=1)
+
+
+def semantic_scene(kind: str, device="cpu"):
+    """Small ray-cast scenes with one feature each on flat ground 1.5 m below
+    the sensor (32-beam lidar, -25..+10 deg, 1800 azimuths, 30 m, sigma 5 mm,
+    map 256 x 256 x 32 at 0.2 m in the initial window, no recentring):
+      box      a 1 x 1 x 2 m box, front face at x = 7.1, y in [-0.5, 0.5];
+      cluster  500 elements (radius 5 cm) uniform in a 1.5 m sphere centred
+               at (8, 3) 1.5 m above the ground;
+      pit      a 2 x 2 x 1 m pit, x in [4.1, 6.1], y in [-0.9, 1.1];
+      downhill the ground drops 1.5 m at x = 8 (cliff); a second scan from
+               (20, 0) on the lower ground sees the area the first one could
+               not;
+      uphill   a ramp rising 1.5 m from x = 6 to x = 7.5 (slope 1).
+    Returns the workload dict plus `feature`, the feature's geometry."""
+    sc = Scene(waves=np.zeros((0, 4)), z0=-1.5)
+    feat = {}
+    poses = [pose12(np.eye(3), np.zeros(3))]
+    if kind == "box":
+        sc.boxes = np.array([[7.1, 8.1, -0.5, 0.5, -1.6, 0.4]])
+        feat = dict(x=(7.1, 8.1), y=(-0.5, 0.5))
+    elif kind == "cluster":
+        rng = np.random.default_rng(11)
+        u = rng.normal(size=(500, 3))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        rad = 1.5 * rng.uniform(size=500) ** (1 / 3)
+        c = np.array([8.0, 3.0, 0.0])
+        sc.spheres = np.concatenate([c + u * rad[:, None], np.full((500, 1), 0.05)], 1)
+        sc.clusters = np.array([[8.0, 3.0, 0.0, 1.5, 0]])
+        sc.cluster_end = np.array([500], np.int64)
+        feat = dict(centre=(8.0, 3.0), radius=1.5)
+    elif kind == "pit":
+        sc.pits = np.array([[4.1, 6.1, -0.9, 1.1, -2.5]])
+        feat = dict(x=(4.1, 6.1), y=(-0.9, 1.1))
+    elif kind == "downhill":
+        sc.ramps = np.array([[8.0, 8.02, -1.5]])
+        poses.append(pose12(rot_zyx(math.pi, 0.0, 0.0), np.array([20.0, 0.0, -1.5])))
+        feat = dict(edge=8.0, drop=1.5)
+    elif kind == "uphill":
+        sc.ramps = np.array([[6.0, 7.5, 1.5]])
+        feat = dict(x=(6.0, 7.5), slope=1.0)
+    else:
+        raise ValueError(kind)
+    rng = np.random.default_rng(7)
+    dirs = lidar_dirs(32, -25.0, 10.0, 1800, device)
+    scans = []
+    for p in poses:
+        P = p.reshape(3, 4).astype(np.float64)
+        scans.append(simulate_scan(sc, P[:, :3], P[:, 3], dirs, 30.0, 0.005, rng))
+    return dict(params=_window_params(256, 32, 0.2), scans=scans, poses=poses,
+                flags=[0] * len(poses), firing=32, scene=sc, feature=feat)

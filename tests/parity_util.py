@@ -54,7 +54,7 @@ def compare_voxels(pair):
     torch.cuda.synchronize()
     s, lut_o, data_o, n_o, origin_o = pair.o.export_voxels()
     assert s == 0
-    n_g = int(n_occ.item())
+    n_g = n_occ
     assert n_g == n_o, (n_g, n_o)
     assert (origin == origin_o).all(), (origin, origin_o)
     lut_g = lut.cpu().numpy()
@@ -64,12 +64,9 @@ def compare_voxels(pair):
     return n_g
 
 
-def compare_2d(pair):
-    out = pair.g.export_2d()
-    torch.cuda.synchronize()
-    g = {k: v.cpu().numpy() for k, v in out.items()}
-    o = pair.o.export_2d()
-    r2 = float(np.float32(pair.params["res_m"])) ** 2
+def compare_2d_arrays(g, o, res_m):
+    """g, o: dicts of host arrays (height, slope, rough, density, flags)."""
+    r2 = float(np.float32(res_m)) ** 2
     fb = np.nonzero(g["flags"] != o["flags"])
     assert fb[0].size == 0, f"{fb[0].size} flag mismatches at {list(zip(*fb))[:5]}: " \
         f"{g['flags'][fb][:5]} vs {o['flags'][fb][:5]}"
@@ -83,7 +80,70 @@ def compare_2d(pair):
         d = np.abs(g[k][~on].astype(np.float64) - o[k][~on])
         lim = tol * np.maximum(np.abs(o[k][~on]).astype(np.float64), floor)
         assert (d <= lim).all(), f"{k}: max excess {np.max(d - lim)}"
+
+
+def host_2d(out):
+    return {k: v.cpu().numpy().copy() for k, v in out.items()}
+
+
+def compare_2d(pair):
+    out = pair.g.export_2d()
+    torch.cuda.synchronize()
+    g = host_2d(out)
+    o = pair.o.export_2d()
+    compare_2d_arrays(g, o, pair.params["res_m"])
     return g, o
+
+
+class OracleTrack:
+    """The oracle side of a long full-size parity run.
+
+    Inserts run in order on one oracle map.  A 2D export of the oracle map at
+    the largest windows takes seconds, so it runs on a worker thread, on a
+    fresh oracle map that imports the oracle's own exported state (lookup
+    table, data array, origin): the 2D maps are a function of that state.
+    Nothing here takes a value from the HIP path.
+    """
+
+    def __init__(self, params, workers=8):
+        from concurrent.futures import ThreadPoolExecutor
+        self.params = dict(params)
+        self.o = oracle.OracleMap(params)
+        self.pool = ThreadPoolExecutor(max_workers=workers)
+
+    def insert(self, xyz_np, pose, flags):
+        return self.o.insert_scan(xyz_np, pose, flags & oracle.RECENTER)
+
+    def voxels(self):
+        s, lut, data, n, origin = self.o.export_voxels()
+        assert s == oracle.OK
+        return lut, np.ascontiguousarray(data), n, origin
+
+    def submit_2d(self, lut, data, origin):
+        params = self.params
+
+        def job():
+            m = oracle.OracleMap(params)
+            try:
+                assert m.import_voxels(lut, data, origin) == oracle.OK
+                return m.export_2d()
+            finally:
+                m.close()
+        return self.pool.submit(job)
+
+    def close(self):
+        self.pool.shutdown(wait=True)
+        self.o.close()
+
+
+def compare_voxel_arrays(gpu_export, lut_o, data_o, n_o, origin_o):
+    lut, data, n_g, origin = gpu_export
+    assert n_g == n_o, (n_g, n_o)
+    assert (origin == origin_o).all(), (origin, origin_o)
+    lut_g = lut.cpu().numpy()
+    bad = np.nonzero(lut_g != lut_o)[0]
+    assert bad.size == 0, f"{bad.size} LUT mismatches, first at {bad[:5]}: {lut_g[bad[:5]]} vs {lut_o[bad[:5]]}"
+    assert (data[:n_g].cpu().numpy() == data_o).all()
 
 
 def compare_all(pair, distinct=False):

@@ -30,7 +30,7 @@ def _snapshot(m):
     lut, data, n, origin = m.export_voxels()
     out = m.export_2d()
     torch.cuda.synchronize()
-    k = int(n.item())
+    k = n
     return (lut.cpu().numpy().copy(), data[:k].cpu().numpy().copy(), origin.copy(),
             {key: v.cpu().numpy().copy() for key, v in out.items()})
 

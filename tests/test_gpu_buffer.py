@@ -154,7 +154,7 @@ def test_64beam_sequence_full_size():
     through a buffer of depth 4 (the first scan evicted), in the launch
     configuration of the benchmark (firing width 64)."""
     from paper_2109_13176_amd import gvom
-    seq = scenegen.sequence_64beam(seed=2, n_scans=5, device="cuda")
+    seq = scenegen.sequence_64beam(seed=2, n_sim=5, device="cuda")
     bp = BufPair(seq["params"], depth=4)
     try:
         for k in range(5):
@@ -239,7 +239,7 @@ def test_incremental_equals_full_combine_full_size():
     outputs are bit-identical after every step (three evictions), and equal
     the oracle's at the end."""
     from paper_2109_13176_amd import gvom
-    seq = scenegen.sequence_64beam(seed=2, n_scans=13, device="cuda")
+    seq = scenegen.sequence_64beam(seed=2, n_sim=13, device="cuda")
     prm = seq["params"]
     inc = BufPair(prm, depth=10)
     full = gvom.ScanBuffer(prm, 10)
@@ -255,9 +255,9 @@ def test_incremental_equals_full_combine_full_size():
             assert gvom.map_buffer_combine(inc.g.h, inc.gm.h) == 0
             full.combine(fm)
             a = inc.gm.export_voxels()
-            lut_a, data_a, n_a = a[0].clone(), a[1].clone(), int(a[2].item())
+            lut_a, data_a, n_a = a[0].clone(), a[1].clone(), a[2]
             b = fm.export_voxels()
-            assert n_a == int(b[2].item()) and np.array_equal(a[3], b[3])
+            assert n_a == b[2] and np.array_equal(a[3], b[3])
             assert torch.equal(lut_a, b[0]) and torch.equal(data_a[:n_a], b[1][:n_a])
             oa, ob = inc.gm.export_2d(), fm.export_2d()
             for key in oa:
@@ -277,7 +277,7 @@ def test_three_lidar_frame_full_size():
     buffer: the 128-beam scan recentres, the two 32-beam scans take its
     window (three maps of one frame, combined)."""
     from paper_2109_13176_amd import gvom
-    fr = scenegen.multi_lidar_frames(seed=3, n_frames=1, device="cuda")
+    fr = scenegen.multi_lidar_frames(seed=3, n_sim=1, device="cuda")
     bp = BufPair(fr["params"], depth=3)
     try:
         for xyz, pose, fl, fw in zip(fr["scans"], fr["poses"], fr["flags"], fr["firing"]):

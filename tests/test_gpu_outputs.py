@@ -93,7 +93,7 @@ def test_64beam_full_size():
     """Density and costmap of the 512 x 512 x 64 window after three scans of
     the 64-beam sequence (firing width 64, as the benchmark runs it)."""
     from paper_2109_13176_amd import gvom
-    seq = scenegen.sequence_64beam(seed=2, n_scans=3, device="cuda")
+    seq = scenegen.sequence_64beam(seed=2, n_sim=3, device="cuda")
     pair = Pair(seq["params"])
     try:
         for k in range(3):
