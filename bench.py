@@ -161,25 +161,130 @@ def calibrate():
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(seq, n_scans):
+def oracle_worker(first, warm, timed):
+    """Child process of the CPU baseline: waits for the path prefix of the
+    saved sequence on stdin, then times the single-threaded C oracle on scans
+    first+warm .. first+warm+timed-1 (each insert + 2D export + table export)
+    after `warm` untimed scans before them, and prints one JSON line."""
     import numpy as np
     import oracle
-    params = seq["params"]
+    prefix = sys.stdin.readline().strip()
+    if not prefix:
+        return
+    scans = np.load(prefix + "_scans.npy", mmap_mode="r")
+    poses = np.load(prefix + "_poses.npy")
+    params = json.loads(open(prefix + "_params.json").read())
     m = oracle.OracleMap(params)
-    scans = [s.cpu().numpy() for s in seq["scans"][:n_scans]]
-    t0 = time.perf_counter()
+    for k in range(first, first + warm):
+        m.insert_scan(np.ascontiguousarray(scans[k]), poses[k], oracle.RECENTER)
     pts = 0
-    for k in range(n_scans):
-        m.insert_scan(scans[k], seq["poses"][k], oracle.RECENTER)
+    t0 = time.perf_counter()
+    for k in range(first + warm, first + warm + timed):
+        m.insert_scan(np.ascontiguousarray(scans[k]), poses[k], oracle.RECENTER)
         m.export_2d()
         m.export_voxels()
-        pts += scans[k].shape[0]
-    dt = time.perf_counter() - t0
+        pts += scans.shape[1]
+    t1 = time.perf_counter()
     m.close()
-    return {"value": pts / dt, "unit": "points/s", "updates_per_s": n_scans / dt,
-            "cores": 1, "kind": "oracle",
-            "sample": f"first {n_scans} scans of the same sequence, each insert + export_2d + "
-                      f"export_voxels, single-threaded C oracle ({dt:.1f} s)"}
+    print(json.dumps({"points": pts, "updates": timed, "t0": t0, "t1": t1}), flush=True)
+
+
+class OracleBaseline:
+    """The CPU oracle timed on the GPU host, in processes started before this
+    process touches the GPU (a process that has initialised the GPU must not
+    fork).  One process alone gives the single-core rate on exactly the
+    scans the GPU times; then `procs` processes at once, each on its own
+    stretch of the sequence, give the all-core rate (sum of their rates)."""
+
+    def __init__(self, warm, timed, procs, n_scans):
+        import subprocess
+        self.warm, self.timed, self.n_scans = warm, timed, n_scans
+        me = os.path.abspath(__file__)
+
+        def spawn(first):
+            return subprocess.Popen([sys.executable, me, "--oracle-worker", str(first), str(warm),
+                                     str(timed)], stdin=subprocess.PIPE, stdout=subprocess.PIPE,
+                                    text=True)
+        self.solo = spawn(0)
+        span = warm + timed
+        self.firsts = [(j * 5) % max(1, n_scans - span + 1) for j in range(procs)]
+        self.group = [spawn(f) for f in self.firsts]
+
+    @staticmethod
+    def _collect(procs):
+        out = []
+        for p in procs:
+            line = p.stdout.readline()
+            p.wait()
+            if not line:
+                raise RuntimeError("oracle worker failed")
+            out.append(json.loads(line))
+        return out
+
+    def run(self, seq):
+        import numpy as np
+        import tempfile
+        shm = "/dev/shm" if os.path.isdir("/dev/shm") else tempfile.gettempdir()
+        prefix = os.path.join(shm, f"gvom_bench_{os.getpid()}")
+        files = [prefix + s for s in ("_scans.npy", "_poses.npy", "_params.json")]
+        try:
+            np.save(files[0], np.stack([s.cpu().numpy() for s in seq["scans"][:self.n_scans]]))
+            np.save(files[1], np.stack([np.asarray(p, np.float32) for p in seq["poses"][:self.n_scans]]))
+            open(files[2], "w").write(json.dumps(seq["params"]))
+            self.solo.stdin.write(prefix + "\n")
+            self.solo.stdin.flush()
+            solo = self._collect([self.solo])[0]
+            log(f"oracle, one process: {solo['updates'] / (solo['t1'] - solo['t0']):.2f} updates/s")
+            for p in self.group:
+                p.stdin.write(prefix + "\n")
+                p.stdin.flush()
+            grp = self._collect(self.group)
+        finally:
+            for f in files:
+                if os.path.exists(f):
+                    os.remove(f)
+        one = solo["points"] / (solo["t1"] - solo["t0"])
+        rates = [g["points"] / (g["t1"] - g["t0"]) for g in grp]
+        upd = [g["updates"] / (g["t1"] - g["t0"]) for g in grp]
+        wall = max(g["t1"] for g in grp) - min(g["t0"] for g in grp)
+        n = len(grp)
+        return {"value": float(sum(rates)), "unit": "points/s", "cores": n, "kind": "oracle",
+                "updates_per_s": float(sum(upd)),
+                "sample": f"{n} single-threaded oracle processes at once, each timing "
+                          f"{self.timed} scans (after {self.warm} untimed) of its own stretch "
+                          f"of the 100-scan sequence (first scans {self.firsts}), each scan "
+                          f"insert + export_2d + export_voxels; value = sum of their rates "
+                          f"(all points over the {wall:.1f} s wall span: "
+                          f"{sum(g['points'] for g in grp) / wall:.4g} points/s)",
+                "single_core": {"value": one, "unit": "points/s", "cores": 1,
+                                "updates_per_s": solo["updates"] / (solo["t1"] - solo["t0"]),
+                                "sample": f"scans {self.warm}..{self.warm + self.timed - 1} "
+                                          f"after scans 0..{self.warm - 1} untimed: the scans "
+                                          f"the GPU's first {self.timed} timed steps process",
+                                "seconds": solo["t1"] - solo["t0"]},
+                "host": host_info()}
+
+    def close(self):
+        for p in [self.solo] + self.group:
+            if p.poll() is None:
+                try:
+                    p.stdin.close()
+                except OSError:
+                    pass
+                p.wait()
+
+
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": aff}
 
 
 def voxel_outputs(args, params, scans, poses, flags):
@@ -263,7 +368,7 @@ def paper_dataflow(args, params, scans, poses, flags, depth=10):
                 c1.record()
                 ev.append((p0, p1, c0, c1))
             cm.export_2d()
-            cm.export_voxels()
+            cm.export_voxels_async()
             origins.append(cm.origin().copy())
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -313,7 +418,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=95)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-scans", type=int, default=12)
+    ap.add_argument("--cpu-scans", type=int, default=20,
+                    help="scans each oracle process times (after --warmup untimed ones)")
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="oracle processes of the all-core figure (0: the usable CPUs, at most 16)")
+    ap.add_argument("--oracle-worker", type=int, nargs=3, metavar=("FIRST", "WARM", "TIMED"),
+                    help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traversal", type=int, default=0, choices=[0, 1, 2],
                     help="ray traversal: 1 binned (LDS tiles), 2 segmented, 0 library default")
@@ -326,6 +436,8 @@ def main():
                          "independent maps stepped as one batch; surrogate: the gap-fill "
                          "network on the 512x512 grid (inference and training step)")
     args = ap.parse_args()
+    if args.oracle_worker:
+        return oracle_worker(*args.oracle_worker)
     if args.print_sha:
         print(source_sha(TRACE_SRCS))
         return
@@ -334,6 +446,19 @@ def main():
               "(independent maps would shard one per GPU with no exchange).", file=sys.stderr)
         sys.exit(2)
 
+    # the CPU oracle's processes start before anything touches the GPU
+    baseline = None
+    if args.workload == "seq64" and not args.calibrate and not args.no_cpu_baseline:
+        procs = args.cpu_procs or min(16, len(os.sched_getaffinity(0)))
+        baseline = OracleBaseline(args.warmup, min(args.cpu_scans, args.steps), procs, 100)
+    try:
+        return bench_main(args, baseline)
+    finally:
+        if baseline:
+            baseline.close()
+
+
+def bench_main(args, baseline):
     import numpy as np
     import torch
     from paper_2109_13176_amd import gvom
@@ -348,7 +473,10 @@ def main():
         return bench_surrogate(args)
     W, K = args.warmup, args.steps
     t0 = time.time()
-    seq = scenegen.sequence_64beam(seed=2, n_scans=W + K, device="cuda")
+    # the 100-scan sequence; all of it is simulated when the oracle processes
+    # need their own stretches of it
+    n_sim = max(W + K, 100) if baseline else W + K
+    seq = scenegen.sequence_64beam(seed=2, n_scans=max(100, W + K), n_sim=n_sim, device="cuda")
     params = seq["params"]
     scans = [s.contiguous() for s in seq["scans"]]
     poses = seq["poses"]
@@ -375,7 +503,7 @@ def main():
     def step(k):
         m.insert(scans[k], poses[k], flags)
         m.export_2d()
-        m.export_voxels()
+        m.export_voxels_async()
 
     for k in range(W):
         step(k)
@@ -427,7 +555,7 @@ def main():
         dev.copy_(host[i], non_blocking=True)
         m.insert(dev, poses[k], flags)
         m.export_2d()
-        m.export_voxels()
+        m.export_voxels_async()
     torch.cuda.synchronize()
     pcie_elapsed = time.perf_counter() - t0
     m.close()
@@ -526,8 +654,8 @@ def main():
     dataflow["full_combine"]["hbm"] = df_hbm
     out["paper_dataflow"] = dataflow
     out["voxel_outputs"] = outputs
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(seq, args.cpu_scans)
+    if baseline:
+        out["cpu_baseline"] = baseline.run(seq)
     print(json.dumps(out), flush=True)
 
 
@@ -541,7 +669,7 @@ def bench_batch(args):
 
     W, K = min(args.warmup, 3), min(args.steps, 20)
     t0 = time.time()
-    veh = scenegen.batch_of_vehicles(32, W + K, device="cuda")
+    veh = scenegen.batch_of_vehicles(32, n_steps=max(100, W + K), n_sim=W + K, device="cuda")
     log(f"generated {32 * (W + K)} scans in {time.time() - t0:.1f} s")
     maps = [gvom.VoxelMap(v["params"]) for v in veh]
     batch = gvom.MapBatch(maps)
@@ -590,7 +718,7 @@ def bench_surrogate(args):
     from synth import scenegen
 
     W, K = max(args.warmup, 3), max(args.steps, 20)
-    seq = scenegen.sequence_64beam(seed=2, n_scans=1, device="cuda")
+    seq = scenegen.sequence_64beam(seed=2, n_sim=1, device="cuda")
     p = seq["params"]
     H, Wd = p["nx"], p["ny"]
     m = gvom.VoxelMap(p)

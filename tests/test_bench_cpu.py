@@ -39,3 +39,19 @@ def test_multi_gpu_request_exits_with_message():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "single GPU" in (r.stdout + r.stderr)
+
+
+def test_oracle_baseline_processes():
+    """The CPU baseline's worker processes (started before any GPU use) time
+    the oracle on their stretches of a saved sequence and report the host."""
+    from synth import scenegen
+    w = scenegen.single_scan_16beam(seed=1)
+    seq = dict(params=w["params"], scans=w["scans"] * 8, poses=w["poses"] * 8)
+    b = bench.OracleBaseline(1, 2, 2, 8)
+    try:
+        r = b.run(seq)
+    finally:
+        b.close()
+    assert r["kind"] == "oracle" and r["cores"] == 2 and r["value"] > 0
+    assert r["single_core"]["cores"] == 1 and r["single_core"]["value"] > 0
+    assert r["host"]["nproc"] >= 1
