@@ -125,6 +125,17 @@ typedef struct {
 
 typedef struct map_t map_t;  /* opaque */
 
+/* Caps the device memory this library allocates in the process (the state of
+ * every map, buffer, batch and network, and their per-scan work buffers) at
+ * `bytes`; 0 removes the cap.  An allocation that would exceed the cap fails
+ * as if the device were out of memory, so the call that needed it returns
+ * MAP_E_OOM (a map_insert_scan that cannot grow its work buffers leaves the
+ * map unchanged).  Memory already held is not affected.  MAP_E_INVALID for
+ * bytes < 0.  For processes that share the GPU with other work. */
+int32_t map_set_device_memory_limit(int64_t bytes);
+/* Device memory, in bytes, the library holds in this process. */
+int64_t map_device_memory_in_use(void);
+
 /* Checks the parameters and derives the integer constants; host only, no HIP
  * call.  Returns MAP_E_INVALID for any parameter outside the ranges above. */
 int32_t map_params_validate(const map_params_t* p, map_derived_t* out);

@@ -10,8 +10,10 @@
 #include <stdio.h>
 
 #include <atomic>
+#include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "gvom_internal.h"
@@ -42,6 +44,40 @@ void set_ring(map_t* m) {
 }  // namespace
 
 namespace gvom {
+
+namespace {
+std::mutex g_mem_mu;
+std::unordered_map<void*, size_t> g_mem_size;
+int64_t g_mem_used = 0;
+int64_t g_mem_cap = 0;  // 0: no cap
+}  // namespace
+
+hipError_t dev_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  if (g_mem_cap > 0 && g_mem_used + (int64_t)bytes > g_mem_cap) return hipErrorOutOfMemory;
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return e;
+  }
+  g_mem_size[*p] = bytes;
+  g_mem_used += (int64_t)bytes;
+  return hipSuccess;
+}
+
+hipError_t dev_free(void* p) {
+  if (!p) return hipSuccess;
+  {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    auto it = g_mem_size.find(p);
+    if (it != g_mem_size.end()) {
+      g_mem_used -= (int64_t)it->second;
+      g_mem_size.erase(it);
+    }
+  }
+  return hipFree(p);
+}
 
 void set_origin(map_t* m, const int32_t o[3]) {
   for (int i = 0; i < 3; i++) m->origin[i] = o[i];
@@ -170,12 +206,24 @@ void prof_release(map_t* m) {
 
 template <class T>
 hipError_t dmalloc(T** p, size_t bytes) {
-  return hipMalloc((void**)p, bytes < 16 ? 16 : bytes);
+  return gvom::dev_alloc((void**)p, bytes < 16 ? 16 : bytes);
 }
 
 }  // namespace
 
 extern "C" {
+
+int32_t map_set_device_memory_limit(int64_t bytes) {
+  if (bytes < 0) return MAP_E_INVALID;
+  std::lock_guard<std::mutex> lk(gvom::g_mem_mu);
+  gvom::g_mem_cap = bytes;
+  return MAP_OK;
+}
+
+int64_t map_device_memory_in_use(void) {
+  std::lock_guard<std::mutex> lk(gvom::g_mem_mu);
+  return gvom::g_mem_used;
+}
 
 int32_t map_params_validate(const map_params_t* p, map_derived_t* out) {
   if (!p) return MAP_E_INVALID;
@@ -287,25 +335,25 @@ int32_t map_destroy(map_t* m) {
   if (!m) return MAP_OK;
   (void)hipStreamSynchronize(m->stream);
   prof_release(m);
-  (void)hipFree(m->hits);
-  (void)hipFree(m->passes);
-  (void)hipFree(m->minqz);
-  (void)hipFree(m->occ);
-  (void)hipFree(m->hq);
-  (void)hipFree(m->block_base);
-  (void)hipFree(m->colpre);
-  (void)hipFree(m->stats);
-  (void)hipFree(m->err);
-  (void)hipFree(m->nocc);
-  (void)hipFree(m->touch);
-  (void)hipFree(m->items);
-  (void)hipFree(m->part_rays);
-  (void)hipFree(m->part_trace);
-  (void)hipFree(m->bin_cnt);
-  (void)hipFree(m->uctl);
-  (void)hipFree(m->bin_ent);
-  (void)hipFree(m->units);
-  (void)hipFree(m->box_rep);
+  (void)gvom::dev_free(m->hits);
+  (void)gvom::dev_free(m->passes);
+  (void)gvom::dev_free(m->minqz);
+  (void)gvom::dev_free(m->occ);
+  (void)gvom::dev_free(m->hq);
+  (void)gvom::dev_free(m->block_base);
+  (void)gvom::dev_free(m->colpre);
+  (void)gvom::dev_free(m->stats);
+  (void)gvom::dev_free(m->err);
+  (void)gvom::dev_free(m->nocc);
+  (void)gvom::dev_free(m->touch);
+  (void)gvom::dev_free(m->items);
+  (void)gvom::dev_free(m->part_rays);
+  (void)gvom::dev_free(m->part_trace);
+  (void)gvom::dev_free(m->bin_cnt);
+  (void)gvom::dev_free(m->uctl);
+  (void)gvom::dev_free(m->bin_ent);
+  (void)gvom::dev_free(m->units);
+  (void)gvom::dev_free(m->box_rep);
   delete m;
   return MAP_OK;
 }
@@ -370,7 +418,7 @@ bool grow(map_t* m, T** p, int64_t* cap, int64_t need, size_t elem) {
   if (need <= *cap) return true;
   if (hipStreamSynchronize(m->stream) != hipSuccess) return false;
   const int64_t want = *cap > 0 && need < 2 * *cap ? 2 * *cap : need;
-  (void)hipFree(*p);
+  (void)gvom::dev_free(*p);
   *p = nullptr;
   *cap = 0;
   if (dmalloc(p, (size_t)want * elem) == hipSuccess) {
@@ -763,7 +811,7 @@ int32_t map_set_tuning(map_t* m, const map_tuning_t* t) {
   if (t->seg_len > 0 && t->seg_len != m->seg_len) {
     // the segment buffer is sized for the segment length: regrow on next insert
     if (hipStreamSynchronize(m->stream) != hipSuccess) return dev_status(m, hipErrorUnknown);
-    (void)hipFree(m->items);
+    (void)gvom::dev_free(m->items);
     m->items = nullptr;
     m->item_cap = 0;
     m->seg_len = t->seg_len;
@@ -1003,9 +1051,9 @@ int32_t map_batch_create(map_t* const* maps, int32_t k, void* stream, map_batch_
   // blocks per CU (the table pass's LDS regions allow it)
   b->grid = gvom::BatchGrid{cu * 4, cu * 8, cu * 8, cu * 8, cu * 2, cu * 4, cu * 8,
                             k * gvom::box_fold_blocks(), surf, lut};
-  hipError_t e = hipMalloc((void**)&b->dtab, sizeof(gvom::BatchTables));
+  hipError_t e = gvom::dev_alloc((void**)&b->dtab, sizeof(gvom::BatchTables));
   if (e == hipSuccess) e = hipHostMalloc((void**)&b->htab, sizeof(gvom::BatchTables), 0);
-  if (e == hipSuccess) e = hipMalloc((void**)&b->dstamps, (gvom::kMaxBatch + 1) * 8);
+  if (e == hipSuccess) e = gvom::dev_alloc((void**)&b->dstamps, (gvom::kMaxBatch + 1) * 8);
   if (e == hipSuccess) e = hipHostMalloc((void**)&b->hstamps, (gvom::kMaxBatch + 1) * 8, 0);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -1024,9 +1072,9 @@ int32_t map_batch_destroy(map_batch_t* b) {
     (void)hipGraphExecDestroy(b->exec);
     (void)hipGraphDestroy(b->graph);
   }
-  (void)hipFree(b->dtab);
+  (void)gvom::dev_free(b->dtab);
   (void)hipHostFree(b->htab);
-  (void)hipFree(b->dstamps);
+  (void)gvom::dev_free(b->dstamps);
   (void)hipHostFree(b->hstamps);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;

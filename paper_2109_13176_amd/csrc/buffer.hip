@@ -692,16 +692,16 @@ int32_t map_buffer_create(const map_params_t* p, int32_t depth, void* stream,
   b->last_out = nullptr;
   b->sticky = MAP_OK;
   const int64_t nb = gvom::n_bricks(prod->d);
-  hipError_t e = hipMalloc((void**)&b->brick_cnt, (size_t)nb * 4);
-  if (e == hipSuccess) e = hipMalloc((void**)&b->group_cnt, (size_t)((nb + 15) / 16) * 4);
-  if (e == hipSuccess) e = hipMalloc((void**)&b->n_occ, (size_t)b->ring * 8);
+  hipError_t e = gvom::dev_alloc((void**)&b->brick_cnt, (size_t)nb * 4);
+  if (e == hipSuccess) e = gvom::dev_alloc((void**)&b->group_cnt, (size_t)((nb + 15) / 16) * 4);
+  if (e == hipSuccess) e = gvom::dev_alloc((void**)&b->n_occ, (size_t)b->ring * 8);
   if (e == hipSuccess)
-    e = hipMalloc((void**)&b->inc_list, (size_t)b->inc_grid * b->inc_cap * 4);
-  if (e == hipSuccess) e = hipMalloc((void**)&b->inc_cnt, (size_t)b->inc_grid * 4);
+    e = gvom::dev_alloc((void**)&b->inc_list, (size_t)b->inc_grid * b->inc_cap * 4);
+  if (e == hipSuccess) e = gvom::dev_alloc((void**)&b->inc_cnt, (size_t)b->inc_grid * 4);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->pushed, hipEventDisableTiming);
   else b->pushed = nullptr;
   for (int i = 0; i < b->ring && e == hipSuccess; i++) {
-    e = hipMalloc((void**)&b->slots[i].lut, (size_t)prod->d.vs * 4);
+    e = gvom::dev_alloc((void**)&b->slots[i].lut, (size_t)prod->d.vs * 4);
     if (e != hipSuccess) b->slots[i].lut = nullptr;
   }
   if (e != hipSuccess) {
@@ -722,14 +722,14 @@ int32_t map_buffer_destroy(map_buffer_t* b) {
   }
   for (hipEvent_t ev : b->pool) (void)hipEventDestroy(ev);
   for (auto& s : b->slots) {
-    (void)hipFree(s.lut);
-    (void)hipFree(s.data);
+    (void)gvom::dev_free(s.lut);
+    (void)gvom::dev_free(s.data);
   }
-  (void)hipFree(b->brick_cnt);
-  (void)hipFree(b->group_cnt);
-  (void)hipFree(b->n_occ);
-  (void)hipFree(b->inc_list);
-  (void)hipFree(b->inc_cnt);
+  (void)gvom::dev_free(b->brick_cnt);
+  (void)gvom::dev_free(b->group_cnt);
+  (void)gvom::dev_free(b->n_occ);
+  (void)gvom::dev_free(b->inc_list);
+  (void)gvom::dev_free(b->inc_cnt);
   if (b->pushed) (void)hipEventDestroy(b->pushed);
   map_destroy(b->prod);
   (void)hipGetLastError();
@@ -786,10 +786,10 @@ int32_t map_buffer_push(map_buffer_t* b, const float* xyz_dev, int64_t n, const 
     e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return buf_fail(b, e);
     const int64_t want = s.cap > 0 && need < 2 * s.cap ? 2 * s.cap : need;
-    (void)hipFree(s.data);
+    (void)gvom::dev_free(s.data);
     s.data = nullptr;
     s.cap = 0;
-    if (hipMalloc((void**)&s.data, (size_t)want * sizeof(map_voxel_t)) != hipSuccess) {
+    if (gvom::dev_alloc((void**)&s.data, (size_t)want * sizeof(map_voxel_t)) != hipSuccess) {
       (void)hipGetLastError();
       s.data = nullptr;
       return MAP_E_OOM;

@@ -21,6 +21,11 @@
 
 namespace gvom {
 
+// Device allocations of the library go through these two calls, which keep
+// the process-wide total that map_set_device_memory_limit caps.
+hipError_t dev_alloc(void** p, size_t bytes);
+hipError_t dev_free(void* p);
+
 struct Dims {
   int32_t nx, ny, nz, W;  // W = occupancy words per column
   int32_t ro[3];          // ring offsets

@@ -910,7 +910,7 @@ int32_t sgt_create(int32_t H, int32_t W, uint64_t seed, void* stream, sgt_net_t*
   for (int l = 0; l < kNL; l++) maxlp = layer_params(l) > maxlp ? layer_params(l) : maxlp;
   hipError_t e = hipSuccess;
   auto al = [&](void** p, size_t b) {
-    if (e == hipSuccess) e = hipMalloc(p, b < 16 ? 16 : b);
+    if (e == hipSuccess) e = gvom::dev_alloc(p, b < 16 ? 16 : b);
   };
   al((void**)&n->master, n->np * 4);
   al((void**)&n->m, n->np * 4);
@@ -969,15 +969,15 @@ int32_t sgt_destroy(sgt_net_t* n) {
   (void)hipStreamSynchronize(n->stream);
   void* ps[] = {n->master, n->m, n->v, n->grad, n->out, n->dz0, n->dz1, n->part, n->mid,
                 n->lpart, n->scal, n->mean, n->stdv};
-  for (void* p : ps) (void)hipFree(p);
+  for (void* p : ps) (void)gvom::dev_free(p);
   for (int k = 0; k < 2; k++) {
-    (void)hipFree(n->dzh[k]);
-    (void)hipFree(n->dzl[k]);
+    (void)gvom::dev_free(n->dzh[k]);
+    (void)gvom::dev_free(n->dzl[k]);
   }
   for (int l = 0; l < kNL; l++) {
-    (void)hipFree(n->wbf[l]);
-    (void)hipFree(n->bias[l]);
-    (void)hipFree(n->act[l]);
+    (void)gvom::dev_free(n->wbf[l]);
+    (void)gvom::dev_free(n->bias[l]);
+    (void)gvom::dev_free(n->act[l]);
   }
   delete n;
   return MAP_OK;
@@ -1053,7 +1053,7 @@ int32_t sgt_feature_sums(sgt_net_t* n, const float* feat_dev, double* sums_host)
   const int64_t P = (int64_t)n->H * n->W;
   const int nb = 1024;
   double* part = nullptr;
-  hipError_t e = hipMalloc((void**)&part, (size_t)nb * 2 * kFeat * 8);
+  hipError_t e = gvom::dev_alloc((void**)&part, (size_t)nb * 2 * kFeat * 8);
   if (e != hipSuccess) return MAP_E_OOM;
   hipLaunchKernelGGL(k_feat_sums, dim3(nb), dim3(256), 0, n->stream, feat_dev, P, part);
   std::vector<double> h((size_t)nb * 2 * kFeat);
@@ -1061,7 +1061,7 @@ int32_t sgt_feature_sums(sgt_net_t* n, const float* feat_dev, double* sums_host)
   if (e == hipSuccess)
     e = hipMemcpyAsync(h.data(), part, h.size() * 8, hipMemcpyDeviceToHost, n->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
-  (void)hipFree(part);
+  (void)gvom::dev_free(part);
   if (e != hipSuccess) return st_of(e);
   for (int k = 0; k < 2 * kFeat; k++) {
     double s = 0.0;

@@ -77,6 +77,7 @@ EXPORTED = [
     "sgt_num_params", "sgt_create", "sgt_destroy", "sgt_get_params", "sgt_set_params",
     "sgt_set_norm", "sgt_features", "sgt_thin", "sgt_feature_sums", "sgt_forward",
     "sgt_loss_grad", "sgt_adam", "sgt_fill",
+    "map_set_device_memory_limit", "map_device_memory_in_use",
 ]
 PROF_PHASES = ("scroll", "rays", "trace", "column", "surface", "lut")
 
@@ -91,6 +92,9 @@ def lib() -> ctypes.CDLL:
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
         L = ctypes.CDLL(LIB_PATH)
         P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.map_set_device_memory_limit.argtypes = [I64]
+        L.map_device_memory_in_use.argtypes = []
+        L.map_device_memory_in_use.restype = I64
         L.map_params_validate.argtypes = [ctypes.POINTER(map_params_t),
                                           ctypes.POINTER(map_derived_t)]
         L.map_create.argtypes = [ctypes.POINTER(map_params_t), P, ctypes.POINTER(P)]
@@ -144,6 +148,7 @@ def lib() -> ctypes.CDLL:
             if f != "map_status_str":
                 getattr(L, f).restype = I32
         L.sgt_num_params.restype = I64
+        L.map_device_memory_in_use.restype = I64
         _lib = L
     return _lib
 
