@@ -27,7 +27,7 @@ METRIC = "lidar points/sec ingested + map updates/sec (64-beam, 512x512x64) on 1
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2109_13176_amd", "csrc")
-# sources of the segmented traversal kernel (k_trace) whose counters are committed
+# sources of the traversal kernel (k_trace) whose counters are committed
 TRACE_SRCS = [os.path.join(CSRC, f) for f in ("insert.hip", "ray_common.h", "gvom_internal.h")]
 
 
@@ -97,67 +97,49 @@ def measured_traffic():
 
 
 def calibrate():
-    """Plain copy bandwidth (the scale for FETCH_SIZE / WRITE_SIZE) and the
-    rate of scattered int32 atomic adds, both with torch's own kernels."""
+    """Reference rates from the library's own calibration kernels
+    (map_calib_copy, map_calib_atomic): a plain device copy, the scale for
+    the FETCH_SIZE / WRITE_SIZE counters, and scattered int32 atomic adds at
+    1, 4, 16 and 64 lanes per 64-byte line on an L2-sized (2 MiB) and an
+    HBM-sized (256 MiB) footprint, reported per update and per line request."""
     import torch
+    from paper_2109_13176_amd import gvom
+    reps = 10
+
+    def timed(fn):
+        for _ in range(2):
+            assert fn() == 0
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
     n = 128 << 20  # int32 elements: 512 MiB per buffer
     src = torch.ones(n, dtype=torch.int32, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 10
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) / reps * 1e-3
-    copy_gbs = 2 * n * 4 / t / 1e9
-    tgt = torch.zeros(64 << 20, dtype=torch.int32, device="cuda")
-    idx = torch.randint(0, tgt.numel(), (16 << 20,), device="cuda")
-    one = torch.ones(idx.numel(), dtype=torch.int32, device="cuda")
-    for _ in range(2):
-        tgt.scatter_add_(0, idx, one)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        tgt.scatter_add_(0, idx, one)
-    e1.record()
-    torch.cuda.synchronize()
-    t2 = e0.elapsed_time(e1) / reps * 1e-3
-    # the same number of adds, but each aligned run of 16 consecutive indices
-    # covers one random 64-byte line (atomics are charged per line request)
-    lines = torch.randint(0, tgt.numel() // 16, (idx.numel() // 16, 1), device="cuda")
-    idx16 = (lines * 16 + torch.arange(16, device="cuda")).reshape(-1)
-    for _ in range(2):
-        tgt.scatter_add_(0, idx16, one)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        tgt.scatter_add_(0, idx16, one)
-    e1.record()
-    torch.cuda.synchronize()
-    t3 = e0.elapsed_time(e1) / reps * 1e-3
-    # the same random adds into a 2 MiB array (L2-resident footprint)
-    small = torch.zeros(512 << 10, dtype=torch.int32, device="cuda")
-    idx_s = torch.randint(0, small.numel(), (idx.numel(),), device="cuda")
-    for _ in range(2):
-        small.scatter_add_(0, idx_s, one)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        small.scatter_add_(0, idx_s, one)
-    e1.record()
-    torch.cuda.synchronize()
-    t4 = e0.elapsed_time(e1) / reps * 1e-3
-    out = {"copy_bytes_per_launch": 2 * n * 4, "copy_GBps": copy_gbs,
-           "scatter_l2_atomics_per_s": idx_s.numel() / t4,
-           "scatter_atomics_per_launch": idx.numel(), "scatter_atomics_per_s": idx.numel() / t2,
-           "line_scatter_lines_per_launch": idx16.numel() // 16,
-           "line_scatter_atomics_per_s": idx16.numel() / t3,
-           "line_scatter_lines_per_s": idx16.numel() / 16 / t3}
+    t = timed(lambda: gvom.map_calib_copy(dst, src))
+    assert torch.equal(dst, src)
+    out = {"kernel_copy": "k_copy_bw", "copy_bytes_per_launch": 2 * n * 4,
+           "copy_GBps": 2 * n * 4 / t / 1e9, "kernel_atomic": "k_atomic_peak", "atomics": []}
+    del src, dst
+    n_waves, per_wave = 16384, 64
+    upd = 64 * n_waves * per_wave
+    for foot_mib in (2, 256):
+        tgt = torch.zeros(foot_mib << 18, dtype=torch.int32, device="cuda")
+        for g in (1, 4, 16, 64):
+            tgt.zero_()
+            ta = timed(lambda: gvom.map_calib_atomic(tgt, n_waves, per_wave, g, seed=7))
+            total = int(tgt.sum(dtype=torch.int64))
+            assert total == upd * (reps + 2), (total, upd)
+            out["atomics"].append({"footprint_MiB": foot_mib, "lanes_per_line": g,
+                                   "updates_per_launch": upd,
+                                   "line_requests_per_launch": upd // g,
+                                   "updates_per_s": upd / ta, "line_requests_per_s": upd / g / ta})
+        del tgt
     print(json.dumps(out), flush=True)
 
 
@@ -425,8 +407,6 @@ def main():
     ap.add_argument("--oracle-worker", type=int, nargs=3, metavar=("FIRST", "WARM", "TIMED"),
                     help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traversal", type=int, default=0, choices=[0, 1, 2],
-                    help="ray traversal: 1 binned (LDS tiles), 2 segmented, 0 library default")
     ap.add_argument("--print-sha", action="store_true",
                     help="print the hash of the traversal kernel sources, then exit")
     ap.add_argument("--calibrate", action="store_true",
@@ -485,8 +465,6 @@ def bench_main(args, baseline):
 
     # untimed pre-pass on a shadow map: distinct voxels touched per scan
     shadow = gvom.VoxelMap(params)
-    if args.traversal:
-        gvom.map_set_tuning(shadow.h, traversal=args.traversal)
     dstats = []
     for k in range(W + K):
         shadow.insert(scans[k], poses[k], flags | gvom.MAP_STATS_DISTINCT)
@@ -496,8 +474,6 @@ def bench_main(args, baseline):
     del shadow
 
     m = gvom.VoxelMap(params)
-    if args.traversal:
-        gvom.map_set_tuning(m.h, traversal=args.traversal)
     trace_bit = 1 << gvom.PROF_PHASES.index("trace")
 
     def step(k):
@@ -524,8 +500,6 @@ def bench_main(args, baseline):
 
     # every phase timed in a second pass over the same scans (fresh map)
     m = gvom.VoxelMap(params)
-    if args.traversal:
-        gvom.map_set_tuning(m.h, traversal=args.traversal)
     for k in range(W):
         step(k)
     gvom.map_profile_enable(m.h, True)
@@ -541,8 +515,6 @@ def bench_main(args, baseline):
     # host memory (the copy is outside the library's boundary: reported, not
     # the value)
     m = gvom.VoxelMap(params)
-    if args.traversal:
-        gvom.map_set_tuning(m.h, traversal=args.traversal)
     for k in range(W):
         step(k)
     host = [scans[k].cpu().pin_memory() for k in range(W, W + K)]
@@ -564,8 +536,6 @@ def bench_main(args, baseline):
     # export (a map update without the voxel table), each on a fresh map
     def timed(fn):
         mm = gvom.VoxelMap(params)
-        if args.traversal:
-            gvom.map_set_tuning(mm.h, traversal=args.traversal)
         for k in range(W):
             fn(mm, k)
         torch.cuda.synchronize()
@@ -599,16 +569,15 @@ def bench_main(args, baseline):
     roof = {"kernel": dom, "bound": "hbm", "achieved": phases[dom]["gbps"],
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": phases[dom]["gbps"] / HBM_PEAK_GBS,
-            "traffic": measured_traffic() if dom == "trace" and args.traversal != 1 else None}
+            "traffic": measured_traffic() if dom == "trace" else None}
     if dom == "trace":
         # co-reported atomic roofline: device atomics are charged per line
-        # request (TCC_ATOMIC), and random int32 scatter (torch scatter_add on
-        # this GPU) issues exactly one line request per add, so its rate is the
-        # measured line-request peak
+        # request (TCC_ATOMIC); the peak is the best line-request rate of the
+        # library's k_atomic_peak (random lines, HBM-sized footprint)
         t_tr = phases["trace"]["avg_ms"] * 1e-3
         cal = read_summary("calibration_mi355x.txt")
-        peak = float(cal["scatter atomics per s"]) if cal else None
-        lr = measured_line_requests() if args.traversal != 1 else None
+        peak = float(cal["peak atomic line requests per s"]) if cal and "peak atomic line requests per s" in cal else None
+        lr = measured_line_requests()
         roof["atomics"] = {"achieved": lr / t_tr if lr else None, "peak": peak,
                            "unit": "line requests/s",
                            "frac": lr / t_tr / peak if (lr and peak) else None,

@@ -169,7 +169,7 @@ int32_t map_reset(map_t* m);
 int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float pose[12],
                         uint32_t flags);
 
-/* Writes the 2D maps of Sec. III-D into the caller's device arrays. */
+/* Writes the 2D maps of Sec. III-D into the caller's device arrays. *//* Writes the 2D maps of Sec. III-D into the caller's device arrays. */
 int32_t map_export_2d(map_t* m, const map_2d_t* out_dev);
 
 /* Writes the Sec. III-A lookup table and data array:
@@ -234,17 +234,15 @@ int32_t map_get_origin(const map_t* m, int32_t origin_vox[3]);
 int32_t map_sync(map_t* m);
 
 /* Launch tuning (performance only: results are bit-identical for every
- * setting).  traversal: 2 = segmented (rays cut every seg_len dominant-axis
- * voxels, runs of equal voxels in neighbouring lanes merged, one global
- * atomic per run; the passes of a 17 x 17 x 9 box around the sensor are
- * summed per block on chip first; default, and always used by batches), 1 = binned (rays cut at 16-voxel storage slabs, passes
- * counted per slab tile in LDS, then added to the map; single-map inserts
- * only, when the window has at most 16,384 tiles and the scan at most
- * 524,288 points, else segmented).  seg_len: dominant-axis voxels per ray
- * segment of the segmented traversal, 1..1024 (default 8);
- * trace_waves_per_cu: resident waves per compute unit requested for the
- * segmented traversal grid, 1..32 (default 32).  A field <= 0 keeps the
- * current value. */
+ * setting).  The traversal cuts every ray every seg_len dominant-axis voxels;
+ * a wave takes one segment index of 64 neighbouring rays, counts its passes
+ * in an LDS table of 64-byte map lines and adds each line to the map with one
+ * request; the passes of a 17 x 17 x 9 box around the sensor are summed per
+ * block on chip first.  seg_len: dominant-axis voxels per ray segment,
+ * 1..1024 (default 8); trace_waves_per_cu: resident waves per compute unit
+ * requested for the traversal grid, 1..32 (default 32); traversal: 2 (the
+ * traversal described; any other positive value is MAP_E_INVALID).  A field
+ * <= 0 keeps the current value. */
 typedef struct {
   int32_t seg_len;
   int32_t trace_waves_per_cu;
@@ -432,6 +430,32 @@ int32_t sgt_adam(sgt_net_t* n, float lr);
  * 11 x 11 window is <= tol_m; otherwise NaN. */
 int32_t sgt_fill(const float* pred_dev, const map_2d_t* plain_dev, int32_t H, int32_t W,
                  float tol_m, float* height_out, float* rough_out, void* stream);
+
+/* ---- roofline calibration (project measurement kernels) ------------------
+ * The two reference rates the mapping kernels are priced against, measured on
+ * the device at hand.  Both enqueue one kernel on `stream` and return without
+ * waiting; the caller times them (HIP events) and owns every buffer.  They
+ * are not part of the method. */
+
+/* Plain device copy of `bytes` (a multiple of 16; both pointers 16-byte
+ * aligned, the ranges disjoint) from src_dev to dst_dev: the practical HBM
+ * rate, and the scale for hardware traffic counters (what they read for a
+ * copy of known size).  MAP_E_INVALID on a null pointer or bad size or
+ * alignment. */
+int32_t map_calib_copy(void* dst_dev, const void* src_dev, int64_t bytes, void* stream);
+
+/* Device-scope int32 atomic adds without return into target_dev[n_words]
+ * (n_words a multiple of 16, at most 16 * (2^32 - 1)): n_waves waves (a
+ * multiple of 4, at most 2^24) of 64 lanes each issue per_wave (1..4096)
+ * instructions.  In every instruction each group of `lanes_per_line` lanes
+ * (1, 2, 4, 8, 16 or 64) adds 1 to words of one pseudo-random 64-byte line
+ * (a hash of seed, wave, instruction and group): distinct words for g <= 16,
+ * four lanes on each of the 16 words for g = 64.  Updates in total:
+ * 64 * n_waves * per_wave; line requests: that / lanes_per_line.  The sum of
+ * target_dev grows by exactly the number of updates.  MAP_E_INVALID on a bad
+ * argument. */
+int32_t map_calib_atomic(int32_t* target_dev, int64_t n_words, int64_t n_waves,
+                         int32_t per_wave, int32_t lanes_per_line, uint32_t seed, void* stream);
 
 /* Static text for a status code. */
 const char* map_status_str(int32_t status);

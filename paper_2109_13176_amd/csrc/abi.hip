@@ -274,7 +274,6 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   }
   m->seg_len = 8;
   m->trace_wpc = 32;
-  m->traversal = 2;
   // traversal blocks (at most 32 waves per CU) + the sensor-box fold blocks
   m->part_trace_cap = (int64_t)m->n_cu * 32 / 4 + gvom::box_fold_blocks() + 1;
   m->d.nx = p->nx;
@@ -303,14 +302,6 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   if (e == hipSuccess) e = dmalloc(&m->box_rep, (int64_t)gvom::kBoxReps * gvom::kBoxCells * 4);
   if (e == hipSuccess)
     e = hipMemsetAsync(m->box_rep, 0, (size_t)gvom::kBoxReps * gvom::kBoxCells * 4, m->stream);
-  m->gx = (p->nx + gvom::kBinT - 1) / gvom::kBinT;
-  m->gy = (p->ny + gvom::kBinT - 1) / gvom::kBinT;
-  m->nbins = 4 * m->gx * m->gy + 1;
-  if (m->nbins <= gvom::kMaxBins) {
-    if (e == hipSuccess) e = dmalloc(&m->bin_cnt, (int64_t)m->nbins * 4);
-    if (e == hipSuccess) e = dmalloc(&m->uctl, 8);
-    if (e == hipSuccess) e = hipMemsetAsync(m->bin_cnt, 0, (size_t)m->nbins * 4, m->stream);
-  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     map_destroy(m);
@@ -346,13 +337,10 @@ int32_t map_destroy(map_t* m) {
   (void)gvom::dev_free(m->err);
   (void)gvom::dev_free(m->nocc);
   (void)gvom::dev_free(m->touch);
-  (void)gvom::dev_free(m->items);
+  (void)gvom::dev_free(m->rays);
+  (void)gvom::dev_free(m->witems);
   (void)gvom::dev_free(m->part_rays);
   (void)gvom::dev_free(m->part_trace);
-  (void)gvom::dev_free(m->bin_cnt);
-  (void)gvom::dev_free(m->uctl);
-  (void)gvom::dev_free(m->bin_ent);
-  (void)gvom::dev_free(m->units);
   (void)gvom::dev_free(m->box_rep);
   delete m;
   return MAP_OK;
@@ -374,8 +362,6 @@ int32_t map_reset(map_t* m) {
   hipError_t e = clear_all(m);
   m->empty = true;
   if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, kStatsBytes, m->stream);
-  if (e == hipSuccess && m->bin_cnt)
-    e = hipMemsetAsync(m->bin_cnt, 0, (size_t)m->nbins * 4, m->stream);
   // an insert that failed between the traversal and the fold leaves counts
   if (e == hipSuccess)
     e = hipMemsetAsync(m->box_rep, 0, (size_t)gvom::kBoxReps * gvom::kBoxCells * 4, m->stream);
@@ -436,43 +422,29 @@ bool grow(map_t* m, T** p, int64_t* cap, int64_t need, size_t elem) {
   return false;
 }
 
-// Second half of an insert (after check_insert): grows the per-scan buffers,
-// moves the window (the slab clears go to `plan`; *full = whole window), and
-// fills the kernel arguments.  Updates the host-side map state.  `single`:
-// a single-map insert (binned traversal allowed; the batched step always
-// takes the segmented traversal).
-int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* pose,
-                       uint32_t flags, const int32_t S[3], gvom::InsertArgs* a,
-                       gvom::ClearArgs* plan, bool* full, bool single) {
-  // ray block b writes its segments into the region of stripe b mod kStripes,
-  // sized for the most segments that stripe's waves can reserve (64 slots per
-  // segment index of a wave, full waves also for the partial last block)
-  const int64_t bin_blocks = (n + gvom::kRayBinBlock - 1) / gvom::kRayBinBlock;
-  const bool binned =
-      single && m->traversal == 1 && m->bin_cnt && bin_blocks <= gvom::kMaxEnt;
-  const int64_t rb = binned ? gvom::kRayBinBlock : gvom::kRayBlock;  // threads per ray block
-  const int64_t ray_blocks = (n + rb - 1) / rb;
-  const int64_t per_ray =
-      binned ? gvom::max_segments_binned(m->d) : gvom::max_segments(m->d, m->seg_len);
-  int64_t need = 0;
+// The wave-item regions of the ray pass: ray block b reserves its waves'
+// items in the region of stripe b mod kStripes, sized for the most items
+// that stripe's waves can reserve (each wave at most one item per segment
+// its longest ray can have).  *need = wave items in all.
+void insert_layout(const map_t* m, int64_t ray_blocks, gvom::InsertArgs* a, int64_t* need) {
+  const int64_t per_ray = gvom::max_segments(m->d, m->seg_len);
+  int64_t tot = 0;
   for (int t = 0; t < gvom::kStripes; t++) {
     const int64_t blocks =
         ray_blocks > t ? (ray_blocks - t + gvom::kStripes - 1) / gvom::kStripes : 0;
-    const int64_t pts = blocks * rb;
-    a->stripe_off[t] = need;
-    a->stripe_cap[t] = pts * per_ray;
-    need += a->stripe_cap[t];
+    a->stripe_off[t] = tot;
+    a->stripe_cap[t] = blocks * (gvom::kRayBlock / 64) * per_ray;
+    tot += a->stripe_cap[t];
   }
-  if (binned && need > 2147483647LL) return MAP_E_RANGE;  // entries hold int32 offsets
-  if (!grow(m, &m->items, &m->item_cap, need, sizeof(int4))) return MAP_E_OOM;
-  if (!grow(m, &m->part_rays, &m->part_rays_cap, ray_blocks, 32)) return MAP_E_OOM;
-  if (binned) {
-    if (!grow(m, &m->bin_ent, &m->bin_ent_cap, (int64_t)m->nbins * (ray_blocks > 0 ? ray_blocks : 1),
-              sizeof(int2)))
-      return MAP_E_OOM;
-    if (!grow(m, &m->units, &m->units_cap, need / gvom::kUnit + m->nbins + 1, sizeof(int4)))
-      return MAP_E_OOM;
-  }
+  *need = tot;
+}
+
+// Everything of an insert but the per-scan buffers (a->rays, a->witems,
+// a->part_rays, set by the caller).
+int32_t fill_insert(map_t* m, const float* xyz_dev, int64_t n, const float* pose,
+                    uint32_t flags, const int32_t S[3], gvom::InsertArgs* a,
+                    gvom::ClearArgs* plan, bool* full, bool single, int64_t need) {
+  const int64_t ray_blocks = (n + gvom::kRayBlock - 1) / gvom::kRayBlock;
   *full = false;
   plan->nbox = 0;
   if (flags & MAP_RECENTER) {
@@ -505,32 +477,13 @@ int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* p
   a->occ = m->occ;
   a->stats = m->stats;
   a->touch = m->touch;
-  a->items = m->items;
-  a->part_rays = m->part_rays;
   a->part_trace = m->part_trace;
-  a->item_cap = m->item_cap;
   a->seg_len = m->seg_len;
   const int64_t tpb = single ? gvom::kTraceBlock : 256;  // threads per traversal block
-  const int64_t want = (need + tpb - 1) / tpb;
+  const int64_t want = (need + tpb / 64 - 1) / (tpb / 64);  // one wave per item
   int64_t lim = (int64_t)m->n_cu * m->trace_wpc / (tpb / 64);
   if (lim < 1) lim = 1;
   a->trace_blocks = n > 0 ? (int32_t)(want < lim ? want : lim) : 0;
-  a->binned = binned ? 1 : 0;
-  a->gx = m->gx;
-  a->gy = m->gy;
-  a->nb = m->nbins;
-  a->maxblk = (int32_t)(ray_blocks > 0 ? ray_blocks : 1);
-  a->bin_tot = m->bin_cnt;
-  a->bin_ent = m->bin_ent;
-  a->units = m->units;
-  a->uctl = m->uctl;
-  // persistent traversal: as many groups as fit next to each other per CU
-  const int64_t lds = (int64_t)gvom::trace_bin_lds(m->p.nz) + 6 * 1024;
-  int64_t per_cu = (160 * 1024) / lds;
-  if (per_cu < 1) per_cu = 1;
-  int64_t tb = (int64_t)m->n_cu * per_cu;
-  if (tb > m->part_trace_cap) tb = m->part_trace_cap;
-  a->tb_blocks = (int32_t)tb;
   // sensor box of the segmented traversal: the box of kBoxXY x kBoxXY x kBoxZ
   // window cells centred on the sensor's voxel, moved inside the window
   const int32_t ext[3] = {gvom::kBoxXY, gvom::kBoxXY, gvom::kBoxZ};
@@ -545,9 +498,29 @@ int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* p
     a->box_s[k] = (int32_t)((lo + m->d.ro[k]) % dims[k]);
   }
   a->box_rep = m->box_rep;
-  m->last_trace_blocks = binned ? a->tb_blocks : a->trace_blocks + gvom::box_fold_blocks();
+  m->last_trace_blocks = a->trace_blocks + gvom::box_fold_blocks();
   if (n <= 0) m->last_trace_blocks = 0;
   return MAP_OK;
+}
+
+// Second half of an insert (after check_insert): grows the per-scan buffers,
+// moves the window (the slab clears go to `plan`; *full = whole window), and
+// fills the kernel arguments.  Updates the host-side map state.  `single`: a
+// single-map insert (512-thread traversal blocks; a batch uses 256).
+int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* pose,
+                       uint32_t flags, const int32_t S[3], gvom::InsertArgs* a,
+                       gvom::ClearArgs* plan, bool* full, bool single) {
+  const int64_t ray_blocks = (n + gvom::kRayBlock - 1) / gvom::kRayBlock;
+  int64_t need = 0;
+  insert_layout(m, ray_blocks, a, &need);
+  if (!grow(m, &m->rays, &m->rays_cap, ray_blocks * gvom::kRayBlock, sizeof(int4)))
+    return MAP_E_OOM;
+  if (!grow(m, &m->witems, &m->witem_cap, need, sizeof(int2))) return MAP_E_OOM;
+  if (!grow(m, &m->part_rays, &m->part_rays_cap, ray_blocks, 32)) return MAP_E_OOM;
+  a->rays = m->rays;
+  a->witems = m->witems;
+  a->part_rays = m->part_rays;
+  return fill_insert(m, xyz_dev, n, pose, flags, S, a, plan, full, single, need);
 }
 
 // ranks: also write the table export's per-column ranks (single-map export)
@@ -758,19 +731,19 @@ int32_t map_import_voxels(map_t* m, const int32_t* lut_dev, const map_voxel_t* d
 int32_t map_get_stats(map_t* m, map_stats_t* out) {
   if (!m || !out) return MAP_E_INVALID;
   if (m->sticky) return m->sticky;
-  std::vector<unsigned long long> pr((size_t)m->last_ray_blocks * 4 + 1),
+  const int64_t nrb = m->last_ray_blocks;
+  std::vector<unsigned long long> pr((size_t)nrb * 4 + 1),
       pt((size_t)m->last_trace_blocks * 4 + 1);
   hipError_t e = hipSuccess;
-  if (m->last_ray_blocks)
-    e = hipMemcpyAsync(pr.data(), m->part_rays, m->last_ray_blocks * 32, hipMemcpyDeviceToHost,
-                       m->stream);
+  if (nrb)
+    e = hipMemcpyAsync(pr.data(), m->part_rays, nrb * 32, hipMemcpyDeviceToHost, m->stream);
   if (e == hipSuccess && m->last_trace_blocks)
     e = hipMemcpyAsync(pt.data(), m->part_trace, m->last_trace_blocks * 32,
                        hipMemcpyDeviceToHost, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) return dev_status(m, e);
   int64_t c[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int64_t b = 0; b < m->last_ray_blocks; b++) {
+  for (int64_t b = 0; b < nrb; b++) {
     c[0] += (int64_t)pr[4 * b + 0];
     c[1] += (int64_t)pr[4 * b + 1];
     c[2] += (int64_t)pr[4 * b + 2];
@@ -807,17 +780,11 @@ int32_t map_sync(map_t* m) {
 
 int32_t map_set_tuning(map_t* m, const map_tuning_t* t) {
   if (!m || !t) return MAP_E_INVALID;
-  if (t->seg_len > 1024 || t->trace_waves_per_cu > 32 || t->traversal > 2) return MAP_E_INVALID;
-  if (t->seg_len > 0 && t->seg_len != m->seg_len) {
-    // the segment buffer is sized for the segment length: regrow on next insert
-    if (hipStreamSynchronize(m->stream) != hipSuccess) return dev_status(m, hipErrorUnknown);
-    (void)gvom::dev_free(m->items);
-    m->items = nullptr;
-    m->item_cap = 0;
-    m->seg_len = t->seg_len;
-  }
+  if (t->seg_len > 1024 || t->trace_waves_per_cu > 32) return MAP_E_INVALID;
+  if (!(t->traversal <= 0 || t->traversal == 2)) return MAP_E_INVALID;
+  // the wave-item buffer is sized for the segment length at the next insert
+  if (t->seg_len > 0) m->seg_len = t->seg_len;
   if (t->trace_waves_per_cu > 0) m->trace_wpc = t->trace_waves_per_cu;
-  if (t->traversal > 0) m->traversal = t->traversal;
   return MAP_OK;
 }
 
@@ -825,7 +792,7 @@ int32_t map_get_tuning(const map_t* m, map_tuning_t* out) {
   if (!m || !out) return MAP_E_INVALID;
   out->seg_len = m->seg_len;
   out->trace_waves_per_cu = m->trace_wpc;
-  out->traversal = m->traversal;
+  out->traversal = 2;
   return MAP_OK;
 }
 

@@ -41,20 +41,6 @@ __host__ __device__ __forceinline__ int32_t col_base(const Dims& d, int32_t sx, 
 constexpr int kStripes = 16;  // independent segment counters of the ray pass
 static_assert((kStripes & (kStripes - 1)) == 0, "the traversal binary-searches the stripes");
 
-// Binned traversal: slab / tile edge along x and y (storage cells), storage
-// rows of a bin's LDS region along the cross axis, segments per work unit,
-// segment length of z-dominant rays, bin and entry limits, block size.
-constexpr int kBinT = 16;
-constexpr int kBinRows = 2 * kBinT + 4;
-constexpr int kLevelHalves = kBinT * kBinRows;    // 16-bit counters per z level
-constexpr int kLevelWords = kLevelHalves / 2;     // 32-bit LDS words per z level
-constexpr int kUnit = 1024;
-constexpr int kSegG = 32;
-constexpr int kMaxBins = 16385;
-constexpr int kMaxEnt = 512;
-constexpr int kTraceBinThreads = 512;
-constexpr int kRayBinBlock = 512;  // threads per block of the binned ray pass
-
 // Sensor box of the segmented traversal: every ray starts in the sensor's
 // voxel, so the cells around it take the passes of thousands of waves and
 // device atomics on their few cache lines serialize.  Passes of cells inside a
@@ -84,23 +70,13 @@ struct InsertArgs {
   uint32_t* touch;             // distinct-voxel bitmaps [2][V/32] or null
   unsigned long long* part_rays;   // per ray block: nonfinite, range, hits, distinct hits
   unsigned long long* part_trace;  // per trace block: passes, distinct passes, updates, 0
-  int4* items;                 // ray segments {Qx, Qy, Qz, segment index}; index < 0: empty slot
-  int64_t item_cap;
-  int64_t stripe_off[kStripes];  // item region of each stripe of ray blocks
+  int4* rays;                  // per ray (ray-pass lane): {Qx, Qy, Qz, segments}
+  int2* witems;                // wave items {ray wave, segment index}, per stripe
+  int64_t stripe_off[kStripes];  // wave-item region of each stripe of ray blocks
   int64_t stripe_cap[kStripes];
   int32_t seg_len;             // dominant-axis voxels per segment
   int32_t trace_blocks;        // grid of the trace kernel (kTraceBlock threads per block
                                // for a single map, 256 in a batch)
-  // binned traversal (used when `binned` is set)
-  int32_t binned;
-  int32_t gx, gy;              // slabs along x and along y (ceil(n / kBinT))
-  int32_t nb;                  // bins, the last one holding z-dominant rays
-  int32_t maxblk;              // ray blocks: entry slots per bin
-  int32_t* bin_tot;            // [nb] segments per bin (zeroed again by k_binscan)
-  int2* bin_ent;               // [nb][maxblk] {first item, count} of ray block b
-  int4* units;                 // {bin, first segment, segments, 0}
-  int32_t* uctl;               // [0] units
-  int32_t tb_blocks;           // grid of the binned traversal
   // sensor box (segmented traversal): storage coordinate of its first cell
   // and extent per axis; cell (dx, dy, dz) has box index
   // (dx * kBoxXY + dy) * kBoxZ + dz
@@ -118,11 +94,8 @@ constexpr int kTraceBlock = 512;
 // Blocks of the sensor-box fold that follows the segmented traversal.
 int box_fold_blocks();
 
-// Segments one ray can produce at most (segmented / binned traversal).
+// Segments one ray can produce at most.
 int64_t max_segments(const Dims& d, int32_t seg_len);
-int64_t max_segments_binned(const Dims& d);
-size_t rays_bin_lds(int nb);
-size_t trace_bin_lds(int nz);
 
 struct ColumnArgs {
   Dims d;
@@ -249,8 +222,6 @@ uint32_t nz_magic(int nz);
 hipError_t launch_clear(const ClearArgs& a, hipStream_t s);
 hipError_t launch_rays(const InsertArgs& a, bool distinct, hipStream_t s);
 hipError_t launch_trace(const InsertArgs& a, bool distinct, hipStream_t s);
-hipError_t launch_rays_bin(const InsertArgs& a, bool distinct, hipStream_t s);
-hipError_t launch_trace_bin(const InsertArgs& a, bool distinct, hipStream_t s);
 hipError_t launch_column(const ColumnArgs& a, hipStream_t s);
 hipError_t launch_surface(const SurfaceArgs& a, hipStream_t s);
 // counted: the column pass already wrote colpre / block_base for this state

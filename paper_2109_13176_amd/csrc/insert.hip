@@ -19,12 +19,10 @@ constexpr int kBlock = 256;
 // axis with the most voxel steps) the path is cut every seg_len voxels:
 // segment j holds the path voxels whose dominant coordinate lies j*seg_len ..
 // (j+1)*seg_len - 1 voxels from the sensor's.  Only segments that start
-// inside the window along the dominant axis are emitted.  A wave reserves
-// 64 slots per segment index (up to its longest ray) and writes segment j of
-// lane i to slot 64 j + i, an empty item where the ray has no segment j: a
-// traversal wave then holds exactly one segment index of 64 neighbouring
-// rays, so their voxels share cache lines (fewer atomic line requests than
-// packed items, which let waves straddle two segment indices).
+// inside the window along the dominant axis count.  Each lane writes its
+// ray's record {Q, segments}; a wave of 64 neighbouring rays with at most s
+// segments each then publishes s wave items {wave, j}, and a traversal wave
+// takes one item: segment j of those 64 rays, whose voxels share cache lines.
 template <bool DISTINCT>
 __device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
   __shared__ unsigned int wcount[kRayBlock / 64][5];
@@ -54,12 +52,12 @@ __device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
     }
   }
 
-  // reserve and write the segments, segment-major within the wave: one
-  // returning atomic per block, wave bases from the block's prefix
+  // reserve the wave items: one returning atomic per block, wave bases from
+  // the block's prefix
   int maxseg = nseg;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) maxseg = max(maxseg, __shfl_xor(maxseg, o));
-  const int total = maxseg * 64;
+  const int total = maxseg;
   const int c0 = __popcll(__ballot(nonfinite));
   const int c1 = __popcll(__ballot(outrange));
   const int c2 = __popcll(__ballot(hit));
@@ -92,12 +90,11 @@ __device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
     pr[2] = s2;
     pr[3] = s5;
   }
+  a.rays[i] = make_int4(q[0], q[1], q[2], nseg);
   __syncthreads();
-  unsigned long long off = wbase[wv];
-  for (int j = 0; j < maxseg; j++) {
-    a.items[off + lane] = nseg > j ? make_int4(q[0], q[1], q[2], j) : make_int4(0, 0, 0, -1);
-    off += 64;
-  }
+  const int gw = blk * (kRayBlock / 64) + wv;  // this wave's rays: 64 gw .. 64 gw + 63
+  const unsigned long long off = wbase[wv];
+  for (int j = lane; j < maxseg; j += 64) a.witems[off + j] = make_int2(gw, j);
 }
 
 template <bool DISTINCT>
@@ -124,22 +121,75 @@ __global__ __launch_bounds__(kRayBlock) void k_rays(InsertArgs a) {
 // first (the shared boundary belongs to the upper cell) and the axes moving
 // down step in the next iteration, so the voxel at that instant is visited.
 //
-// Lanes of a wave step in lock-step; the lanes that pass the same voxel as
-// their left neighbour join its run and the run's first lane adds the run
-// length with one atomic.  With BOX, runs in the sensor box add into the
-// block's LDS copy of the box instead, which the block flushes into its
-// replica at the end (k_box_fold adds the replicas into the map).
+// Counting.  Device atomics are charged per (instruction, 64-byte line) at
+// the memory side, and the 64 rays of a wave item pass a compact set of lines
+// (about 15 on the 64-beam workload, against about 60 line requests when
+// every step adds its voxels straight to the map).  So each wave counts its
+// item in a private LDS line table: kWtSlots slots of one 64-byte storage
+// line each (16 counters and a tag = storage index >> 4), found by a hash of
+// the line with kWtProbe linear probes and claimed by compare-and-swap; a lane
+// remembers the slot of its current line, so it looks up only when its ray
+// enters another line.  When the item is done the wave adds every non-zero
+// counter of its claimed slots to the map, 16 lanes per line (one line request
+// per line), and empties the table.  A line that finds no slot on its probe
+// path is added to the map directly.  With BOX, voxels in the sensor box add
+// into the block's LDS copy of the box instead, which the block flushes into
+// its replica at the end (k_box_fold adds the replicas into the map).  Every
+// pass ends up in exactly one counter that reaches the map once, so the
+// result is the same integer sum whatever the claim order.
+constexpr int kWtSlots = 64;     // slots per wave (one per lane at the flush)
+constexpr int kWtStride = 17;    // LDS words per slot's counters (bank spread)
+constexpr int kWtProbe = 4;
+constexpr int32_t kWtEmpty = -1;
+
+struct WaveTable {
+  int32_t tag[kWtSlots];
+  int32_t cnt[kWtSlots * kWtStride];
+  int32_t lst[kWtSlots];
+};
+
+// Orders the LDS accesses of one wave's lanes (a wave's LDS operations are
+// executed in issue order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Slot of storage line `line` in the wave's table, claiming an empty one on
+// its probe path; -1 when the path holds other lines only.
+__device__ __forceinline__ int wt_lookup(WaveTable& wt, const int32_t line) {
+  uint32_t h = (uint32_t)line;  // 32-bit finaliser of MurmurHash3 (Appleby)
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  const int s0 = (int)(h >> 26);
+#pragma unroll
+  for (int p = 0; p < kWtProbe; p++) {
+    const int s = (s0 + p) & (kWtSlots - 1);
+    int32_t t = wt.tag[s];
+    if (t == kWtEmpty) t = atomicCAS(&wt.tag[s], kWtEmpty, line);
+    if (t == kWtEmpty || t == line) return s;
+  }
+  return -1;
+}
+
 template <bool DISTINCT, bool BOX, int NT>
 __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, const int nblk) {
   const int lane = __lane_id();
   __shared__ int32_t box_cnt[BOX ? kBoxCells : 1];
+  __shared__ WaveTable wtab[NT / 64];
+  WaveTable& wt = wtab[threadIdx.x >> 6];
+  wt.tag[lane] = kWtEmpty;
+  for (int i = lane; i < kWtSlots * kWtStride; i += 64) wt.cnt[i] = 0;
   if (BOX) {
     for (int i = threadIdx.x; i < kBoxCells; i += NT) box_cnt[i] = 0;
-    __syncthreads();
   }
+  __syncthreads();
   const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
   const int32_t dims[3] = {nx, ny, nz};
-  // items of stripe t occupy [stripe_off[t], stripe_off[t] + cnt[t]); the
+  // wave items of stripe t occupy [stripe_off[t], stripe_off[t] + cnt[t]); the
   // loop runs over their concatenation.  The stripe prefix lives in LDS
   // (in registers it would cost the kernel its last wave per SIMD).
   __shared__ int64_t s_pre[kStripes + 1];
@@ -155,30 +205,29 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
     s_pre[kStripes] = p;
   }
   __syncthreads();
-  const int64_t count = s_pre[kStripes];
-  const int64_t stride = (int64_t)nblk * NT;
+  const int64_t count = s_pre[kStripes];  // wave items
+  const int64_t stride = (int64_t)nblk * (NT / 64);
   uint32_t* touch_p = DISTINCT ? a.touch + ((a.d.vs + 31) >> 5) : nullptr;
   int32_t* const passes = a.passes;  // kept in registers across the loop
   int n_pass = 0, n_dpass = 0, n_upd = 0;  // n_pass is wave-uniform
 
-  for (int64_t wbase = (int64_t)blk * NT + (threadIdx.x & ~63); wbase < count;
-       wbase += stride) {
-    const int64_t it = wbase + lane;
+  for (int64_t u = (int64_t)blk * (NT / 64) + (threadIdx.x >> 6); u < count; u += stride) {
     bool active = false, near = false;
     Walk w = {};
     int32_t cnt[3] = {0, 0, 0};
     bool stop[3] = {false, false, false};
     int32_t sc[3] = {0, 0, 0};
     int32_t sidx = 0;
-    if (it < count) {
-      // last stripe t with s_pre[t] <= it (empty stripes share their prefix)
+    {
+      // last stripe t with s_pre[t] <= u (empty stripes share their prefix)
       int t = 0;
 #pragma unroll
       for (int step = kStripes / 2; step >= 1; step >>= 1)
-        if (it >= s_pre[t + step]) t += step;
-      const int4 item = a.items[s_base[t] + it];
-      const int32_t q[3] = {item.x, item.y, item.z};
-      const int j = item.w < 0 ? 0 : item.w;  // w < 0: empty slot
+        if (u >= s_pre[t + step]) t += step;
+      const int2 item = a.witems[s_base[t] + u];
+      const int4 ray = a.rays[(int64_t)item.x * 64 + lane];
+      const int32_t q[3] = {ray.x, ray.y, ray.z};
+      const int j = item.y;
       int32_t sv[3], n[3], sg[3], ad[3];
 #pragma unroll
       for (int k = 0; k < 3; k++) {
@@ -191,8 +240,8 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
       }
       const int dom = dominant_axis(n);
       int32_t v[3] = {sv[0], sv[1], sv[2]};
-      if (j > 0) entry_voxel(a.S, sg, ad, dom, sv[dom] + sg[dom] * j * a.seg_len, v);
-      bool inside = item.w >= 0;
+      bool inside = j < ray.w;  // the ray has segment j
+      if (inside && j > 0) entry_voxel(a.S, sg, ad, dom, sv[dom] + sg[dom] * j * a.seg_len, v);
       int32_t l[3];
 #pragma unroll
       for (int k = 0; k < 3; k++) {
@@ -221,20 +270,14 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
     const bool px = w.sg[0] > 0, py = w.sg[1] > 0, pz = w.sg[2] > 0;
     const int32_t trig0 = px ? nx : -1, trig1 = py ? ny : -1, trig2 = pz ? nz : -1;
     const int32_t wv0 = px ? 0 : nx - 1, wv1 = py ? 0 : ny - 1, wv2 = pz ? 0 : nz - 1;
+    int32_t cur_line = kWtEmpty;  // this lane's current line and its slot
+    int cur_slot = -1;
     for (;;) {
       const unsigned long long ab = __ballot(active);
       if (!ab) break;
       n_pass += __popcll(ab);
-      // ---- aggregated pass of the current voxel: runs of equal addresses in
-      // neighbouring lanes (left neighbour via a whole-wave DPP shift)
-      const int addr = active ? sidx : -1;
-      const int prev = __builtin_amdgcn_update_dpp(-2, addr, 0x138, 0xf, 0xf, false);
-      const bool head = active && prev != addr;
-      const unsigned long long hb = __ballot(head);
-      if (head) {
-        const unsigned long long bnd = hb | ~ab;
-        const unsigned long long after = lane == 63 ? 0ull : (bnd >> (lane + 1));
-        const int len = after ? __ffsll((long long)after) : 64 - lane;
+      // ---- one pass of the current voxel
+      if (active) {
         int bidx = -1;
         if (BOX && wnear) {
           // storage offsets from the box's first cell (unsigned: wrapped)
@@ -245,14 +288,23 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
             bidx = (int)((d0 * kBoxXY + d1) * kBoxZ + d2);
         }
         if (BOX && bidx >= 0) {
-          atomicAdd(&box_cnt[bidx], len);
+          atomicAdd(&box_cnt[bidx], 1);
         } else {
-          n_upd++;
-          atomicAdd(&passes[addr], len);
-          if (DISTINCT) {
-            const uint32_t bit = 1u << (addr & 31);
-            const uint32_t old = atomicOr(&touch_p[(uint32_t)addr >> 5], bit);
-            n_dpass += !(old & bit);
+          const int32_t line = sidx >> 4;
+          if (line != cur_line) {
+            cur_line = line;
+            cur_slot = wt_lookup(wt, line);
+          }
+          if (cur_slot >= 0) {
+            atomicAdd(&wt.cnt[cur_slot * kWtStride + (sidx & 15)], 1);
+          } else {
+            n_upd++;
+            atomicAdd(&passes[sidx], 1);
+            if (DISTINCT) {
+              const uint32_t bit = 1u << (sidx & 31);
+              const uint32_t old = atomicOr(&touch_p[(uint32_t)sidx >> 5], bit);
+              n_dpass += !(old & bit);
+            }
           }
         }
       }
@@ -267,6 +319,37 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
       sc[2] = t2 == trig2 ? wv2 : t2;
       sidx = col_base24(a.d, sc[0], sc[1]) + (sc[2] << 4);
       active = active & !out & ((cnt[0] | cnt[1] | cnt[2]) != 0);
+    }
+    // ---- flush the wave's table: 16 lanes per claimed line
+    wave_lds_sync();
+    const int32_t tg = wt.tag[lane];
+    const unsigned long long vm = __ballot(tg != kWtEmpty);
+    if (vm) {
+      if (tg != kWtEmpty) wt.lst[__popcll(vm & ((1ull << lane) - 1ull))] = lane;
+      wave_lds_sync();
+      const int nv = __popcll(vm);
+      const int w = lane & 15;
+      for (int k = 0; k < nv; k += 4) {
+        const int e = k + (lane >> 4);
+        if (e < nv) {
+          const int s = wt.lst[e];
+          const int c = wt.cnt[s * kWtStride + w];
+          if (c) {
+            wt.cnt[s * kWtStride + w] = 0;
+            const int32_t addr = (wt.tag[s] << 4) + w;
+            n_upd++;
+            atomicAdd(&passes[addr], c);
+            if (DISTINCT) {
+              const uint32_t bit = 1u << (addr & 31);
+              const uint32_t old = atomicOr(&touch_p[(uint32_t)addr >> 5], bit);
+              n_dpass += !(old & bit);
+            }
+          }
+        }
+      }
+      wave_lds_sync();
+      wt.tag[lane] = kWtEmpty;
+      wave_lds_sync();
     }
   }
   if (BOX) {
@@ -540,7 +623,6 @@ int64_t max_segments(const Dims& d, int32_t seg_len) {
 hipError_t launch_rays(const InsertArgs& a, bool distinct, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
   const int g = (a.n + kRayBlock - 1) / kRayBlock;
-  if (a.binned) return launch_rays_bin(a, distinct, s);
   if (distinct)
     hipLaunchKernelGGL(k_rays<true>, dim3(g), dim3(kRayBlock), 0, s, a);
   else
@@ -550,7 +632,6 @@ hipError_t launch_rays(const InsertArgs& a, bool distinct, hipStream_t s) {
 
 hipError_t launch_trace(const InsertArgs& a, bool distinct, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  if (a.binned) return launch_trace_bin(a, distinct, s);
   if (!a.box_rep || a.trace_blocks < 1) return hipErrorInvalidValue;
   const dim3 fb(kFoldCellBlocks, kFoldGroups);
   if (distinct) {
@@ -564,5 +645,6 @@ hipError_t launch_trace(const InsertArgs& a, bool distinct, hipStream_t s) {
 }
 
 int box_fold_blocks() { return kFoldCellBlocks * kFoldGroups; }
+
 
 }  // namespace gvom

@@ -24,22 +24,15 @@ struct map_t {
   int32_t* err;
   int64_t* nocc;              // occupied-voxel count of a synchronous table export
   uint32_t* touch;            // distinct-voxel bitmaps, allocated on first use
-  int4* items;                // ray segments of the current insert
-  int64_t item_cap;
+  int4* rays;                 // per-ray records of the current insert
+  int2* witems;               // its wave items
+  int64_t rays_cap, witem_cap;
   unsigned long long* part_rays;   // per-block counters of the ray pass
   unsigned long long* part_trace;  // per-block counters of the traversal pass
   int64_t part_rays_cap, part_trace_cap;
   int64_t last_ray_blocks, last_trace_blocks;
   int32_t seg_len;
   int32_t trace_wpc;
-  int32_t traversal;          // 1: binned when the window allows it, 2: segmented
-  // binned traversal state (allocated when the window gives few enough bins)
-  int32_t gx, gy, nbins;      // slabs along x / y; bins incl. the z-dominant one
-  int32_t* bin_cnt;           // [nbins] segments per bin
-  int32_t* uctl;              // [1] work units
-  int2* bin_ent;              // [nbins][blocks]
-  int4* units;
-  int64_t bin_ent_cap, units_cap;
   int32_t* box_rep;           // sensor-box replicas of the segmented traversal
   int32_t n_cu;
   int32_t sticky;

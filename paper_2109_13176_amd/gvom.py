@@ -78,6 +78,7 @@ EXPORTED = [
     "sgt_set_norm", "sgt_features", "sgt_thin", "sgt_feature_sums", "sgt_forward",
     "sgt_loss_grad", "sgt_adam", "sgt_fill",
     "map_set_device_memory_limit", "map_device_memory_in_use",
+    "map_calib_copy", "map_calib_atomic",
 ]
 PROF_PHASES = ("scroll", "rays", "trace", "column", "surface", "lut")
 
@@ -142,6 +143,8 @@ def lib() -> ctypes.CDLL:
         L.sgt_fill.argtypes = [P, ctypes.POINTER(map_2d_t), I32, I32, ctypes.c_float, P, P, P]
         L.map_profile_enable.argtypes = [P, I32]
         L.map_profile_read.argtypes = [P, P, P]
+        L.map_calib_copy.argtypes = [P, P, I64, P]
+        L.map_calib_atomic.argtypes = [P, I64, I64, I32, I32, ctypes.c_uint32, P]
         L.map_status_str.argtypes = [I32]
         L.map_status_str.restype = ctypes.c_char_p
         for f in EXPORTED:
@@ -721,3 +724,25 @@ def sgt_fill(pred, plain, tol_m: float, stream=None):
     if s != MAP_OK:
         raise RuntimeError(f"sgt_fill: {map_status_str(s)}")
     return h, r
+
+
+def map_calib_copy(dst, src, stream=None) -> int:
+    """Enqueues the library's plain device copy of src into dst (same size)."""
+    import torch
+    if dst.numel() * dst.element_size() != src.numel() * src.element_size():
+        raise ValueError("map_calib_copy: sizes differ")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return lib().map_calib_copy(_dev(dst), _dev(src), dst.numel() * dst.element_size(),
+                                ctypes.c_void_p(stream.cuda_stream))
+
+
+def map_calib_atomic(target, n_waves: int, per_wave: int, lanes_per_line: int,
+                     seed: int = 1, stream=None) -> int:
+    """Enqueues the library's scattered atomic-add kernel on the int32 target."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return lib().map_calib_atomic(_dev(target, torch.int32), target.numel(), n_waves, per_wave,
+                                  lanes_per_line, ctypes.c_uint32(seed),
+                                  ctypes.c_void_p(stream.cuda_stream))

@@ -17,11 +17,11 @@ ROUGH_RTOL = 1e-5
 class Pair:
     """The HIP map and the oracle map, fed the same inputs."""
 
-    def __init__(self, params, traversal=0):
+    def __init__(self, params, seg_len=0):
         self.params = dict(params)
         self.g = gvom.VoxelMap(params)
-        if traversal:
-            assert gvom.map_set_tuning(self.g.h, traversal=traversal) == 0
+        if seg_len:
+            assert gvom.map_set_tuning(self.g.h, seg_len=seg_len) == 0
         self.o = oracle.OracleMap(params)
 
     def insert(self, xyz, pose, flags=0, firing=0):

@@ -184,15 +184,16 @@ def test_batched_32_vehicles_autotuned_full_size():
             o.close()
 
 
-@pytest.mark.parametrize("traversal", [2, 1])
-def test_64beam_scans_both_traversals(traversal):
-    """The first three scans of the sequence under each traversal mode."""
+@pytest.mark.parametrize("seg_len", [8, 5])
+def test_64beam_scans_segment_lengths(seg_len):
+    """The first three scans of the sequence with the default segment length
+    and with one that cuts rays at other cells."""
     from paper_2109_13176_amd import gvom
     seq = scenegen.sequence_64beam(seed=2, n_sim=3, device="cuda")
-    pair = Pair(seq["params"], traversal)
+    pair = Pair(seq["params"], seg_len)
     try:
         for k in range(3):
-            print(f"64-beam scan {k}, traversal {traversal}", flush=True)
+            print(f"64-beam scan {k}, segment length {seg_len}", flush=True)
             assert pair.insert(seq["scans"][k], seq["poses"][k], gvom.MAP_RECENTER,
                                firing=64) == 0
         n, g, o = compare_all(pair)

@@ -26,11 +26,11 @@ def _cloud(rng, n, radius):
     return p.astype(np.float32)
 
 
-@pytest.mark.parametrize("traversal", [1, 2])
+@pytest.mark.parametrize("seg_len", [3, 8])
 @pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 257, 3001])
-def test_ragged_clouds_tiny_map(n, traversal):
+def test_ragged_clouds_tiny_map(n, seg_len):
     rng = np.random.default_rng(100 + n)
-    pair = Pair(params(16, 16, 16, 0.5, szv=7), traversal)
+    pair = Pair(params(16, 16, 16, 0.5, szv=7), seg_len)
     try:
         pose = scenegen.pose12(_rot(0.3, 0.1, -0.2), [0.7, -0.4, 0.25])
         assert pair.insert(_cloud(rng, n, 6.0), pose, 0) == 0
@@ -42,11 +42,11 @@ def test_ragged_clouds_tiny_map(n, traversal):
 @pytest.mark.parametrize("dims", [(16, 16, 16, 0.5), (18, 10, 12, 0.25), (40, 26, 7, 0.3),
                                   (32, 32, 64, 0.2), (30, 34, 96, 0.1), (20, 22, 128, 0.15),
                                   (24, 24, 48, 0.4)])
-@pytest.mark.parametrize("traversal", [1, 2])
-def test_shapes_and_distinct_counts(dims, traversal):
+@pytest.mark.parametrize("seg_len", [3, 8])
+def test_shapes_and_distinct_counts(dims, seg_len):
     nx, ny, nz, res = dims
     rng = np.random.default_rng(nx * 1000 + nz)
-    pair = Pair(params(nx, ny, nz, res), traversal)
+    pair = Pair(params(nx, ny, nz, res), seg_len)
     try:
         for k in range(3):
             ang = rng.uniform(-np.pi, np.pi, 3) * np.array([1, 0.3, 0.3])
@@ -101,10 +101,10 @@ def test_table_export_reuses_2d_export_ranks():
         pair.close()
 
 
-@pytest.mark.parametrize("traversal", [1, 2])
-def test_single_scan_16beam_scene(traversal):
+@pytest.mark.parametrize("seg_len", [3, 8])
+def test_single_scan_16beam_scene(seg_len):
     w = scenegen.single_scan_16beam(seed=1)
-    pair = Pair(w["params"], traversal)
+    pair = Pair(w["params"], seg_len)
     try:
         assert pair.insert(w["scans"][0], w["poses"][0], 2, firing=16) == 0
         n, g, o = compare_all(pair, distinct=True)
@@ -132,13 +132,13 @@ def test_firing_hint_does_not_change_results():
             assert (o2[k].view(np.uint8) == outs[0][2][k].view(np.uint8)).all(), k
 
 
-@pytest.mark.parametrize("traversal", [1, 2])
-def test_moving_window_sequence(traversal):
+@pytest.mark.parametrize("seg_len", [3, 8])
+def test_moving_window_sequence(seg_len):
     """Recentring every scan: scrolls in x, y and z (toroidal wrap), one jump
     larger than the window (full clear), general rotations."""
     rng = np.random.default_rng(7)
     p = params(48, 40, 20, 0.5, szv=8)
-    pair = Pair(p, traversal)
+    pair = Pair(p, seg_len)
     try:
         pos = np.zeros(3)
         for k in range(14):
@@ -304,17 +304,19 @@ def _state(m):
 
 
 @pytest.mark.parametrize("distinct", [False, True])
-def test_traversal_modes_bit_identical(distinct):
-    """The binned traversal (LDS tiles) and the segmented one (global atomics)
-    give the same map bit for bit: four scans of the 64-beam sequence on the
-    512 x 512 x 64 window (recentred each scan, so the storage offsets move),
-    then a cloud of steep rays (z-dominant ones take the global bin)."""
+def test_tunings_bit_identical(distinct):
+    """Results do not depend on the launch tuning: the default traversal
+    (segments of 8 voxels, 32 waves per CU) and a different one (segments of
+    32 voxels, 8 waves per CU, so other waves share line tables and other
+    blocks share the sensor box) give the same map bit for bit: four scans of
+    the 64-beam sequence on the 512 x 512 x 64 window (recentred each scan, so
+    the storage offsets move), then a cloud of steep rays."""
     from paper_2109_13176_amd import gvom
     seq = scenegen.sequence_64beam(seed=2, n_sim=4, device="cuda")
     maps = [gvom.VoxelMap(seq["params"]) for _ in range(2)]
-    for m, mode in zip(maps, (1, 2)):
-        assert gvom.map_set_tuning(m.h, traversal=mode) == 0
-        assert gvom.map_get_tuning(m.h)[1]["traversal"] == mode
+    assert gvom.map_set_tuning(maps[1].h, seg_len=32, trace_waves_per_cu=8) == 0
+    assert gvom.map_get_tuning(maps[1].h)[1]["seg_len"] == 32
+    assert gvom.map_set_tuning(maps[1].h, traversal=1) == gvom.MAP_E_INVALID
     rng = np.random.default_rng(3)
     steep = _cloud(rng, 20000, 30.0)
     steep[:, 2] *= 3.0
