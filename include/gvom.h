@@ -169,6 +169,25 @@ int32_t map_reset(map_t* m);
 int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float pose[12],
                         uint32_t flags);
 
+/* map_insert_scan for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and errors as map_insert_scan, but the per-scan
+ * work buffers (ray records, wave items, per-block counters; at most
+ * 64 MiB) come from a fixed device array of the library, one per GPU, held
+ * until the process ends, instead of buffers the map grows, and the call
+ * enqueues kernels only (no allocation, no memset, no event).  The array is
+ * shared by every map on the GPU: calls that overlap on one GPU (maps on
+ * different streams) race and give wrong results; calls on one stream are
+ * ordered and safe.  MAP_E_CAPACITY (map unchanged) when the scan needs more
+ * than the array holds: about 16 + 8 * ceil(max(nx, ny, nz) / seg_len) / 64
+ * bytes per point, so 2.7 M points on a 512 x 512 x 64 window at the default
+ * seg_len of 8.
+ * MAP_STATS_DISTINCT is not accepted (MAP_E_INVALID): its bitmaps are
+ * allocated on first use.  map_get_stats reports the call's counters until
+ * the next insert into the same map. */
+int32_t map_insert_scan_static(map_t* m, const float* xyz_dev, int64_t n,
+                               const float pose[12], uint32_t flags);
+
 /* Writes the 2D maps of Sec. III-D into the caller's device arrays. *//* Writes the 2D maps of Sec. III-D into the caller's device arrays. */
 int32_t map_export_2d(map_t* m, const map_2d_t* out_dev);
 

@@ -456,6 +456,7 @@ int32_t fill_insert(map_t* m, const float* xyz_dev, int64_t n, const float* pose
   }
   m->last_points = n;
   m->last_distinct = false;
+  m->last_static = false;
   m->last_ray_blocks = n > 0 ? ray_blocks : 0;
   a->xyz = xyz_dev;
   a->n = (int32_t)n;
@@ -577,6 +578,56 @@ bool valid_2d(const map_2d_t* out) {
 
 }  // namespace
 
+// ---- the insert without allocation (map_insert_scan_static) ----------------
+// Its per-scan work buffers (ray records, wave items, per-block ray counters)
+// live in this file-scope device array instead of buffers the map grows: one
+// copy per device, held until the process ends, shared by every such call on
+// that device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device
+
+// Device address of the scratch array on device `dev`, looked up once per
+// device with that device current (the array's host-side name is not a
+// device address); null on failure.
+unsigned char* device_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = (unsigned char*)p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bytes of the scratch an insert of n points needs (ray records, wave items,
+// per-block counters), each region 256-byte aligned.
+size_t static_insert_bytes(const map_t* m, int64_t n, int64_t* need) {
+  const int64_t ray_blocks = (n + gvom::kRayBlock - 1) / gvom::kRayBlock;
+  gvom::InsertArgs tmp;
+  insert_layout(m, ray_blocks, &tmp, need);
+  return align256((size_t)ray_blocks * gvom::kRayBlock * sizeof(int4)) +
+         align256((size_t)*need * sizeof(int2)) + align256((size_t)ray_blocks * 32);
+}
+
+}  // namespace
+
 extern "C" {
 
 int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float pose[12],
@@ -614,6 +665,44 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
       e = gvom::launch_trace(a, distinct, m->stream);
       prof_end(m, pm);
     }
+  }
+  return dev_status(m, e);
+}
+
+int32_t map_insert_scan_static(map_t* m, const float* xyz_dev, int64_t n, const float pose[12],
+                               uint32_t flags) {
+  int32_t S[3];
+  if (m && (flags & MAP_STATS_DISTINCT)) return MAP_E_INVALID;
+  int32_t st = check_insert(m, xyz_dev, n, pose, flags, S);
+  if (st) return st;
+  int64_t need = 0;
+  if (static_insert_bytes(m, n, &need) > kScratchBytes) return MAP_E_CAPACITY;
+  unsigned char* base = device_scratch(m->device);
+  if (!base) return MAP_E_DEVICE;  // nothing enqueued, the map is unchanged
+  gvom::InsertArgs a;
+  gvom::ClearArgs plan;
+  bool full = false;
+  const int64_t ray_blocks = (n + gvom::kRayBlock - 1) / gvom::kRayBlock;
+  insert_layout(m, ray_blocks, &a, &need);
+  a.rays = (int4*)base;
+  base += align256((size_t)ray_blocks * gvom::kRayBlock * sizeof(int4));
+  a.witems = (int2*)base;
+  base += align256((size_t)need * sizeof(int2));
+  a.part_rays = (unsigned long long*)base;
+  m->lut_counted = false;
+  m->version = gvom::next_version();
+  st = fill_insert(m, xyz_dev, n, pose, flags, S, &a, &plan, &full, true, need);
+  if (st) return st;
+  m->last_static = true;
+  // kernels only (no memset, no allocation): callers may capture this call
+  hipError_t e = m->empty ? hipSuccess : full ? clear_all(m) : gvom::launch_clear(plan, m->stream);
+  if (n > 0) m->empty = false;
+  if (e == hipSuccess)
+    e = gvom::launch_fill_i32((int32_t*)m->stats, 0, (int64_t)(kStatsBytes / 4), m->stream);
+  if (e == hipSuccess && n > 0) {
+    e = gvom::launch_rays(a, false, m->stream);
+    if (e == hipSuccess) e = gvom::launch_trace(a, false, m->stream);
+    if (e == hipSuccess) e = gvom::launch_sum_ray_parts(a.part_rays, ray_blocks, m->stats, m->stream);
   }
   return dev_status(m, e);
 }
@@ -731,12 +820,14 @@ int32_t map_import_voxels(map_t* m, const int32_t* lut_dev, const map_voxel_t* d
 int32_t map_get_stats(map_t* m, map_stats_t* out) {
   if (!m || !out) return MAP_E_INVALID;
   if (m->sticky) return m->sticky;
-  const int64_t nrb = m->last_ray_blocks;
+  // a static insert left its ray-pass sums in stats[0..3] (one "block")
+  const int64_t nrb = m->last_static ? (m->last_ray_blocks ? 1 : 0) : m->last_ray_blocks;
   std::vector<unsigned long long> pr((size_t)nrb * 4 + 1),
       pt((size_t)m->last_trace_blocks * 4 + 1);
   hipError_t e = hipSuccess;
   if (nrb)
-    e = hipMemcpyAsync(pr.data(), m->part_rays, nrb * 32, hipMemcpyDeviceToHost, m->stream);
+    e = hipMemcpyAsync(pr.data(), m->last_static ? m->stats : m->part_rays, nrb * 32,
+                       hipMemcpyDeviceToHost, m->stream);
   if (e == hipSuccess && m->last_trace_blocks)
     e = hipMemcpyAsync(pt.data(), m->part_trace, m->last_trace_blocks * 32,
                        hipMemcpyDeviceToHost, m->stream);

@@ -230,6 +230,9 @@ hipError_t launch_import(const Dims& d, const int32_t* lut, const map_voxel_t* d
                          int64_t n_data, int32_t* hits, int32_t* passes, int32_t* minqz,
                          unsigned long long* occ, int32_t* err, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+// out[0..3] = column sums of the ray pass's per-block counters parts[nblocks][4].
+hipError_t launch_sum_ray_parts(const unsigned long long* parts, int64_t nblocks,
+                                unsigned long long* out, hipStream_t s);
 hipError_t launch_density(const DensityArgs& a, hipStream_t s);
 hipError_t launch_costmap(const CostArgs& a, hipStream_t s);
 // Exclusive prefix of base[0..nb) in place (one block); *total = the sum.

@@ -645,6 +645,34 @@ hipError_t launch_trace(const InsertArgs& a, bool distinct, hipStream_t s) {
 }
 
 int box_fold_blocks() { return kFoldCellBlocks * kFoldGroups; }
+// Sums the ray pass's per-block counters (4 per block) into out[0..3]: one
+// block, each thread a strided share of the blocks, then a fixed-order sum
+// over the threads (no atomics).
+__global__ __launch_bounds__(kBlock) void k_sum_ray_parts(const unsigned long long* parts,
+                                                          int64_t nblocks,
+                                                          unsigned long long* out) {
+  __shared__ unsigned long long s[4][kBlock];
+  unsigned long long c[4] = {0, 0, 0, 0};
+  for (int64_t b = threadIdx.x; b < nblocks; b += kBlock)
+#pragma unroll
+    for (int k = 0; k < 4; k++) c[k] += parts[4 * b + k];
+#pragma unroll
+  for (int k = 0; k < 4; k++) s[k][threadIdx.x] = c[k];
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+#pragma unroll
+      for (int k = 0; k < 4; k++) s[k][threadIdx.x] += s[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+hipError_t launch_sum_ray_parts(const unsigned long long* parts, int64_t nblocks,
+                                unsigned long long* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_ray_parts, dim3(1), dim3(kBlock), 0, s, parts, nblocks, out);
+  return hipGetLastError();
+}
 
 
 }  // namespace gvom

@@ -38,6 +38,9 @@ struct map_t {
   int32_t sticky;
   int64_t last_points, last_cleared;
   bool last_distinct;
+  // the last insert ran from the device's static scratch: its ray-pass
+  // counters were summed into stats[0..3] (the per-block ones are not kept)
+  bool last_static;
   int32_t prof_mask;          // profiled phases (bit p = phase p)
   // the last 2D export left the table export's per-column ranks (colpre,
   // block_base) for the current map state; any change of the map clears it

@@ -78,7 +78,7 @@ EXPORTED = [
     "sgt_set_norm", "sgt_features", "sgt_thin", "sgt_feature_sums", "sgt_forward",
     "sgt_loss_grad", "sgt_adam", "sgt_fill",
     "map_set_device_memory_limit", "map_device_memory_in_use",
-    "map_calib_copy", "map_calib_atomic",
+    "map_calib_copy", "map_calib_atomic", "map_insert_scan_static",
 ]
 PROF_PHASES = ("scroll", "rays", "trace", "column", "surface", "lut")
 
@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
         L.map_destroy.argtypes = [P]
         L.map_reset.argtypes = [P]
         L.map_insert_scan.argtypes = [P, P, I64, P, ctypes.c_uint32]
+        L.map_insert_scan_static.argtypes = [P, P, I64, P, ctypes.c_uint32]
         L.map_export_2d.argtypes = [P, ctypes.POINTER(map_2d_t)]
         L.map_export_voxels.argtypes = [P, P, P, I64, P, P]
         L.map_export_voxels_async.argtypes = [P, P, P, I64, P, P]
@@ -208,6 +209,18 @@ def map_insert_scan(h, xyz, pose, flags: int = 0) -> int:
         raise ValueError("xyz must be [n, 3]")
     pose = np.ascontiguousarray(pose, dtype=np.float32).reshape(12)
     return lib().map_insert_scan(h, ptr, n, pose.ctypes.data_as(ctypes.c_void_p), flags)
+
+
+def map_insert_scan_static(h, xyz, pose, flags: int = 0) -> int:
+    """map_insert_scan whose work buffers come from the library's fixed
+    per-GPU array (no device allocation)."""
+    import torch
+    n = 0 if xyz is None else xyz.shape[0]
+    ptr = ctypes.c_void_p(0) if n == 0 else _dev(xyz, torch.float32, "xyz")
+    if n and (xyz.dim() != 2 or xyz.shape[1] != 3):
+        raise ValueError("xyz must be [n, 3]")
+    pose = np.ascontiguousarray(pose, dtype=np.float32).reshape(12)
+    return lib().map_insert_scan_static(h, ptr, n, pose.ctypes.data_as(ctypes.c_void_p), flags)
 
 
 def map_export_2d(h, out: dict) -> int:
