@@ -259,13 +259,14 @@ int32_t map_sync(map_t* m);
  * request; the passes of a 17 x 17 x 9 box around the sensor are summed per
  * block on chip first.  seg_len: dominant-axis voxels per ray segment,
  * 1..1024 (default 8); trace_waves_per_cu: resident waves per compute unit
- * requested for the traversal grid, 1..32 (default 32); traversal: 2 (the
- * traversal described; any other positive value is MAP_E_INVALID).  A field
- * <= 0 keeps the current value. */
+ * requested for the traversal grid, 1..32 (default 32); surface_tile: edge in
+ * pixels of the tiles of the slope / roughness / negative-obstacle pass, 16
+ * or 32 (default 32; other positive values are MAP_E_INVALID).  A field
+ * <= 0 keeps the current value.  The batch autotuner sets all three. */
 typedef struct {
   int32_t seg_len;
   int32_t trace_waves_per_cu;
-  int32_t traversal;
+  int32_t surface_tile;
 } map_tuning_t;
 int32_t map_set_tuning(map_t* m, const map_tuning_t* t);
 int32_t map_get_tuning(const map_t* m, map_tuning_t* out);
@@ -387,7 +388,8 @@ int32_t map_batch_latency(const map_batch_t* b, double* ms);
 int32_t map_batch_set_graph(map_batch_t* b, int32_t enable);
 
 /* Autotuner: times every candidate tuning (seg_len 8/16/32 x
- * trace_waves_per_cu 8/16/32) on this step's inputs with batch steps, applies
+ * trace_waves_per_cu 16/32 x surface_tile 16/32) on this step's inputs with
+ * batch steps, applies
  * the fastest to all maps and appends it to the text cache `cache_path`
  * (NULL: no cache).  A cached entry for the same device, map shapes and
  * point-count range is applied without timing.  The maps are left empty

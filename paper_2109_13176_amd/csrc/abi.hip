@@ -274,6 +274,7 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
   }
   m->seg_len = 8;
   m->trace_wpc = 32;
+  m->surf_tile = 32;
   // traversal blocks (at most 32 waves per CU) + the sensor-box fold blocks
   m->part_trace_cap = (int64_t)m->n_cu * 32 / 4 + gvom::box_fold_blocks() + 1;
   m->d.nx = p->nx;
@@ -720,7 +721,7 @@ int32_t map_export_2d(map_t* m, const map_2d_t* out) {
     gvom::SurfaceArgs sa;
     surface_args(m, out, &sa);
     pm = prof_begin(m, MAP_PROF_SURFACE);
-    e = gvom::launch_surface(sa, m->stream);
+    e = gvom::launch_surface(sa, m->surf_tile, m->stream);
     prof_end(m, pm);
   }
   return dev_status(m, e);
@@ -872,10 +873,12 @@ int32_t map_sync(map_t* m) {
 int32_t map_set_tuning(map_t* m, const map_tuning_t* t) {
   if (!m || !t) return MAP_E_INVALID;
   if (t->seg_len > 1024 || t->trace_waves_per_cu > 32) return MAP_E_INVALID;
-  if (!(t->traversal <= 0 || t->traversal == 2)) return MAP_E_INVALID;
+  if (!(t->surface_tile <= 0 || t->surface_tile == 16 || t->surface_tile == 32))
+    return MAP_E_INVALID;
   // the wave-item buffer is sized for the segment length at the next insert
   if (t->seg_len > 0) m->seg_len = t->seg_len;
   if (t->trace_waves_per_cu > 0) m->trace_wpc = t->trace_waves_per_cu;
+  if (t->surface_tile > 0) m->surf_tile = t->surface_tile;
   return MAP_OK;
 }
 
@@ -883,7 +886,7 @@ int32_t map_get_tuning(const map_t* m, map_tuning_t* out) {
   if (!m || !out) return MAP_E_INVALID;
   out->seg_len = m->seg_len;
   out->trace_waves_per_cu = m->trace_wpc;
-  out->traversal = 2;
+  out->surface_tile = m->surf_tile;
   return MAP_OK;
 }
 
@@ -957,9 +960,8 @@ int32_t batch_prepare(map_batch_t* b, const float* const* xyz_dev, const int64_t
   gvom::BatchTables* t = b->htab;
   gvom::BatchStep& st = t->st;
   st.nmaps = b->k;
-  st.pre_rays[0] = st.pre_trace[0] = st.pre_col[0] = st.pre_surf[0] = 0;
+  st.pre_rays[0] = st.pre_trace[0] = st.pre_col[0] = st.pre_surf[0][0] = st.pre_surf[1][0] = 0;
   st.pre_lcount[0] = st.pre_lscan[0] = st.pre_lwrite[0] = 0;
-  const int tile = gvom::surface_tile();
   for (int i = 0; i < b->k; i++) {
     map_t* m = b->maps[i];
     bool full = false;
@@ -978,6 +980,7 @@ int32_t batch_prepare(map_batch_t* b, const float* const* xyz_dev, const int64_t
     }
     const int64_t C = (int64_t)m->p.nx * m->p.ny;
     const int ray_blocks = (int)((n[i] + gvom::kRayBlock - 1) / gvom::kRayBlock);
+    const int tile = m->surf_tile, ti = tile == 16 ? 0 : 1;
     const int tiles_y = (m->p.ny + tile - 1) / tile;
     const int tiles = ((m->p.nx + tile - 1) / tile) * tiles_y;
     const int lw_by = (m->d.nby + 3) / 4;
@@ -985,7 +988,8 @@ int32_t batch_prepare(map_batch_t* b, const float* const* xyz_dev, const int64_t
     st.pre_rays[i + 1] = st.pre_rays[i] + (n[i] > 0 ? ray_blocks : 0);
     st.pre_trace[i + 1] = st.pre_trace[i] + t->ins[i].trace_blocks;
     st.pre_col[i + 1] = st.pre_col[i] + (int)((C + 255) / 256);
-    st.pre_surf[i + 1] = st.pre_surf[i] + tiles;
+    st.pre_surf[ti][i + 1] = st.pre_surf[ti][i] + tiles;
+    st.pre_surf[1 - ti][i + 1] = st.pre_surf[1 - ti][i];
     st.pre_lcount[i + 1] = st.pre_lcount[i] + (lut ? (int)((C + 255) / 256) : 0);
     st.pre_lscan[i + 1] = st.pre_lscan[i] + (lut ? 1 : 0);
     st.pre_lwrite[i + 1] = st.pre_lwrite[i] + (lut ? lw : 0);
@@ -1100,14 +1104,16 @@ int32_t map_batch_create(map_t* const* maps, int32_t k, void* stream, map_batch_
   for (int i = 0; i < k; i++) {
     const map_t* m = maps[i];
     const int H = m->c.search_d > m->c.half_fit ? m->c.search_d : m->c.half_fit;
-    const size_t s1 = gvom::surface_lds(H), s2 = gvom::lut_lds(m->p.nz);
+    // either tile size (the maps' tuning may change before a step)
+    const size_t s32 = gvom::surface_lds(H, 32), s16 = gvom::surface_lds(H, 16);
+    const size_t s1 = s32 > s16 ? s32 : s16, s2 = gvom::lut_lds(m->p.nz);
     surf = s1 > surf ? s1 : surf;
     lut = s2 > lut ? s2 : lut;
   }
   const int cu = b->n_cu;
   // persistent grids; the bandwidth-bound column and table passes get eight
   // blocks per CU (the table pass's LDS regions allow it)
-  b->grid = gvom::BatchGrid{cu * 4, cu * 8, cu * 8, cu * 8, cu * 2, cu * 4, cu * 8,
+  b->grid = gvom::BatchGrid{cu * 4, cu * 8, cu * 8, cu * 8, cu * 2, cu * 8, cu * 4, cu * 8,
                             k * gvom::box_fold_blocks(), surf, lut};
   hipError_t e = gvom::dev_alloc((void**)&b->dtab, sizeof(gvom::BatchTables));
   if (e == hipSuccess) e = hipHostMalloc((void**)&b->htab, sizeof(gvom::BatchTables), 0);
@@ -1193,10 +1199,11 @@ int32_t map_batch_autotune(map_batch_t* b, const float* const* xyz_dev, const in
       char line[8192];
       while (fgets(line, sizeof(line), f)) {
         char k2[8000];
-        int a = 0, w = 0;
-        if (sscanf(line, "%7999s %d %d", k2, &a, &w) == 3 && key == k2) {
+        int a = 0, w = 0, tl = 0;
+        if (sscanf(line, "%7999s %d %d %d", k2, &a, &w, &tl) == 4 && key == k2) {
           best.seg_len = a;
           best.trace_waves_per_cu = w;
+          best.surface_tile = tl;
           cached = true;
         }
       }
@@ -1204,13 +1211,15 @@ int32_t map_batch_autotune(map_batch_t* b, const float* const* xyz_dev, const in
     }
   }
   if (!cached) {
-    const int segs[3] = {8, 16, 32}, wpcs[3] = {8, 16, 32};
+    // segment length x traversal waves per CU x surface tile
+    const int segs[3] = {8, 16, 32}, wpcs[2] = {16, 32}, tiles[2] = {16, 32};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MAP_E_DEVICE;
     float best_ms = 1e30f;
     for (int si = 0; si < 3; si++)
-      for (int wi = 0; wi < 3; wi++) {
-        const map_tuning_t t{segs[si], wpcs[wi], 0};
+      for (int wi = 0; wi < 2; wi++)
+        for (int ti = 0; ti < 2; ti++) {
+        const map_tuning_t t{segs[si], wpcs[wi], tiles[ti]};
         for (int i = 0; i < b->k; i++) map_set_tuning(b->maps[i], &t);
         float tot = 0.0f;
         for (int rep = 0; rep < 3; rep++) {
@@ -1232,12 +1241,13 @@ int32_t map_batch_autotune(map_batch_t* b, const float* const* xyz_dev, const in
           best_ms = tot;
           best = t;
         }
-      }
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (cache_path) {
       if (FILE* f = fopen(cache_path, "a")) {
-        fprintf(f, "%s %d %d\n", key.c_str(), best.seg_len, best.trace_waves_per_cu);
+        fprintf(f, "%s %d %d %d\n", key.c_str(), best.seg_len, best.trace_waves_per_cu,
+                best.surface_tile);
         fclose(f);
       }
     }

@@ -1,7 +1,7 @@
 // Roofline calibration kernels: the two reference rates the measurements of
 // the mapping kernels are priced against on the device at hand.
 //
-//  * k_copy_bw: a plain device copy (16-byte loads and stores, grid-stride),
+//  * k_copy_bw: a plain device copy (16-byte streaming loads and stores),
 //    the practical HBM rate and the scale for the FETCH_SIZE / WRITE_SIZE
 //    counters (what they read for a copy of known size).
 //  * k_atomic_peak: device-scope int32 atomic adds without return on
@@ -17,19 +17,21 @@
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_copy_bw(int4* __restrict__ dst,
-                                                 const int4* __restrict__ src, int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // four independent 16-byte loads in flight per lane
-  for (; i + 3 * stride < n; i += 4 * stride) {
-    const int4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-    dst[i] = a;
-    dst[i + stride] = b;
-    dst[i + 2 * stride] = c;
-    dst[i + 3 * stride] = d;
-  }
-  for (; i < n; i += stride) dst[i] = src[i];
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// Block b copies the 1,024 16-byte elements 1024 b .. 1024 b + 1023: each
+// lane loads four (256 apart) before it stores them, streaming (non-temporal)
+// both ways.  This measured faster on the MI355X than grid-stride loops.
+__global__ __launch_bounds__(256) void k_copy_bw(v4i* __restrict__ dst,
+                                                 const v4i* __restrict__ src, int64_t n) {
+  const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  v4i v[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+    if (base + 256 * k < n) v[k] = __builtin_nontemporal_load(&src[base + 256 * k]);
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+    if (base + 256 * k < n) __builtin_nontemporal_store(v[k], &dst[base + 256 * k]);
 }
 
 // 32-bit mixing function (the finaliser of MurmurHash3 by Austin Appleby).
@@ -68,17 +70,10 @@ int32_t map_calib_copy(void* dst_dev, const void* src_dev, int64_t bytes, void* 
     return MAP_E_INVALID;
   if (bytes == 0) return MAP_OK;
   const int64_t n = bytes >> 4;
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-    (void)hipGetLastError();
-    return MAP_E_DEVICE;
-  }
-  int64_t blocks = (n + 255) / 256;
-  const int64_t cap = (int64_t)cus * 16;
-  if (blocks > cap) blocks = cap;
+  const int64_t blocks = (n + 1023) / 1024;
+  if (blocks > 0x7FFFFFFF) return MAP_E_INVALID;
   hipLaunchKernelGGL(k_copy_bw, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
-                     (int4*)dst_dev, (const int4*)src_dev, n);
+                     (v4i*)dst_dev, (const v4i*)src_dev, n);
   if (hipGetLastError() != hipSuccess) return MAP_E_DEVICE;
   return MAP_OK;
 }

@@ -86,6 +86,7 @@ struct InsertArgs {
   int32_t* box_rep;            // [kBoxReps][kBoxCells], zero between inserts
 };
 
+constexpr int kBlock = 256;       // threads per block of the plain kernels
 constexpr int kRayBlock = 256;    // threads per block of the ray pass
 // threads per block of the single-map traversal: eight waves share one LDS
 // copy of the sensor box (the batched traversal uses 256-thread blocks)
@@ -93,6 +94,8 @@ constexpr int kTraceBlock = 512;
 
 // Blocks of the sensor-box fold that follows the segmented traversal.
 int box_fold_blocks();
+// Replica groups of the fold (each fold block sums one group of replicas).
+int box_fold_groups();
 
 // Segments one ray can produce at most.
 int64_t max_segments(const Dims& d, int32_t seg_len);
@@ -173,13 +176,15 @@ constexpr int kMaxBatch = 64;
 
 // Per-step table of a batch: virtual-block prefixes of every stage (block b of
 // stage S belongs to the map m with pre[m] <= b < pre[m+1]) and per-map
-// launch constants.  Lives in device memory, uploaded once per step.
+// launch constants.  Lives in device memory, uploaded once per step.  The
+// surface pass has one prefix per tile size (index 0: 16, 1: 32); a map has
+// blocks only in the prefix of its own tile.
 struct BatchStep {
   int32_t nmaps;
   int32_t pre_rays[kMaxBatch + 1];
   int32_t pre_trace[kMaxBatch + 1];
   int32_t pre_col[kMaxBatch + 1];
-  int32_t pre_surf[kMaxBatch + 1];
+  int32_t pre_surf[2][kMaxBatch + 1];
   int32_t pre_lcount[kMaxBatch + 1];
   int32_t pre_lscan[kMaxBatch + 1];
   int32_t pre_lwrite[kMaxBatch + 1];
@@ -201,8 +206,8 @@ struct BatchTables {
 };
 
 struct BatchGrid {
-  int clear, rays, trace, col, surf, lcount, lwrite;  // persistent grid sizes
-  int fold;                                            // maps x sensor-box fold blocks
+  int clear, rays, trace, col, surf, surf16, lcount, lwrite;  // persistent grid sizes
+  int fold;                                                   // maps x sensor-box fold blocks
   size_t surf_lds, lut_lds;
 };
 
@@ -214,7 +219,7 @@ hipError_t launch_batch_insert(const BatchTables* tab, const BatchGrid& g,
 hipError_t launch_batch_export(const BatchTables* tab, const BatchGrid& g,
                                unsigned long long* stamps, hipStream_t s);
 int surface_tile();
-size_t surface_lds(int H);
+size_t surface_lds(int H, int tile);
 size_t lut_lds(int nz);
 uint32_t nz_magic(int nz);
 
@@ -223,7 +228,7 @@ hipError_t launch_clear(const ClearArgs& a, hipStream_t s);
 hipError_t launch_rays(const InsertArgs& a, bool distinct, hipStream_t s);
 hipError_t launch_trace(const InsertArgs& a, bool distinct, hipStream_t s);
 hipError_t launch_column(const ColumnArgs& a, hipStream_t s);
-hipError_t launch_surface(const SurfaceArgs& a, hipStream_t s);
+hipError_t launch_surface(const SurfaceArgs& a, int tile, hipStream_t s);  // tile 16 or 32
 // counted: the column pass already wrote colpre / block_base for this state
 hipError_t launch_lut(const LutArgs& a, bool counted, hipStream_t s);
 hipError_t launch_import(const Dims& d, const int32_t* lut, const map_voxel_t* data,

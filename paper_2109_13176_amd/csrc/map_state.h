@@ -33,6 +33,7 @@ struct map_t {
   int64_t last_ray_blocks, last_trace_blocks;
   int32_t seg_len;
   int32_t trace_wpc;
+  int32_t surf_tile;           // 16 or 32
   int32_t* box_rep;           // sensor-box replicas of the segmented traversal
   int32_t n_cu;
   int32_t sticky;

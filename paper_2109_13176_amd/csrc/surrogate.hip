@@ -664,61 +664,83 @@ __global__ __launch_bounds__(TR * 64) void k_bwd_weight_mfma(const uint16_t* __r
   if (threadIdx.x < CO) out[NW + threadIdx.x] = sbias[threadIdx.x];
 }
 
-// Weight and bias gradient partials of the 2-channel output layer, one per
-// 16 x 16 pixel tile: thread t takes input channel t % 32 and the 32 pixels
-// of group t / 32, and the 8 groups are summed in LDS in group order.
+// Weight (and bias) gradient of the 32 -> 2 output layer:
+// dW[co][tap][ci] = sum over pixels p of dz[p][co] x[p + off(tap)][ci].  A
+// half-wave (32 lanes, lane = input channel) sweeps one image row over a
+// chunk of kWoCols columns, keeping the 3 x 3 neighbourhood of its channel in
+// registers (three new loads per pixel, 64 contiguous bytes across the
+// lanes) and the 18 sums of its channel; the block's eight half-waves are
+// added in a fixed order into one partial per block (bias: lane 0 sums dz),
+// so the result is reproducible.  Partial b covers units 8 b .. 8 b + 7
+// (unit = row x column chunk).
+constexpr int kWoCols = 64;
+
 __global__ __launch_bounds__(256) void k_bwd_weight_out(const float* __restrict__ dz,
                                                         const uint16_t* __restrict__ x,
                                                         float* __restrict__ part, int H, int W) {
   constexpr int CIN = 32, COUT = 2, NW = COUT * CIN * 9;
-  __shared__ float sdz[256 * COUT];
-  __shared__ float sx[18 * 18 * CIN];
-  __shared__ float red[8][NW];
-  const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
-  for (int i = threadIdx.x; i < 256 * COUT; i += 256) {
-    const int pix = i / COUT, co = i - pix * COUT;
-    const int gr = r0 + pix / 16, gc = c0 + pix % 16;
-    sdz[i] = (gr < H && gc < W) ? dz[((int64_t)gr * W + gc) * COUT + co] : 0.0f;
-  }
-  for (int i = threadIdx.x; i < 18 * 18 * CIN; i += 256) {
-    const int pix = i / CIN, ci = i - pix * CIN;
-    const int gr = r0 + pix / 18 - 1, gc = c0 + pix % 18 - 1;
-    sx[i] = (gr >= 0 && gr < H && gc >= 0 && gc < W) ? from_bf16(x[((int64_t)gr * W + gc) * CIN + ci]) : 0.0f;
-  }
-  __syncthreads();
-  const int ci = threadIdx.x & 31, pg = threadIdx.x >> 5;
+  __shared__ float red[8][NW + COUT];
+  const int ci = threadIdx.x & 31, hw = threadIdx.x >> 5;
+  const int chunks = (W + kWoCols - 1) / kWoCols;
+  const int unit = blockIdx.x * 8 + hw;
   float acc[COUT][9];
 #pragma unroll
   for (int c = 0; c < COUT; c++)
 #pragma unroll
-    for (int t = 0; t < 9; t++) acc[c][t] = 0.0f;
-  for (int p = pg * 32; p < pg * 32 + 32; p++) {
-    const int pr = p / 16, pc = p % 16;
-    const float d0 = sdz[p * COUT], d1 = sdz[p * COUT + 1];
+    for (int k = 0; k < 9; k++) acc[c][k] = 0.0f;
+  float bsum[COUT] = {0.0f, 0.0f};
+  if (unit < H * chunks) {
+    const int r = unit / chunks, c0 = (unit - r * chunks) * kWoCols;
+    const int c1 = min(c0 + kWoCols, W);
+    auto ld = [&](int rr, int cc) -> float {
+      return (rr >= 0 && rr < H && cc >= 0 && cc < W)
+                 ? from_bf16(x[((int64_t)rr * W + cc) * CIN + ci])
+                 : 0.0f;
+    };
+    // win[dy][dx] = x[r + dy - 1][c + dx - 1][ci] for the current pixel c
+    float win[3][3];
 #pragma unroll
-    for (int t = 0; t < 9; t++) {
-      const float xv = sx[((pr + t / 3) * 18 + pc + t % 3) * CIN + ci];
-      acc[0][t] = __builtin_fmaf(d0, xv, acc[0][t]);
-      acc[1][t] = __builtin_fmaf(d1, xv, acc[1][t]);
+    for (int dy = 0; dy < 3; dy++) {
+      win[dy][0] = ld(r + dy - 1, c0 - 1);
+      win[dy][1] = ld(r + dy - 1, c0);
+    }
+    for (int c = c0; c < c1; c++) {
+#pragma unroll
+      for (int dy = 0; dy < 3; dy++) win[dy][2] = ld(r + dy - 1, c + 1);
+      const float d0 = dz[((int64_t)r * W + c) * COUT];
+      const float d1 = dz[((int64_t)r * W + c) * COUT + 1];
+#pragma unroll
+      for (int k = 0; k < 9; k++) {
+        acc[0][k] = __builtin_fmaf(d0, win[k / 3][k % 3], acc[0][k]);
+        acc[1][k] = __builtin_fmaf(d1, win[k / 3][k % 3], acc[1][k]);
+      }
+      bsum[0] += d0;
+      bsum[1] += d1;
+#pragma unroll
+      for (int dy = 0; dy < 3; dy++) {
+        win[dy][0] = win[dy][1];
+        win[dy][1] = win[dy][2];
+      }
     }
   }
 #pragma unroll
   for (int c = 0; c < COUT; c++)
 #pragma unroll
-    for (int t = 0; t < 9; t++) red[pg][(c * CIN + ci) * 9 + t] = acc[c][t];
+    for (int k = 0; k < 9; k++) red[hw][(c * CIN + ci) * 9 + k] = acc[c][k];
+  if (ci == 0) {
+    red[hw][NW] = bsum[0];
+    red[hw][NW + 1] = bsum[1];
+  }
   __syncthreads();
-  float* out = part + (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * (NW + COUT);
-  for (int i = threadIdx.x; i < NW; i += 256) {
+  float* out = part + (int64_t)blockIdx.x * (NW + COUT);
+  for (int i = threadIdx.x; i < NW + COUT; i += 256) {
     float sum = 0.0f;
     for (int g = 0; g < 8; g++) sum += red[g][i];
     out[i] = sum;
   }
-  if (threadIdx.x < COUT) {
-    float b = 0.0f;
-    for (int p = 0; p < 256; p++) b += sdz[p * COUT + threadIdx.x];
-    out[NW + threadIdx.x] = b;
-  }
 }
+
+int wo_blocks(int H, int W) { return (H * ((W + kWoCols - 1) / kWoCols) + 7) / 8; }
 
 // Two-stage fixed-order (deterministic) reduction of the weight-gradient
 // partials: stage 1 sums groups of kRedGroup consecutive tiles per parameter
@@ -906,6 +928,7 @@ int32_t sgt_create(int32_t H, int32_t W, uint64_t seed, void* stream, sgt_net_t*
   n->part_blocks = ((W + 15) / 16) * ((H + 15) / 16);
   const int mfma_blocks = ((W + kTC - 1) / kTC) * ((H + 3) / 4);
   if (mfma_blocks > n->part_blocks) n->part_blocks = mfma_blocks;
+  if (wo_blocks(H, W) > n->part_blocks) n->part_blocks = wo_blocks(H, W);
   int64_t maxlp = 0;
   for (int l = 0; l < kNL; l++) maxlp = layer_params(l) > maxlp ? layer_params(l) : maxlp;
   hipError_t e = hipSuccess;
@@ -1102,8 +1125,9 @@ int32_t sgt_loss_grad(sgt_net_t* n, const float* feat_dev, const float* label_de
     // matrix cores (dz of those comes as the bf16 pair of the layer above)
     int nb;
     if (l == 4) {
-      hipLaunchKernelGGL(k_bwd_weight_out, g16, dim3(256), 0, n->stream, dz, n->act[l], n->part, H, W);
-      nb = (int)(g16.x * g16.y);
+      nb = wo_blocks(H, W);
+      hipLaunchKernelGGL(k_bwd_weight_out, dim3(nb), dim3(256), 0, n->stream, dz, n->act[l],
+                         n->part, H, W);
     } else {
       const dim3 gw((W + kTC - 1) / kTC, (H + 3) / 4);
       if (l == 0)

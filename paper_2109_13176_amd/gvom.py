@@ -48,7 +48,7 @@ class map_2d_t(ctypes.Structure):
 
 class map_tuning_t(ctypes.Structure):
     _fields_ = [("seg_len", ctypes.c_int32), ("trace_waves_per_cu", ctypes.c_int32),
-                ("traversal", ctypes.c_int32)]
+                ("surface_tile", ctypes.c_int32)]
 
 
 COST_LAYERS = ("slope", "rough", "density", "positive", "hard", "soft", "negative", "unknown")
@@ -296,16 +296,16 @@ def map_sync(h) -> int:
     return lib().map_sync(h)
 
 
-def map_set_tuning(h, seg_len: int = 0, trace_waves_per_cu: int = 0, traversal: int = 0) -> int:
+def map_set_tuning(h, seg_len: int = 0, trace_waves_per_cu: int = 0, surface_tile: int = 0) -> int:
     return lib().map_set_tuning(h, ctypes.byref(map_tuning_t(seg_len, trace_waves_per_cu,
-                                                             traversal)))
+                                                             surface_tile)))
 
 
 def map_get_tuning(h):
     t = map_tuning_t()
     s = lib().map_get_tuning(h, ctypes.byref(t))
     return s, {"seg_len": t.seg_len, "trace_waves_per_cu": t.trace_waves_per_cu,
-               "traversal": t.traversal}
+               "surface_tile": t.surface_tile}
 
 
 MAP_PROF_ALL = (1 << len(PROF_PHASES)) - 1
@@ -433,7 +433,8 @@ class MapBatch:
                                      ctypes.byref(t))
         if s != MAP_OK:
             raise RuntimeError(f"map_batch_autotune: {map_status_str(s)}")
-        return {"seg_len": t.seg_len, "trace_waves_per_cu": t.trace_waves_per_cu}
+        return {"seg_len": t.seg_len, "trace_waves_per_cu": t.trace_waves_per_cu,
+                "surface_tile": t.surface_tile}
 
 
 class VoxelMap:

@@ -58,6 +58,10 @@ def test_batch_equals_single_maps(graph):
     ps = [params(*sh) for sh in SHAPES]
     bmaps = [gvom.VoxelMap(p) for p in ps]
     smaps = [gvom.VoxelMap(p) for p in ps]
+    # half the batch's maps take the 16-pixel surface tiles (the single maps
+    # keep 32): results must not depend on the tile
+    for i in range(1, len(bmaps), 2):
+        assert gvom.map_set_tuning(bmaps[i].h, surface_tile=16) == 0
     batch = gvom.MapBatch(bmaps)
     batch.set_graph(graph)
     try:
@@ -123,7 +127,8 @@ def test_autotune_cache_and_results_unchanged():
     with tempfile.TemporaryDirectory() as d:
         cache = os.path.join(d, "tune.txt")
         t1 = batch.autotune(xyzs, poses, flags, cache)
-        assert t1["seg_len"] in (8, 16, 32) and t1["trace_waves_per_cu"] in (8, 16, 32)
+        assert t1["seg_len"] in (8, 16, 32) and t1["trace_waves_per_cu"] in (16, 32)
+        assert t1["surface_tile"] in (16, 32)
         assert os.path.exists(cache) and open(cache).read().count("\n") == 1
         t2 = batch.autotune(xyzs, poses, flags, cache)  # served from the cache
         assert t2 == t1 and open(cache).read().count("\n") == 1

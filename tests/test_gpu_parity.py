@@ -305,18 +305,20 @@ def _state(m):
 
 @pytest.mark.parametrize("distinct", [False, True])
 def test_tunings_bit_identical(distinct):
-    """Results do not depend on the launch tuning: the default traversal
-    (segments of 8 voxels, 32 waves per CU) and a different one (segments of
-    32 voxels, 8 waves per CU, so other waves share line tables and other
-    blocks share the sensor box) give the same map bit for bit: four scans of
+    """Results do not depend on the launch tuning: the default (segments of
+    8 voxels, 32 waves per CU, 32-pixel surface tiles) and a different one
+    (segments of 32 voxels, 8 waves per CU, so other waves share line tables
+    and other blocks share the sensor box; 16-pixel surface tiles on
+    256-thread blocks) give the same map bit for bit: four scans of
     the 64-beam sequence on the 512 x 512 x 64 window (recentred each scan, so
     the storage offsets move), then a cloud of steep rays."""
     from paper_2109_13176_amd import gvom
     seq = scenegen.sequence_64beam(seed=2, n_sim=4, device="cuda")
     maps = [gvom.VoxelMap(seq["params"]) for _ in range(2)]
-    assert gvom.map_set_tuning(maps[1].h, seg_len=32, trace_waves_per_cu=8) == 0
+    assert gvom.map_set_tuning(maps[1].h, seg_len=32, trace_waves_per_cu=8, surface_tile=16) == 0
     assert gvom.map_get_tuning(maps[1].h)[1]["seg_len"] == 32
-    assert gvom.map_set_tuning(maps[1].h, traversal=1) == gvom.MAP_E_INVALID
+    assert gvom.map_get_tuning(maps[1].h)[1]["surface_tile"] == 16
+    assert gvom.map_set_tuning(maps[1].h, surface_tile=24) == gvom.MAP_E_INVALID
     rng = np.random.default_rng(3)
     steep = _cloud(rng, 20000, 30.0)
     steep[:, 2] *= 3.0
