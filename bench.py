@@ -28,7 +28,8 @@ HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2109_13176_amd", "csrc")
 # sources of the traversal kernel (k_trace) whose counters are committed
-TRACE_SRCS = [os.path.join(CSRC, f) for f in ("insert.hip", "ray_common.h", "gvom_internal.h")]
+TRACE_SRCS = [os.path.join(CSRC, f)
+              for f in ("insert.hip", "insert_body.h", "ray_common.h", "gvom_internal.h")]
 
 
 def log(*a):

@@ -666,14 +666,14 @@ __global__ __launch_bounds__(TR * 64) void k_bwd_weight_mfma(const uint16_t* __r
 
 // Weight (and bias) gradient of the 32 -> 2 output layer:
 // dW[co][tap][ci] = sum over pixels p of dz[p][co] x[p + off(tap)][ci].  A
-// half-wave (32 lanes, lane = input channel) sweeps one image row over a
-// chunk of kWoCols columns, keeping the 3 x 3 neighbourhood of its channel in
-// registers (three new loads per pixel, 64 contiguous bytes across the
-// lanes) and the 18 sums of its channel; the block's eight half-waves are
-// added in a fixed order into one partial per block (bias: lane 0 sums dz),
-// so the result is reproducible.  Partial b covers units 8 b .. 8 b + 7
-// (unit = row x column chunk).
-constexpr int kWoCols = 64;
+// half-wave (32 lanes, lane = input channel) takes kWoCols pixels of one
+// image row: it loads the 3 x (kWoCols + 2) input values of its channel
+// (64 contiguous bytes across the lanes per value) and the pixels' dz at
+// once, then adds up the 18 sums of its channel in column order; the block's
+// eight half-waves are added in a fixed order into one partial per block
+// (bias: lane 0 sums dz), so the result is reproducible.  Partial b covers
+// units 8 b .. 8 b + 7 (unit = row x column chunk).
+constexpr int kWoCols = 16;
 
 __global__ __launch_bounds__(256) void k_bwd_weight_out(const float* __restrict__ dz,
                                                         const uint16_t* __restrict__ x,
@@ -691,36 +691,34 @@ __global__ __launch_bounds__(256) void k_bwd_weight_out(const float* __restrict_
   float bsum[COUT] = {0.0f, 0.0f};
   if (unit < H * chunks) {
     const int r = unit / chunks, c0 = (unit - r * chunks) * kWoCols;
-    const int c1 = min(c0 + kWoCols, W);
     auto ld = [&](int rr, int cc) -> float {
       return (rr >= 0 && rr < H && cc >= 0 && cc < W)
                  ? from_bf16(x[((int64_t)rr * W + cc) * CIN + ci])
                  : 0.0f;
     };
-    // win[dy][dx] = x[r + dy - 1][c + dx - 1][ci] for the current pixel c
-    float win[3][3];
+    // the chunk's 3 x (kWoCols + 2) input values and its dz, loaded up front
+    // (independent loads in flight), then the sums in column order
+    float xv[3][kWoCols + 2];
+    float d[kWoCols][COUT];
 #pragma unroll
-    for (int dy = 0; dy < 3; dy++) {
-      win[dy][0] = ld(r + dy - 1, c0 - 1);
-      win[dy][1] = ld(r + dy - 1, c0);
+    for (int dy = 0; dy < 3; dy++)
+#pragma unroll
+      for (int j = 0; j < kWoCols + 2; j++) xv[dy][j] = ld(r + dy - 1, c0 + j - 1);
+#pragma unroll
+    for (int j = 0; j < kWoCols; j++) {
+      const bool ok = c0 + j < W;
+      d[j][0] = ok ? dz[((int64_t)r * W + c0 + j) * COUT] : 0.0f;
+      d[j][1] = ok ? dz[((int64_t)r * W + c0 + j) * COUT + 1] : 0.0f;
     }
-    for (int c = c0; c < c1; c++) {
 #pragma unroll
-      for (int dy = 0; dy < 3; dy++) win[dy][2] = ld(r + dy - 1, c + 1);
-      const float d0 = dz[((int64_t)r * W + c) * COUT];
-      const float d1 = dz[((int64_t)r * W + c) * COUT + 1];
+    for (int j = 0; j < kWoCols; j++) {
 #pragma unroll
       for (int k = 0; k < 9; k++) {
-        acc[0][k] = __builtin_fmaf(d0, win[k / 3][k % 3], acc[0][k]);
-        acc[1][k] = __builtin_fmaf(d1, win[k / 3][k % 3], acc[1][k]);
+        acc[0][k] = __builtin_fmaf(d[j][0], xv[k / 3][j + k % 3], acc[0][k]);
+        acc[1][k] = __builtin_fmaf(d[j][1], xv[k / 3][j + k % 3], acc[1][k]);
       }
-      bsum[0] += d0;
-      bsum[1] += d1;
-#pragma unroll
-      for (int dy = 0; dy < 3; dy++) {
-        win[dy][0] = win[dy][1];
-        win[dy][1] = win[dy][2];
-      }
+      bsum[0] += d[j][0];
+      bsum[1] += d[j][1];
     }
   }
 #pragma unroll
