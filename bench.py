@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "lidar points/sec ingested + map updates/sec (64-beam, 512x512x64) on 1 MI355X"
 HBM_PEAK_GBS = 8000.0
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions/s (non-packed)
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2109_13176_amd", "csrc")
 # sources of the traversal kernel (k_trace) whose counters are committed
@@ -95,6 +96,16 @@ def measured_traffic():
     if not s or s.get("kernel sources sha256[:16]") != source_sha(TRACE_SRCS):
         return None
     return float(s["hbm bytes per launch"])
+
+
+def measured_valu():
+    """VALU wave-instructions per launch of the traversal kernel from the
+    committed SQ counter summary, or None when the kernel source changed
+    since the counters were taken."""
+    s = read_summary("trace_seq64_instructions.txt")
+    if not s or s.get("kernel sources sha256[:16]") != source_sha(TRACE_SRCS):
+        return None
+    return float(s["k_trace<false> SQ_INSTS_VALU"])
 
 
 def calibrate():
@@ -589,6 +600,13 @@ def bench_main(args, baseline):
                            "line_requests_per_launch": lr,
                            "updates_per_launch": avg["n_pass_updates"],
                            "updates_per_s": avg["n_pass_updates"] / t_tr}
+        # co-reported issue roofline: the walk is bound by VALU issue; a wave64
+        # VALU instruction takes a 16-lane SIMD 4 cycles, 1024 SIMDs at 2.4 GHz
+        valu = measured_valu()
+        roof["valu_issue"] = {"achieved": valu / t_tr if valu else None, "peak": VALU_ISSUE_PEAK,
+                              "unit": "wave instructions/s",
+                              "frac": valu / t_tr / VALU_ISSUE_PEAK if valu else None,
+                              "valu_per_launch": valu}
 
     # whole-path HBM fractions with the counted minimum bytes: the ray cast
     # moves 12 N + 16 U_h + 8 U_p, the exports 4 V (table) + 12 M + 17 C
