@@ -254,12 +254,14 @@ int32_t map_sync(map_t* m);
 
 /* Launch tuning (performance only: results are bit-identical for every
  * setting).  The traversal cuts every ray every seg_len dominant-axis voxels;
- * a wave takes one segment index of 64 neighbouring rays, counts its passes
- * in an LDS table of 64-byte map lines and adds each line to the map with one
- * request; the passes of a 17 x 17 x 9 box around the sensor are summed per
- * block on chip first.  seg_len: dominant-axis voxels per ray segment,
- * 1..1024 (default 8); trace_waves_per_cu: resident waves per compute unit
- * requested for the traversal grid, 1..32 (default 32); surface_tile: edge in
+ * a wave takes one segment index of 64 rays of one ray-pass block (the block
+ * groups its rays by segment count), counts its passes in an LDS table of
+ * 64-byte map lines and adds each line to the map with one request; the
+ * passes of a 17 x 17 x 9 box around the sensor are summed per block on chip
+ * first.  seg_len: dominant-axis voxels per ray segment, 1..1024 (default 8);
+ * trace_waves_per_cu: resident waves per compute unit requested for the
+ * traversal grid (blocks of four waves), 1..32 (default 28, the most that fit
+ * a compute unit); surface_tile: edge in
  * pixels of the tiles of the slope / roughness / negative-obstacle pass, 16
  * or 32 (default 32; other positive values are MAP_E_INVALID).  A field
  * <= 0 keeps the current value.  The batch autotuner sets all three. */
@@ -387,8 +389,8 @@ int32_t map_batch_latency(const map_batch_t* b, double* ms);
 /* Graph replay on (default) or off (plain stream launches of the same kernels). */
 int32_t map_batch_set_graph(map_batch_t* b, int32_t enable);
 
-/* Autotuner: times every candidate tuning (seg_len 8/16/32 x
- * trace_waves_per_cu 16/32 x surface_tile 16/32) on this step's inputs with
+/* Autotuner: times every candidate tuning (seg_len 6/8/16 x
+ * trace_waves_per_cu 16/28 x surface_tile 16/32) on this step's inputs with
  * batch steps, applies
  * the fastest to all maps and appends it to the text cache `cache_path`
  * (NULL: no cache).  A cached entry for the same device, map shapes and

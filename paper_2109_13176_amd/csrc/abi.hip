@@ -273,7 +273,7 @@ int32_t map_create(const map_params_t* p, void* stream, map_t** out) {
     return MAP_E_DEVICE;
   }
   m->seg_len = 8;
-  m->trace_wpc = 32;
+  m->trace_wpc = 28;
   m->surf_tile = 32;
   // traversal blocks (at most 32 waves per CU) + the sensor-box fold blocks
   m->part_trace_cap = (int64_t)m->n_cu * 32 / 4 + gvom::box_fold_blocks() + 1;
@@ -444,7 +444,7 @@ void insert_layout(const map_t* m, int64_t ray_blocks, gvom::InsertArgs* a, int6
 // a->part_rays, set by the caller).
 int32_t fill_insert(map_t* m, const float* xyz_dev, int64_t n, const float* pose,
                     uint32_t flags, const int32_t S[3], gvom::InsertArgs* a,
-                    gvom::ClearArgs* plan, bool* full, bool single, int64_t need) {
+                    gvom::ClearArgs* plan, bool* full, int64_t need) {
   const int64_t ray_blocks = (n + gvom::kRayBlock - 1) / gvom::kRayBlock;
   *full = false;
   plan->nbox = 0;
@@ -481,7 +481,7 @@ int32_t fill_insert(map_t* m, const float* xyz_dev, int64_t n, const float* pose
   a->touch = m->touch;
   a->part_trace = m->part_trace;
   a->seg_len = m->seg_len;
-  const int64_t tpb = single ? gvom::kTraceBlock : 256;  // threads per traversal block
+  const int64_t tpb = gvom::kTraceBlock;  // threads per traversal block
   const int64_t want = (need + tpb / 64 - 1) / (tpb / 64);  // one wave per item
   int64_t lim = (int64_t)m->n_cu * m->trace_wpc / (tpb / 64);
   if (lim < 1) lim = 1;
@@ -507,11 +507,10 @@ int32_t fill_insert(map_t* m, const float* xyz_dev, int64_t n, const float* pose
 
 // Second half of an insert (after check_insert): grows the per-scan buffers,
 // moves the window (the slab clears go to `plan`; *full = whole window), and
-// fills the kernel arguments.  Updates the host-side map state.  `single`: a
-// single-map insert (512-thread traversal blocks; a batch uses 256).
+// fills the kernel arguments.  Updates the host-side map state.
 int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* pose,
                        uint32_t flags, const int32_t S[3], gvom::InsertArgs* a,
-                       gvom::ClearArgs* plan, bool* full, bool single) {
+                       gvom::ClearArgs* plan, bool* full) {
   const int64_t ray_blocks = (n + gvom::kRayBlock - 1) / gvom::kRayBlock;
   int64_t need = 0;
   insert_layout(m, ray_blocks, a, &need);
@@ -522,7 +521,7 @@ int32_t prepare_insert(map_t* m, const float* xyz_dev, int64_t n, const float* p
   a->rays = m->rays;
   a->witems = m->witems;
   a->part_rays = m->part_rays;
-  return fill_insert(m, xyz_dev, n, pose, flags, S, a, plan, full, single, need);
+  return fill_insert(m, xyz_dev, n, pose, flags, S, a, plan, full, need);
 }
 
 // ranks: also write the table export's per-column ranks (single-map export)
@@ -642,7 +641,7 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
   m->lut_counted = false;
   m->version = gvom::next_version();
   const int pm0 = prof_begin(m, MAP_PROF_SCROLL);
-  st = prepare_insert(m, xyz_dev, n, pose, flags, S, &a, &plan, &full, true);
+  st = prepare_insert(m, xyz_dev, n, pose, flags, S, &a, &plan, &full);
   if (st) return st;
   // an empty map moves its window without clearing anything
   hipError_t e = m->empty ? hipSuccess : full ? clear_all(m) : gvom::launch_clear(plan, m->stream);
@@ -692,7 +691,7 @@ int32_t map_insert_scan_static(map_t* m, const float* xyz_dev, int64_t n, const 
   a.part_rays = (unsigned long long*)base;
   m->lut_counted = false;
   m->version = gvom::next_version();
-  st = fill_insert(m, xyz_dev, n, pose, flags, S, &a, &plan, &full, true, need);
+  st = fill_insert(m, xyz_dev, n, pose, flags, S, &a, &plan, &full, need);
   if (st) return st;
   m->last_static = true;
   // kernels only (no memset, no allocation): callers may capture this call
@@ -966,7 +965,7 @@ int32_t batch_prepare(map_batch_t* b, const float* const* xyz_dev, const int64_t
     map_t* m = b->maps[i];
     bool full = false;
     const int32_t s = prepare_insert(m, xyz_dev[i], n[i], poses + 12 * i, flags[i], S[i],
-                                     &t->ins[i], &t->clr[i], &full, false);
+                                     &t->ins[i], &t->clr[i], &full);
     if (s) return s;  // allocation failure
     column_args(m, &out2d[i], false, &t->col[i]);
     m->lut_counted = false;
@@ -1113,7 +1112,7 @@ int32_t map_batch_create(map_t* const* maps, int32_t k, void* stream, map_batch_
   const int cu = b->n_cu;
   // persistent grids; the bandwidth-bound column and table passes get eight
   // blocks per CU (the table pass's LDS regions allow it)
-  b->grid = gvom::BatchGrid{cu * 4, cu * 8, cu * 8, cu * 8, cu * 2, cu * 8, cu * 4, cu * 8,
+  b->grid = gvom::BatchGrid{cu * 4, cu * 2, cu * 8, cu * 8, cu * 2, cu * 8, cu * 4, cu * 8,
                             k * gvom::box_fold_blocks(), surf, lut};
   hipError_t e = gvom::dev_alloc((void**)&b->dtab, sizeof(gvom::BatchTables));
   if (e == hipSuccess) e = hipHostMalloc((void**)&b->htab, sizeof(gvom::BatchTables), 0);
@@ -1212,7 +1211,7 @@ int32_t map_batch_autotune(map_batch_t* b, const float* const* xyz_dev, const in
   }
   if (!cached) {
     // segment length x traversal waves per CU x surface tile
-    const int segs[3] = {8, 16, 32}, wpcs[2] = {16, 32}, tiles[2] = {16, 32};
+    const int segs[3] = {6, 8, 16}, wpcs[2] = {16, 28}, tiles[2] = {16, 32};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MAP_E_DEVICE;
     float best_ms = 1e30f;

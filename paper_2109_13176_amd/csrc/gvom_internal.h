@@ -87,10 +87,12 @@ struct InsertArgs {
 };
 
 constexpr int kBlock = 256;       // threads per block of the plain kernels
-constexpr int kRayBlock = 256;    // threads per block of the ray pass
-// threads per block of the single-map traversal: eight waves share one LDS
-// copy of the sensor box (the batched traversal uses 256-thread blocks)
-constexpr int kTraceBlock = 512;
+constexpr int kRayBlock = 512;    // threads per block of the ray pass (rays regrouped per block)
+// threads per block of the traversal (single map and batch): four waves
+// share one LDS copy of the sensor box; small blocks let seven of them fit a
+// CU (LDS and registers), and the walk is bound by per-wave latency
+constexpr int kTraceBlock = 256;
+constexpr int kTraceWavesPerSimd = 7;
 
 // Blocks of the sensor-box fold that follows the segmented traversal.
 int box_fold_blocks();

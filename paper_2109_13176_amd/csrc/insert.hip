@@ -17,7 +17,7 @@ __global__ __launch_bounds__(kRayBlock) void k_rays(InsertArgs a) {
 }
 
 template <bool DISTINCT>
-__global__ __launch_bounds__(kTraceBlock) void k_trace(InsertArgs a) {
+__global__ __launch_bounds__(kTraceBlock, kTraceWavesPerSimd) void k_trace(InsertArgs a) {
   __shared__ int32_t box_cnt[kBoxCells];
   __shared__ WaveTable wtab[kTraceBlock / 64];
   trace_body<DISTINCT, true, kTraceBlock>(a, blockIdx.x, gridDim.x, box_cnt, wtab);
@@ -65,15 +65,16 @@ __global__ __launch_bounds__(kRayBlock) void k_b_rays(const BatchTables* __restr
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_b_trace(const BatchTables* __restrict__ t) {
+__global__ __launch_bounds__(kTraceBlock, kTraceWavesPerSimd) void k_b_trace(
+    const BatchTables* __restrict__ t) {
   __shared__ int32_t box_cnt[kBoxCells];
-  __shared__ WaveTable wtab[kBlock / 64];
+  __shared__ WaveTable wtab[kTraceBlock / 64];
   const int n = t->st.nmaps;
   const int total = t->st.pre_trace[n];
   for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
     const int m = find_map(t->st.pre_trace, n, vb);
-    trace_body<false, true, kBlock>(t->ins[m], vb - t->st.pre_trace[m], t->ins[m].trace_blocks,
-                                    box_cnt, wtab);
+    trace_body<false, true, kTraceBlock>(t->ins[m], vb - t->st.pre_trace[m],
+                                         t->ins[m].trace_blocks, box_cnt, wtab);
     __syncthreads();
   }
 }
@@ -117,7 +118,7 @@ hipError_t launch_batch_insert(const BatchTables* tab, const BatchGrid& g,
                                unsigned long long* stamps, hipStream_t s) {
   hipLaunchKernelGGL(k_b_clear, dim3(g.clear), dim3(kBlock), 0, s, tab, stamps);
   hipLaunchKernelGGL(k_b_rays, dim3(g.rays), dim3(kRayBlock), 0, s, tab);
-  hipLaunchKernelGGL(k_b_trace, dim3(g.trace), dim3(kBlock), 0, s, tab);
+  hipLaunchKernelGGL(k_b_trace, dim3(g.trace), dim3(kTraceBlock), 0, s, tab);
   hipLaunchKernelGGL(k_b_box_fold, dim3(g.fold), dim3(kBlock), 0, s, tab);
   return hipGetLastError();
 }

@@ -21,14 +21,49 @@ namespace {
 // axis with the most voxel steps) the path is cut every seg_len voxels:
 // segment j holds the path voxels whose dominant coordinate lies j*seg_len ..
 // (j+1)*seg_len - 1 voxels from the sensor's.  Only segments that start
-// inside the window along the dominant axis count.  Each lane writes its
-// ray's record {Q, segments}; a wave of 64 neighbouring rays with at most s
-// segments each then publishes s wave items {wave, j}, and a traversal wave
-// takes one item: segment j of those 64 rays, whose voxels share cache lines.
+// inside the window along the dominant axis count.
+//
+// The block then regroups its rays by segment count (most first; rays of
+// equal count keep their order, so neighbouring rays stay together) and
+// writes their records {Q, segments} in that order: a traversal wave holds
+// segment j of 64 rays that all have it, instead of 64 neighbouring rays of
+// which the short ones ended long before j.  Each group of 64 records with at
+// most s segments publishes s wave items {group, j}.
+constexpr int kRayWaves = kRayBlock / 64;
+constexpr int kSegBins = 64;  // segment counts >= kSegBins - 1 share a bin
+static_assert(kSegBins * kRayWaves == kRayBlock, "one scan entry per thread");
+
+// Exclusive prefix sum over the block (one value per thread); wtot is
+// kRayWaves words of the caller's LDS.
+__device__ __forceinline__ int block_excl_scan(int v, int* wtot) {
+  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wtot[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < kRayWaves; w++) {
+      const int c = wtot[w];
+      wtot[w] = s;
+      s += c;
+    }
+  }
+  __syncthreads();
+  return x - v + wtot[wv];
+}
+
 template <bool DISTINCT>
 __device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
-  __shared__ unsigned int wcount[kRayBlock / 64][5];
-  __shared__ unsigned long long wbase[kRayBlock / 64];
+  __shared__ unsigned int wcount[kRayWaves][5];
+  __shared__ unsigned long long wbase[kRayWaves];
+  __shared__ int bin_pre[kSegBins * kRayWaves];  // [bin][wave]: count, then prefix
+  __shared__ int wtot[kRayWaves];
+  __shared__ int4 srec[kRayBlock];
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
   const int i = blk * kRayBlock + threadIdx.x;
   const int32_t dims[3] = {a.d.nx, a.d.ny, a.d.nz};
@@ -47,25 +82,46 @@ __device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
     }
     if (n[0] + n[1] + n[2] > 0) {
       const int dom = dominant_axis(n);
-      const int32_t sv = a.S[dom] >> 16;
-      const int32_t lc = sv - a.O[dom];
-      const int32_t room = q[dom] > a.S[dom] ? dims[dom] - 1 - lc : lc;
-      nseg = min(n[dom], room) / a.seg_len + 1;
+      const int32_t Sd = sel3(dom, a.S[0], a.S[1], a.S[2]);
+      const int32_t lc = (Sd >> 16) - sel3(dom, a.O[0], a.O[1], a.O[2]);
+      const int32_t room = sel3(dom, q[0], q[1], q[2]) > Sd ? sel3(dom, dims[0], dims[1], dims[2]) - 1 - lc : lc;
+      nseg = min(sel3(dom, n[0], n[1], n[2]), room) / a.seg_len + 1;
     }
   }
 
-  // reserve the wave items: one returning atomic per block, wave bases from
-  // the block's prefix
-  int maxseg = nseg;
+  // ---- stable counting sort of the block's rays by bin (most segments first)
+  const int bin = kSegBins - 1 - min(nseg, kSegBins - 1);
+  unsigned long long peers = ~0ull;  // lanes of this wave in the same bin
+#pragma unroll
+  for (int k = 0; k < 6; k++) {
+    const bool bit = (bin >> k) & 1;
+    const unsigned long long m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  const int rank = __popcll(peers & ((1ull << lane) - 1ull));
+  bin_pre[threadIdx.x] = 0;
+  __syncthreads();
+  if (rank == 0) bin_pre[bin * kRayWaves + wv] = __popcll(peers);
+  __syncthreads();
+  const int pre = block_excl_scan(bin_pre[threadIdx.x], wtot);
+  bin_pre[threadIdx.x] = pre;  // every thread read its entry before the scan's barriers
+  __syncthreads();
+  srec[bin_pre[bin * kRayWaves + wv] + rank] = make_int4(q[0], q[1], q[2], nseg);
+  __syncthreads();
+  const int4 rec = srec[threadIdx.x];
+  a.rays[i] = rec;
+
+  // ---- reserve the wave items: one returning atomic per block, group bases
+  // from the block's prefix
+  int maxseg = rec.w;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) maxseg = max(maxseg, __shfl_xor(maxseg, o));
-  const int total = maxseg;
   const int c0 = __popcll(__ballot(nonfinite));
   const int c1 = __popcll(__ballot(outrange));
   const int c2 = __popcll(__ballot(hit));
   const int c5 = DISTINCT ? __popcll(__ballot(dhit)) : 0;
   if (lane == 0) {
-    wcount[wv][0] = total;
+    wcount[wv][0] = maxseg;
     wcount[wv][1] = c0;
     wcount[wv][2] = c1;
     wcount[wv][3] = c2;
@@ -74,7 +130,7 @@ __device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long sum = 0, s0 = 0, s1 = 0, s2 = 0, s5 = 0;
-    for (int w = 0; w < kRayBlock / 64; w++) {
+    for (int w = 0; w < kRayWaves; w++) {
       wbase[w] = sum;
       sum += wcount[w][0];
       s0 += wcount[w][1];
@@ -85,16 +141,15 @@ __device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
     // blocks are spread over kStripes counters, each with its own item region
     const int st = blk % kStripes;
     const unsigned long long b = sum ? atomicAdd(&a.stats[8 + st], sum) : 0ull;
-    for (int w = 0; w < kRayBlock / 64; w++) wbase[w] += b + a.stripe_off[st];
+    for (int w = 0; w < kRayWaves; w++) wbase[w] += b + a.stripe_off[st];
     unsigned long long* pr = a.part_rays + 4 * (size_t)blk;
     pr[0] = s0;
     pr[1] = s1;
     pr[2] = s2;
     pr[3] = s5;
   }
-  a.rays[i] = make_int4(q[0], q[1], q[2], nseg);
   __syncthreads();
-  const int gw = blk * (kRayBlock / 64) + wv;  // this wave's rays: 64 gw .. 64 gw + 63
+  const int gw = blk * kRayWaves + wv;  // this group's rays: 64 gw .. 64 gw + 63
   const unsigned long long off = wbase[wv];
   for (int j = lane; j < maxseg; j += 64) a.witems[off + j] = make_int2(gw, j);
 }
@@ -123,7 +178,9 @@ __device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
 // (about 15 on the 64-beam workload, against about 60 line requests when
 // every step adds its voxels straight to the map).  So each wave counts its
 // item in a private LDS line table: kWtSlots slots of one 64-byte storage
-// line each (16 counters and a tag = storage index >> 4), found by a hash of
+// line each (16 counters of 16 bits, two per word: a voxel takes at most one
+// pass per lane of the item, so a counter stays below 65 while it is in the
+// table; and a tag = storage index >> 4), found by a hash of
 // the line with kWtProbe linear probes and claimed by compare-and-swap; a lane
 // remembers the slot of its current line, so it looks up only when its ray
 // enters another line.  When the item is done the wave adds every non-zero
@@ -135,13 +192,13 @@ __device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
 // pass ends up in exactly one counter that reaches the map once, so the
 // result is the same integer sum whatever the claim order.
 constexpr int kWtSlots = 64;     // slots per wave (one per lane at the flush)
-constexpr int kWtStride = 17;    // LDS words per slot's counters (bank spread)
+constexpr int kWtStride = 9;     // LDS words per slot: 8 counter pairs + 1 (bank spread)
 constexpr int kWtProbe = 4;
 constexpr int32_t kWtEmpty = -1;
 
 struct WaveTable {
   int32_t tag[kWtSlots];
-  int32_t cnt[kWtSlots * kWtStride];
+  uint32_t cnt[kWtSlots * kWtStride];
   int32_t lst[kWtSlots];
 };
 
@@ -153,14 +210,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Slot of storage line `line` in the wave's table, claiming an empty one on
-// its probe path; -1 when the path holds other lines only.
+// its probe path; -1 when the path holds other lines only.  The first slot
+// is a multiplicative (Fibonacci) hash of the line's low 24 bits: the top six
+// bits of their product with 2^24 / golden ratio (Knuth, TAOCP vol. 3,
+// 6.4), one 24-bit multiply.  Tags hold the whole line, so lines that share
+// low bits only share a probe path.
 __device__ __forceinline__ int wt_lookup(WaveTable& wt, const int32_t line) {
-  uint32_t h = (uint32_t)line;  // 32-bit finaliser of MurmurHash3 (Appleby)
-  h ^= h >> 16;
-  h *= 0x85ebca6bu;
-  h ^= h >> 13;
-  h *= 0xc2b2ae35u;
-  h ^= h >> 16;
+  const uint32_t h = mad_u24((uint32_t)line & 0xFFFFFFu, 0x9E3779u, 0u);
   const int s0 = (int)(h >> 26);
 #pragma unroll
   for (int p = 0; p < kWtProbe; p++) {
@@ -238,7 +294,9 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
       const int dom = dominant_axis(n);
       int32_t v[3] = {sv[0], sv[1], sv[2]};
       bool inside = j < ray.w;  // the ray has segment j
-      if (inside && j > 0) entry_voxel(a.S, sg, ad, dom, sv[dom] + sg[dom] * j * a.seg_len, v);
+      const int32_t sgd = sel3(dom, sg[0], sg[1], sg[2]);
+      if (inside && j > 0)
+        entry_voxel(a.S, sg, ad, dom, sel3(dom, sv[0], sv[1], sv[2]) + sgd * j * a.seg_len, v);
       int32_t l[3];
 #pragma unroll
       for (int k = 0; k < 3; k++) {
@@ -254,9 +312,10 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
         active = (cnt[0] | cnt[1] | cnt[2]) != 0;
         if (BOX) {
           // the segment's dominant-axis cells (window-local) against the box's
-          const int32_t c0 = l[dom], c1 = l[dom] + sg[dom] * (a.seg_len - 1);
+          const int32_t c0 = sel3(dom, l[0], l[1], l[2]), c1 = c0 + sgd * (a.seg_len - 1);
           const int32_t lo = c0 < c1 ? c0 : c1, hi = c0 < c1 ? c1 : c0;
-          near = hi >= a.box_l[dom] && lo < a.box_l[dom] + a.box_e[dom];
+          const int32_t bl = sel3(dom, a.box_l[0], a.box_l[1], a.box_l[2]);
+          near = hi >= bl && lo < bl + sel3(dom, a.box_e[0], a.box_e[1], a.box_e[2]);
         }
       }
     }
@@ -293,7 +352,7 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
             cur_slot = wt_lookup(wt, line);
           }
           if (cur_slot >= 0) {
-            atomicAdd(&wt.cnt[cur_slot * kWtStride + (sidx & 15)], 1);
+            atomicAdd(&wt.cnt[cur_slot * kWtStride + ((sidx & 15) >> 1)], 1u << ((sidx & 1) << 4));
           } else {
             n_upd++;
             atomicAdd(&passes[sidx], 1);
@@ -330,9 +389,11 @@ __device__ __forceinline__ void trace_body(const InsertArgs& a, const int blk, c
         const int e = k + (lane >> 4);
         if (e < nv) {
           const int s = wt.lst[e];
-          const int c = wt.cnt[s * kWtStride + w];
+          const uint32_t pair = wt.cnt[s * kWtStride + (w >> 1)];
+          const int c = (int)((pair >> ((w & 1) << 4)) & 0xFFFFu);
+          // both lanes of a pair have read it before the even one clears it
+          if (pair && !(w & 1)) wt.cnt[s * kWtStride + (w >> 1)] = 0;
           if (c) {
-            wt.cnt[s * kWtStride + w] = 0;
             const int32_t addr = (wt.tag[s] << 4) + w;
             n_upd++;
             atomicAdd(&passes[addr], c);

@@ -23,6 +23,13 @@ __device__ __forceinline__ int32_t mod_pos(int32_t v, int32_t n) {
   return v < 0 ? v + n : v;
 }
 
+// x[k] for a lane-varying axis k, by selects (an indexed private array
+// would go to scratch memory).
+__device__ __forceinline__ int32_t sel3(const int k, const int32_t x0, const int32_t x1,
+                                        const int32_t x2) {
+  return k == 0 ? x0 : (k == 1 ? x1 : x2);
+}
+
 __device__ __forceinline__ int dominant_axis(const int32_t n[3]) {
   return (n[1] > n[0]) ? (n[2] > n[1] ? 2 : 1) : (n[2] > n[0] ? 2 : 0);
 }
@@ -99,34 +106,46 @@ __device__ __forceinline__ bool point_pass(const InsertArgs& a, const int i, int
   return true;
 }
 
-// floor(x / d) for d > 0 (|x| < 2^60): double estimate, exact integer fix-up.
-__device__ __forceinline__ int64_t floor_div_pos(int64_t x, int64_t d, bool* exact) {
-  int64_t q = (int64_t)floor((double)x / (double)d);
-  int64_t r = x - q * d;
-  while (r < 0) { q--; r += d; }
-  while (r >= d) { q++; r -= d; }
-  *exact = r == 0;
-  return q;
-}
-
 // Voxel at which the ray S -> q enters world cell c along axis dm (c is not
 // the sensor's cell): see the traversal pass below for the tie rule.
+//
+// At that instant another axis k lies at X_k = (S_k |D| + s_k |D_k| num) / |D|
+// (Q units; D = the dominant component, s_k the sign along k, num = the
+// dominant-axis distance from the sensor to the cell's boundary), in cell
+// floor(X_k / 2^16).  A float estimate of that quotient is within 0.02 of it
+// (|S_k| < 2^31, the displacement along k is below 2^27, each float step
+// rounds to 2^-24 relative), so its floor is off by at most one and one
+// exact 64-bit remainder test each way settles it.  All three axes are
+// computed without branches (dm varies across a wave) and the dominant one
+// is replaced by c.
 __device__ __forceinline__ void entry_voxel(const int32_t S[3], const int32_t sg[3],
                                             const int32_t ad[3], const int dm, const int32_t c,
                                             int32_t v[3]) {
-  const int64_t num = sg[dm] > 0 ? ((int64_t)c << 16) - S[dm] : (int64_t)S[dm] - (((int64_t)c + 1) << 16);
-  const int64_t den = (int64_t)ad[dm] << 16;
+  const int32_t Sd = sel3(dm, S[0], S[1], S[2]);
+  const int32_t dd = sel3(dm, ad[0], ad[1], ad[2]);
+  const int32_t sd = sel3(dm, sg[0], sg[1], sg[2]);
+  // |num| < 2^28 (the ray spans fewer than 2^11 cells); formed from the
+  // cell offset so that no intermediate overflows
+  const int32_t off = c - (Sd >> 16);
+  const int32_t num = sd > 0 ? (off << 16) - (Sd & 0xFFFF) : (Sd & 0xFFFF) - ((off + 1) << 16);
+  const int64_t den = (int64_t)dd << 16;
+  const float rden = __builtin_amdgcn_rcpf((float)dd * 65536.0f);
+  const float fdd = (float)dd, fnum = (float)num;
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    if (k == dm) {
-      v[k] = c;
-      continue;
+    const int32_t sad = sg[k] * ad[k];
+    const int64_t x = (int64_t)S[k] * dd + (int64_t)num * sad;
+    int64_t qe = (int64_t)floorf(__builtin_fmaf((float)S[k], fdd, fnum * (float)sad) * rden);
+    int64_t r = x - ((qe * dd) << 16);
+    if (r < 0) {
+      qe -= 1;
+      r += den;
+    } else if (r >= den) {
+      qe += 1;
+      r -= den;
     }
-    bool exact;
-    const int64_t x = (int64_t)S[k] * ad[dm] + num * (sg[k] * (int64_t)ad[k]);
-    int64_t vb = floor_div_pos(x, den, &exact);
-    if (exact && sg[dm] < 0 && sg[k] < 0) vb -= 1;
-    v[k] = (int32_t)vb;
+    if (r == 0 && sd < 0 && sg[k] < 0) qe -= 1;
+    v[k] = k == dm ? c : (int32_t)qe;
   }
 }
 
@@ -156,7 +175,7 @@ __device__ __forceinline__ void split_e(int64_t e, int32_t& f, int32_t& c) {
 __device__ __forceinline__ void walk_init(const InsertArgs& a, const int32_t q[3],
                                           const int32_t v[3], const int32_t l[3], Walk& w) {
   const int32_t dims[3] = {a.d.nx, a.d.ny, a.d.nz};
-  int64_t num[3];
+  int32_t num[3];  // |num| < 2^28: v lies on the ray, which spans fewer than 2^11 cells
 #pragma unroll
   for (int k = 0; k < 3; k++) {
     const int32_t ev = q[k] >> 16;
@@ -165,11 +184,12 @@ __device__ __forceinline__ void walk_init(const InsertArgs& a, const int32_t q[3
     w.ad[k] = dq < 0 ? -dq : dq;
     w.rem[k] = ev > v[k] ? ev - v[k] : v[k] - ev;
     w.room[k] = w.sg[k] > 0 ? dims[k] - 1 - l[k] : l[k];
-    num[k] = w.sg[k] > 0 ? (((int64_t)v[k] + 1) << 16) - a.S[k] : (int64_t)a.S[k] - ((int64_t)v[k] << 16);
+    const int32_t off = v[k] - (a.S[k] >> 16), fr = a.S[k] & 0xFFFF;
+    num[k] = w.sg[k] > 0 ? ((off + 1) << 16) - fr : fr - (off << 16);
   }
-  split_e(num[0] * w.ad[1] - num[1] * w.ad[0], w.fxy, w.cxy);
-  split_e(num[0] * w.ad[2] - num[2] * w.ad[0], w.fxz, w.cxz);
-  split_e(num[1] * w.ad[2] - num[2] * w.ad[1], w.fyz, w.cyz);
+  split_e((int64_t)num[0] * w.ad[1] - (int64_t)num[1] * w.ad[0], w.fxy, w.cxy);
+  split_e((int64_t)num[0] * w.ad[2] - (int64_t)num[2] * w.ad[0], w.fxz, w.cxz);
+  split_e((int64_t)num[1] * w.ad[2] - (int64_t)num[2] * w.ad[1], w.fyz, w.cyz);
 }
 
 // One step: the axes with the smallest crossing time move; when several
@@ -241,12 +261,21 @@ __device__ __forceinline__ bool budget_step(Walk& w, int32_t cnt[3], const bool 
   return out;
 }
 
-// col_base with 24-bit multiplies (full rate): brick coordinates < 2^11,
-// nby <= 2048 and nz <= 128 keep every operand within 24 bits, and the
-// index is below 2^31 for every map the library accepts.
+// a * b + c on the 24-bit multiplier (operands below 2^24).  Written out
+// because the compiler widens the plain expression into a 64-bit
+// multiply-add when the result feeds an address.
+__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+// col_base with 24-bit multiplies: brick coordinates < 2^11, nby <= 2048
+// and 16 nz <= 2048 keep every operand within 24 bits, and the index is
+// below 2^31 for every map the library accepts.
 __device__ __forceinline__ int32_t col_base24(const Dims& d, int32_t sx, int32_t sy) {
-  const uint32_t b = __umul24((uint32_t)(sx >> 2), (uint32_t)d.nby) + (uint32_t)(sy >> 2);
-  return (int32_t)((__umul24(b, (uint32_t)d.nz) << 4) + ((sy & 3) << 2) + (sx & 3));
+  const uint32_t b = mad_u24((uint32_t)(sx >> 2), (uint32_t)d.nby, (uint32_t)(sy >> 2));
+  return (int32_t)mad_u24(b, (uint32_t)d.nz << 4, (uint32_t)(((sy & 3) << 2) | (sx & 3)));
 }
 
 }  // namespace

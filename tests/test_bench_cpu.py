@@ -15,7 +15,8 @@ def test_profile_summaries_parse():
     for name, keys in (("trace_seq64_traffic.txt", ["hbm bytes per launch",
                                                      "algorithmic bytes per launch (8 x distinct passed voxels)"]),
                        ("atomics_seq64.txt", ["line requests per traversal phase"]),
-                       ("calibration_mi355x.txt", ["copy GB/s", "scatter atomics per s"])):
+                       ("trace_seq64_instructions.txt", ["k_trace<false> SQ_INSTS_VALU"]),
+                       ("calibration_mi355x.txt", ["copy GB/s", "peak atomic line requests per s"])):
         s = bench.read_summary(name)
         assert s is not None, name
         for k in keys:
@@ -30,7 +31,7 @@ def test_line_requests_below_updates():
     line requests cannot exceed its run-merged updates."""
     s = bench.read_summary("atomics_seq64.txt")
     lr = float(s["line requests per traversal phase"])
-    upd = float(s["pass updates per launch (run-merged, outside the sensor box)"])
+    upd = float(s["pass updates per launch (outside the sensor box, one per non-zero voxel counter a wave item flushes)"])
     assert 0 < lr <= upd
 
 
