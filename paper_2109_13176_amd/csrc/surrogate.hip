@@ -191,6 +191,26 @@ constexpr int kTC = 64, kPad = 8;
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
+// Copies N 16-byte items into LDS with all of a thread's global loads issued
+// before its first LDS store (a loop that stores each item as it arrives
+// waits out one memory latency per item): item i = load(i), then
+// store(i, item).
+template <int N, int NT, class Load, class Store>
+__device__ __forceinline__ void stage16(Load load, Store store) {
+  constexpr int IT = (N + NT - 1) / NT;
+  uint4 v[IT];
+#pragma unroll
+  for (int k = 0; k < IT; k++) {
+    const int i = (int)threadIdx.x + k * NT;
+    v[k] = i < N ? load(i) : make_uint4(0u, 0u, 0u, 0u);
+  }
+#pragma unroll
+  for (int k = 0; k < IT; k++) {
+    const int i = (int)threadIdx.x + k * NT;
+    if (i < N) store(i, v[k]);
+  }
+}
+
 // NORM (first layer): x holds the raw fp32 features; each is normalised as
 // bf16((float)((f - mean) / std)) (double arithmetic) while staged, and the
 // block's own pixels are also written to xn, the layer input the backward
@@ -209,36 +229,63 @@ __global__ __launch_bounds__(TR * 64) void k_conv_mfma(const void* __restrict__ 
   __shared__ __attribute__((aligned(16))) uint16_t sw[32 * 9 * PS];
   const int r0 = blockIdx.y * TR, c0 = blockIdx.x * kTC;
   constexpr int Q = CIN / 8;  // 8-channel groups per pixel
-  for (int i = threadIdx.x; i < (TR + 2) * (kTC + 2) * Q; i += NT) {
+  constexpr int NX = (TR + 2) * (kTC + 2) * Q;
+  auto in_tile = [&](int i, int64_t* e) {
     const int pix = i / Q, cq = i - pix * Q;
     const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
     const int gr = r0 + tr - 1, gc = c0 + tc - 1;
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (gr >= 0 && gr < H && gc >= 0 && gc < W) {
-      const int64_t e = ((int64_t)gr * W + gc) * CIN + cq * 8;
-      if constexpr (NORM) {
-        const float* f = (const float*)xin + e;
-        uint16_t b[8];
+    *e = ((int64_t)gr * W + gc) * CIN + cq * 8;
+    return gr >= 0 && gr < H && gc >= 0 && gc < W;
+  };
+  if constexpr (NORM) {
+    // raw features: all loads of the thread first, then normalise and store
+    constexpr int IT = (NX + NT - 1) / NT;
+    float4 f[IT][2];
 #pragma unroll
-        for (int k = 0; k < 8; k++) {
-          const int ch = cq * 8 + k;
-          b[k] = to_bf16((float)(((double)f[k] - (double)mean[ch]) / (double)stdv[ch]));
-        }
-        v.x = (uint32_t)b[0] | ((uint32_t)b[1] << 16);
-        v.y = (uint32_t)b[2] | ((uint32_t)b[3] << 16);
-        v.z = (uint32_t)b[4] | ((uint32_t)b[5] << 16);
-        v.w = (uint32_t)b[6] | ((uint32_t)b[7] << 16);
-        if (tr >= 1 && tr <= TR && tc >= 1 && tc <= kTC) *(uint4*)(xn + e) = v;
-      } else {
-        v = *(const uint4*)((const uint16_t*)xin + e);
+    for (int k = 0; k < IT; k++) {
+      const int i = (int)threadIdx.x + k * NT;
+      int64_t e = 0;
+      f[k][0] = f[k][1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (i < NX && in_tile(i, &e)) {
+        f[k][0] = *(const float4*)((const float*)xin + e);
+        f[k][1] = *(const float4*)((const float*)xin + e + 4);
       }
     }
-    *(uint4*)(sx + pix * PS + cq * 8) = v;
+#pragma unroll
+    for (int k = 0; k < IT; k++) {
+      const int i = (int)threadIdx.x + k * NT;
+      if (i >= NX) continue;
+      int64_t e = 0;
+      const bool in = in_tile(i, &e);
+      const int pix = i / Q, cq = i - pix * Q;
+      const float fv[8] = {f[k][0].x, f[k][0].y, f[k][0].z, f[k][0].w,
+                           f[k][1].x, f[k][1].y, f[k][1].z, f[k][1].w};
+      uint16_t b[8];
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const int ch = cq * 8 + j;
+        b[j] = in ? to_bf16((float)(((double)fv[j] - (double)mean[ch]) / (double)stdv[ch])) : 0;
+      }
+      const uint4 v = make_uint4((uint32_t)b[0] | ((uint32_t)b[1] << 16),
+                                 (uint32_t)b[2] | ((uint32_t)b[3] << 16),
+                                 (uint32_t)b[4] | ((uint32_t)b[5] << 16),
+                                 (uint32_t)b[6] | ((uint32_t)b[7] << 16));
+      const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
+      if (in && tr >= 1 && tr <= TR && tc >= 1 && tc <= kTC) *(uint4*)(xn + e) = v;
+      *(uint4*)(sx + pix * PS + cq * 8) = v;
+    }
+  } else {
+    stage16<NX, NT>(
+        [&](int i) {
+          int64_t e = 0;
+          return in_tile(i, &e) ? *(const uint4*)((const uint16_t*)xin + e)
+                                : make_uint4(0u, 0u, 0u, 0u);
+        },
+        [&](int i, uint4 v) { *(uint4*)(sx + (i / Q) * PS + (i % Q) * 8) = v; });
   }
-  for (int i = threadIdx.x; i < 32 * 9 * Q; i += NT) {
-    const int row = i / Q, cq = i - row * Q;
-    *(uint4*)(sw + row * PS + cq * 8) = *(const uint4*)(w + row * CIN + cq * 8);
-  }
+  stage16<32 * 9 * Q, NT>(
+      [&](int i) { return *(const uint4*)(w + (i / Q) * CIN + (i % Q) * 8); },
+      [&](int i, uint4 v) { *(uint4*)(sw + (i / Q) * PS + (i % Q) * 8) = v; });
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -272,6 +319,11 @@ __global__ __launch_bounds__(TR * 64) void k_conv_mfma(const void* __restrict__ 
   }
   const int r = r0 + wv;
   if (r >= H) return;
+  float bv[2][4];
+#pragma unroll
+  for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+    for (int e = 0; e < 4; e++) bv[mt][e] = bias[mt * 16 + 4 * lk + e];
 #pragma unroll
   for (int mt = 0; mt < 2; mt++)
 #pragma unroll
@@ -282,7 +334,7 @@ __global__ __launch_bounds__(TR * 64) void k_conv_mfma(const void* __restrict__ 
       uint16_t o[4];
 #pragma unroll
       for (int e = 0; e < 4; e++) {
-        const float z = acc[mt][nt][e] + bias[co0 + e];
+        const float z = acc[mt][nt][e] + bv[mt][e];
         o[e] = to_bf16(z > 0.0f ? z : 0.0f);
       }
       uint2 pk;
@@ -292,45 +344,60 @@ __global__ __launch_bounds__(TR * 64) void k_conv_mfma(const void* __restrict__ 
     }
 }
 
-// Output layer (32 -> 2, no ReLU): fp32 accumulation of bf16 products, tap
-// by tap and channel by channel.  Block = 8 rows x 64 pixels, one thread per
-// pixel, the input tile with its halo staged in LDS.
+// Output layer (32 -> 2, no ReLU) on matrix cores, laid out as k_conv_mfma
+// with one 16-row output tile whose rows 0 and 1 are the two channels (the
+// A operands of rows 2..15 are zero); each wave keeps its nine A operands
+// in registers.  Block = 8 rows x 64 pixels, one wave per row, the input
+// tile with its halo staged in LDS.
 __global__ __launch_bounds__(512) void k_conv_out(const uint16_t* __restrict__ x,
                                                   const uint16_t* __restrict__ w,
                                                   const float* __restrict__ bias,
                                                   float* __restrict__ out, int H, int W) {
-  constexpr int TR = 8, PS = 32 + kPad;
+  constexpr int TR = 8, CIN = 32, PS = CIN + kPad, Q = CIN / 8;
   __shared__ __attribute__((aligned(16))) uint16_t sx[(TR + 2) * (kTC + 2) * PS];
-  __shared__ float sw[2 * 9 * 32];
   const int r0 = blockIdx.y * TR, c0 = blockIdx.x * kTC;
-  for (int i = threadIdx.x; i < 2 * 9 * 32; i += 512) sw[i] = from_bf16(w[i]);
-  for (int i = threadIdx.x; i < (TR + 2) * (kTC + 2) * 4; i += 512) {
-    const int pix = i >> 2, cq = i & 3;
-    const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
-    const int gr = r0 + tr - 1, gc = c0 + tc - 1;
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (gr >= 0 && gr < H && gc >= 0 && gc < W)
-      v = *(const uint4*)(x + ((int64_t)gr * W + gc) * 32 + cq * 8);
-    *(uint4*)(sx + pix * PS + cq * 8) = v;
-  }
-  __syncthreads();
-  const int tr = threadIdx.x >> 6, tc = threadIdx.x & 63;
-  const int r = r0 + tr, c = c0 + tc;
-  if (r >= H || c >= W) return;
-  float s0 = bias[0], s1 = bias[1];
-  for (int tap = 0; tap < 9; tap++) {
-    const int rr = r + tap / 3 - 1, cc = c + tap % 3 - 1;
-    if (rr < 0 || rr >= H || cc < 0 || cc >= W) continue;
-    const uint16_t* xp = sx + ((tr + tap / 3) * (kTC + 2) + tc + tap % 3) * PS;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  v8bf aw[9];
 #pragma unroll
-    for (int ci = 0; ci < 32; ci++) {
-      const float v = from_bf16(xp[ci]);
-      s0 = __builtin_fmaf(sw[(0 * 9 + tap) * 32 + ci], v, s0);
-      s1 = __builtin_fmaf(sw[(1 * 9 + tap) * 32 + ci], v, s1);
+  for (int tap = 0; tap < 9; tap++) {
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (lr < 2) v = *(const uint4*)(w + (lr * 9 + tap) * CIN + 8 * lk);
+    aw[tap] = __builtin_bit_cast(v8bf, v);
+  }
+  stage16<(TR + 2) * (kTC + 2) * Q, 512>(
+      [&](int i) {
+        const int pix = i / Q, cq = i - pix * Q;
+        const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
+        const int gr = r0 + tr - 1, gc = c0 + tc - 1;
+        return (gr >= 0 && gr < H && gc >= 0 && gc < W)
+                   ? *(const uint4*)(x + ((int64_t)gr * W + gc) * CIN + cq * 8)
+                   : make_uint4(0u, 0u, 0u, 0u);
+      },
+      [&](int i, uint4 v) { *(uint4*)(sx + (i / Q) * PS + (i % Q) * 8) = v; });
+  __syncthreads();
+  v4f acc[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; nt++) acc[nt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int tap = 0; tap < 9; tap++) {
+    const int dy = tap / 3, dx = tap - dy * 3;
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++) {
+      const v8bf b = *(const v8bf*)(sx + ((wv + dy) * (kTC + 2) + nt * 16 + lr + dx) * PS + 8 * lk);
+      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[tap], b, acc[nt], 0, 0, 0);
     }
   }
-  out[((int64_t)r * W + c) * 2] = s0;
-  out[((int64_t)r * W + c) * 2 + 1] = s1;
+  // result lane: pixel column lr, rows (channels) 4 lk + e: the two channels
+  // sit in the lanes with lk = 0
+  const int r = r0 + wv;
+  if (r >= H || lk != 0) return;
+  const float b0 = bias[0], b1 = bias[1];
+#pragma unroll
+  for (int nt = 0; nt < 4; nt++) {
+    const int col = c0 + nt * 16 + lr;
+    if (col < W) *(float2*)(out + ((int64_t)r * W + col) * 2) = make_float2(acc[nt][0] + b0, acc[nt][1] + b1);
+  }
 }
 
 
@@ -390,68 +457,83 @@ __global__ __launch_bounds__(256) void k_loss_total(const double* part, int nb, 
 }
 
 // -------------------------------------------------------------- backward
-// Input gradient of a layer, then through the ReLU of the layer below:
-// dprev[p][ci] = (x[p][ci] > 0) * sum over taps, co of W[co][tap][ci] dz[p - tap][co].
-// Block = 16 x 16 pixels, dz tile with halo and the weights in LDS.
-template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_bwd_data(const float* __restrict__ dz,
-                                                  const uint16_t* __restrict__ w,
-                                                  const uint16_t* __restrict__ x,
-                                                  float* __restrict__ dprev,
-                                                  uint16_t* __restrict__ dph,
-                                                  uint16_t* __restrict__ dpl, int H, int W) {
-  __shared__ float sdz[18 * 18 * COUT];
-  __shared__ float sw[COUT * 9 * CIN];
-  const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
-  for (int i = threadIdx.x; i < 18 * 18 * COUT; i += 256) {
-    const int pix = i / COUT, co = i - pix * COUT;
-    const int gr = r0 + pix / 18 - 1, gc = c0 + pix % 18 - 1;
-    sdz[i] = (gr >= 0 && gr < H && gc >= 0 && gc < W) ? dz[((int64_t)gr * W + gc) * COUT + co] : 0.0f;
+// Input gradient of the 32 -> 2 output layer, then through the ReLU of the
+// layer below: dprev[p][ci] = (x[p][ci] > 0) * sum over taps t and co of
+// W[co][t][ci] dz[p - offset(t)][co], on matrix cores as one GEMM with
+// K = 2 t + co (18 of the 32 of v_mfma_f32_16x16x32_bf16 used; the rest
+// zero): A[ci][k] = W[co][t][ci] (constant, built once per lane), B[k][p] =
+// dz[p - offset(t)][co] gathered from the block's dz tile in LDS.  The loss
+// gradient dz is a sign (-1, 0 or 1), exact in bf16, so the products are
+// exact and fp32-accumulated.  Stored as the bf16 pair hi = bf16(dprev),
+// lo = bf16(dprev - hi) that the matrix-core kernels of the layer below read.
+// Block = 8 rows x 64 pixels, one wave per row.
+__global__ __launch_bounds__(512) void k_bwd_data_out(const float* __restrict__ dz,
+                                                      const uint16_t* __restrict__ w,
+                                                      const uint16_t* __restrict__ x,
+                                                      uint16_t* __restrict__ dph,
+                                                      uint16_t* __restrict__ dpl, int H, int W) {
+  constexpr int TR = 8, C = 32, XC = kTC + 2;
+  __shared__ float sdz[(TR + 2) * XC * 2];
+  const int r0 = blockIdx.y * TR, c0 = blockIdx.x * kTC;
+  for (int i = threadIdx.x; i < (TR + 2) * XC; i += 512) {
+    const int tr = i / XC, tc = i - tr * XC;
+    const int gr = r0 + tr - 1, gc = c0 + tc - 1;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (gr >= 0 && gr < H && gc >= 0 && gc < W) v = *(const float2*)(dz + ((int64_t)gr * W + gc) * 2);
+    sdz[2 * i] = v.x;
+    sdz[2 * i + 1] = v.y;
   }
-  for (int i = threadIdx.x; i < COUT * 9 * CIN; i += 256) sw[i] = from_bf16(w[i]);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lr = lane & 15, kg = lane >> 4;
+  // A: row ci = 16 mt + lr, k = 8 kg + j -> (t, co) = (k / 2, k % 2)
+  v8bf a[2];
+#pragma unroll
+  for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int k = 8 * kg + j, tap = k >> 1, co = k & 1;
+      const uint16_t wb = k < 18 ? w[(co * 9 + tap) * C + 16 * mt + lr] : (uint16_t)0;
+      a[mt][j] = __builtin_bit_cast(__bf16, wb);
+    }
   __syncthreads();
-  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-  const int r = r0 + tr, c = c0 + tc;
-  if (r >= H || c >= W) return;
-  float acc[CIN];
-  for (int k = 0; k < CIN; k++) acc[k] = 0.0f;
-  for (int tap = 0; tap < 9; tap++) {
-    // the output pixel p - (tap offset) sees this pixel through tap
-    const int sr = tr + 1 - (tap / 3 - 1), sc = tc + 1 - (tap % 3 - 1);
-    const float* g = sdz + (sr * 18 + sc) * COUT;
-    for (int co = 0; co < COUT; co++) {
-      const float gv = g[co];
-      const float* wr = sw + (co * 9 + tap) * CIN;
+  const int r = r0 + wv;
 #pragma unroll
-      for (int k = 0; k < CIN; k++) acc[k] = __builtin_fmaf(wr[k], gv, acc[k]);
+  for (int nt = 0; nt < kTC / 16; nt++) {
+    const int pc = nt * 16 + lr;  // tile column of this lane's pixel
+    v8bf b;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int k = 8 * kg + j, kk = k < 18 ? k : 0, tap = kk >> 1, co = kk & 1;
+      // the output pixel p - offset(t) sees this pixel through tap t
+      const int sr = wv + 1 - (tap / 3 - 1), sc = pc + 1 - (tap % 3 - 1);
+      const float v = sdz[(sr * XC + sc) * 2 + co];
+      b[j] = (__bf16)(k < 18 ? v : 0.0f);
     }
-  }
-  const uint16_t* xp = x + ((int64_t)r * W + c) * CIN;
-  const int64_t o = ((int64_t)r * W + c) * CIN;
-  static_assert(CIN % 8 == 0, "bf16 pairs are stored 8 channels at a time");
+    v4f acc[2];
 #pragma unroll
-  for (int k0 = 0; k0 < CIN; k0 += 8) {
-    const uint4 xq = *(const uint4*)(xp + k0);
-    const uint32_t xw[4] = {xq.x, xq.y, xq.z, xq.w};
-    float v[8];
-    uint32_t hw[4], lw[4];
+    for (int mt = 0; mt < 2; mt++)
+      acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, v4f{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+    const int col = c0 + pc;
+    if (r >= H || col >= W) continue;
 #pragma unroll
-    for (int k = 0; k < 8; k++) {
-      const uint16_t xb = (uint16_t)(xw[k >> 1] >> (16 * (k & 1)));
-      v[k] = from_bf16(xb) > 0.0f ? acc[k0 + k] : 0.0f;
+    for (int mt = 0; mt < 2; mt++) {
+      const int ci0 = mt * 16 + 4 * kg;
+      const int64_t o = ((int64_t)r * W + col) * C + ci0;
+      const uint2 xm = *(const uint2*)(x + o);
+      const uint16_t xs[4] = {(uint16_t)(xm.x & 0xFFFFu), (uint16_t)(xm.x >> 16),
+                              (uint16_t)(xm.y & 0xFFFFu), (uint16_t)(xm.y >> 16)};
+      uint16_t hi[4], lo[4];
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const float v = from_bf16(xs[e]) > 0.0f ? acc[mt][e] : 0.0f;
+        hi[e] = to_bf16(v);
+        lo[e] = to_bf16(v - from_bf16(hi[e]));
+      }
+      *(uint2*)(dph + o) = make_uint2((uint32_t)hi[0] | ((uint32_t)hi[1] << 16),
+                                      (uint32_t)hi[2] | ((uint32_t)hi[3] << 16));
+      *(uint2*)(dpl + o) = make_uint2((uint32_t)lo[0] | ((uint32_t)lo[1] << 16),
+                                      (uint32_t)lo[2] | ((uint32_t)lo[3] << 16));
     }
-#pragma unroll
-    for (int k = 0; k < 8; k += 2) {
-      // the bf16 pair the matrix-core kernels of the layer below read
-      const uint16_t h0 = to_bf16(v[k]), h1 = to_bf16(v[k + 1]);
-      const uint16_t l0 = to_bf16(v[k] - from_bf16(h0)), l1 = to_bf16(v[k + 1] - from_bf16(h1));
-      hw[k / 2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-      lw[k / 2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
-    }
-    *(float4*)(dprev + o + k0) = make_float4(v[0], v[1], v[2], v[3]);
-    *(float4*)(dprev + o + k0 + 4) = make_float4(v[4], v[5], v[6], v[7]);
-    *(uint4*)(dph + o + k0) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-    *(uint4*)(dpl + o + k0) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
   }
 }
 
@@ -462,13 +544,14 @@ __global__ __launch_bounds__(256) void k_bwd_data(const float* __restrict__ dz,
 // parts, hi = bf16(dz) and lo = bf16(dz - hi), each through the same
 // instructions into one fp32 accumulator, so the product keeps about 16 bits
 // of dz beyond bf16.  Layout and operand lanes as k_conv_mfma (CIN = 32); the
-// tile is staged twice (hi, then lo) through one LDS array.
+// tile is staged twice (hi, then lo) through one LDS array.  wt holds the
+// transposed weights W' (rows ci * 9 + t, 32 co each, written by k_pack);
+// the result leaves as the bf16 pair of the layer below only.
 template <int TR>
 __global__ __launch_bounds__(TR * 64) void k_bwd_data_mfma(const uint16_t* __restrict__ dzh,
                                                            const uint16_t* __restrict__ dzl,
-                                                           const uint16_t* __restrict__ w,
+                                                           const uint16_t* __restrict__ wt,
                                                            const uint16_t* __restrict__ x,
-                                                           float* __restrict__ dprev,
                                                            uint16_t* __restrict__ dph,
                                                            uint16_t* __restrict__ dpl, int H,
                                                            int W) {
@@ -476,12 +559,9 @@ __global__ __launch_bounds__(TR * 64) void k_bwd_data_mfma(const uint16_t* __res
   __shared__ __attribute__((aligned(16))) uint16_t sx[(TR + 2) * (kTC + 2) * PS];
   __shared__ __attribute__((aligned(16))) uint16_t sw[32 * 9 * PS];
   const int r0 = blockIdx.y * TR, c0 = blockIdx.x * kTC;
-  // row ci * 9 + t of the transposed weights: W[co][8 - t][ci] over co
-  for (int i = threadIdx.x; i < 32 * 9 * C; i += NT) {
-    const int row = i / C, co = i - row * C;
-    const int ci = row / 9, t = row - ci * 9;
-    sw[row * PS + co] = w[(co * 9 + (8 - t)) * C + ci];
-  }
+  stage16<32 * 9 * Q, NT>(
+      [&](int i) { return *(const uint4*)(wt + (i / Q) * C + (i % Q) * 8); },
+      [&](int i, uint4 v) { *(uint4*)(sw + (i / Q) * PS + (i % Q) * 8) = v; });
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   v4f acc[2][4];
@@ -489,15 +569,16 @@ __global__ __launch_bounds__(TR * 64) void k_bwd_data_mfma(const uint16_t* __res
     for (int n = 0; n < 4; n++) acc[m][n] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
   for (int part = 0; part < 2; part++) {
     const uint16_t* src = part ? dzl : dzh;
-    for (int i = threadIdx.x; i < (TR + 2) * (kTC + 2) * Q; i += NT) {
-      const int pix = i / Q, cq = i - pix * Q;
-      const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
-      const int gr = r0 + tr - 1, gc = c0 + tc - 1;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (gr >= 0 && gr < H && gc >= 0 && gc < W)
-        v = *(const uint4*)(src + ((int64_t)gr * W + gc) * C + cq * 8);
-      *(uint4*)(sx + pix * PS + cq * 8) = v;
-    }
+    stage16<(TR + 2) * (kTC + 2) * Q, NT>(
+        [&](int i) {
+          const int pix = i / Q, cq = i - pix * Q;
+          const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
+          const int gr = r0 + tr - 1, gc = c0 + tc - 1;
+          return (gr >= 0 && gr < H && gc >= 0 && gc < W)
+                     ? *(const uint4*)(src + ((int64_t)gr * W + gc) * C + cq * 8)
+                     : make_uint4(0u, 0u, 0u, 0u);
+        },
+        [&](int i, uint4 v) { *(uint4*)(sx + (i / Q) * PS + (i % Q) * 8) = v; });
     __syncthreads();
 #pragma unroll
     for (int tap = 0; tap < 9; tap++) {
@@ -535,7 +616,6 @@ __global__ __launch_bounds__(TR * 64) void k_bwd_data_mfma(const uint16_t* __res
         hi[e] = to_bf16(v[e]);
         lo[e] = to_bf16(v[e] - from_bf16(hi[e]));
       }
-      *(float4*)(dprev + o) = make_float4(v[0], v[1], v[2], v[3]);
       *(uint2*)(dph + o) = make_uint2((uint32_t)hi[0] | ((uint32_t)hi[1] << 16),
                                       (uint32_t)hi[2] | ((uint32_t)hi[3] << 16));
       *(uint2*)(dpl + o) = make_uint2((uint32_t)lo[0] | ((uint32_t)lo[1] << 16),
@@ -543,232 +623,278 @@ __global__ __launch_bounds__(TR * 64) void k_bwd_data_mfma(const uint16_t* __res
     }
 }
 
-// Weight and bias gradient partials on matrix cores, one per block of TR
-// rows x 64 pixels: dW[co][ci][t] = sum_p dz[p][co] x[p + offset(t)][ci] is
-// one GEMM per tap with A = dz^T (row = output channel), B = shifted x
-// (column = input channel) and K = pixels.  Both are staged transposed
-// (channel-major, pixels contiguous) so that a lane's 8 consecutive K values
-// are one 16-byte LDS read; x is staged once per column shift dx (taps of
-// equal dx share the copy).  dz enters as the bf16 pair hi + lo written by
-// the input-gradient kernel of the layer above.  Wave w takes input-channel
-// tile w % (CIN / 16) and every (TR * CIN / 16 / 4)-th row from w / (CIN /
-// 16), so a wave keeps 9 x 2 accumulator tiles; the waves' results are
-// summed in LDS in wave order (deterministic) before the partial is written.
-constexpr int kWRS = kTC + 8;  // LDS row stride (bf16) of the transposed tiles
+// Weight and bias gradient partials on matrix cores: dW[co][ci][t] =
+// sum_p dz[p][co] x[p + offset(t)][ci] is one GEMM per tap with A = dz^T
+// (row = output channel), B = the shifted x (column = input channel) and
+// K = pixels.  Both tiles stay in LDS in their memory layout (pixel rows,
+// channels contiguous, stored with 16-byte loads and 8-byte LDS writes); the
+// K-major operand fragments come from the LDS transpose read
+// (ds_read_b64_tr_b16): within each 16-lane group, output lane s receives
+// element s % 4 of the 8-byte rows read by lanes s / 4, 4 + s / 4,
+// 8 + s / 4 and 12 + s / 4.  So when lane s of group g points at pixel
+// p0 + 8 g + s / 4 (and + 4 for the second half), channel c0 + 4 (s % 4),
+// lane s holds the 8 consecutive pixels of channel c0 + s that the 16x16x32
+// operand layout asks for (A row / B column = lane % 16, k = 8 (lane / 16)
+// + e).  The tap shift is a whole-pixel offset in the staged x tile.
+//
+// Block = 4 waves over NTILE tiles of 4 rows x 64 pixels (accumulators stay
+// in registers across the tiles); wave w takes output tile pair (co tile
+// w % 2, ci tile (w / 2) % (CIN / 16)) for all 9 taps and, for CIN = 16, the
+// rows of parity w / 2 (the two waves of a pair are added in LDS in fixed
+// order).  dz enters as the bf16 pair hi + lo of the input-gradient kernel
+// of the layer above (two MFMAs per product).  The bias gradient is the same
+// product with an all-ones B.  One partial [co][ci][tap] + [co] per block.
+constexpr int kWgRows = 4;            // rows per tile
+constexpr int kWgTiles = 4;           // tiles per block
+constexpr int kWgPZ = 32 + 4;         // LDS pixel stride (bf16) of the dz tiles
+typedef short v8s __attribute__((ext_vector_type(8)));
 
-template <int CIN, int TR>
-__global__ __launch_bounds__(TR * 64) void k_bwd_weight_mfma(const uint16_t* __restrict__ dzh,
-                                                             const uint16_t* __restrict__ dzl,
-                                                             const uint16_t* __restrict__ x,
-                                                             float* __restrict__ part, int H,
-                                                             int W) {
-  constexpr int CO = 32, NT = TR * 64, NCT = CIN / 16;
-  constexpr int NW = CO * CIN * 9;
-  constexpr int NWAVE = TR, RSTEP = NWAVE / NCT;  // waves; row step of a wave
-  static_assert(NWAVE % NCT == 0, "waves split evenly over the channel tiles");
-  static_assert(2 * CO * TR * kWRS * 2 >= NW * 4, "the wave sum reuses the dz tile");
-  __shared__ __attribute__((aligned(16))) uint16_t sdz[2 * CO * TR * kWRS];  // [hi/lo][co][row][col]
-  __shared__ __attribute__((aligned(16))) uint16_t sx[CIN * (TR + 2) * kWRS];  // [ci][row][col]
-  __shared__ float sbias[CO];
-  const int r0 = blockIdx.y * TR, c0 = blockIdx.x * kTC;
+__device__ __forceinline__ v8bf tr_pair(const uint16_t* lo4, const uint16_t* hi4) {
+  const v4s a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) v4s*)lo4);
+  const v4s b = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) v4s*)hi4);
+  const v8s c = __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_bit_cast(v8bf, c);
+}
+
+template <int CIN, int NTILE>
+__global__ __launch_bounds__(256) void k_bwd_weight_mfma(const uint16_t* __restrict__ dzh,
+                                                         const uint16_t* __restrict__ dzl,
+                                                         const uint16_t* __restrict__ x,
+                                                         float* __restrict__ part, int H, int W) {
+  constexpr int CO = 32, NW = CO * CIN * 9, NCT = CIN / 16;
+  constexpr int NPAIR = 2 * NCT, RSPLIT = 4 / NPAIR;  // waves per (co, ci) tile pair
+  constexpr int PX = CIN + 4;                          // LDS pixel stride of the x tile
+  constexpr int XC = kTC + 2, XR = kWgRows + 2;       // x tile with its halo
+  static_assert(NPAIR * RSPLIT == 4, "four waves");
+  __shared__ __attribute__((aligned(16))) uint16_t sdz[2 * kWgRows * kTC * kWgPZ];
+  __shared__ __attribute__((aligned(16))) uint16_t sx[XR * XC * PX];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
-  for (int i = threadIdx.x; i < 2 * TR * kTC * (CO / 8); i += NT) {
-    const int cg = i % (CO / 8);
-    int rest = i / (CO / 8);
-    const int col = rest % kTC;
-    rest /= kTC;
-    const int row = rest % TR, hl = rest / TR;
-    const int gr = r0 + row, gc = c0 + col;
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (gr < H && gc < W) v = *(const uint4*)((hl ? dzl : dzh) + ((int64_t)gr * W + gc) * CO + cg * 8);
-    const uint32_t q[4] = {v.x, v.y, v.z, v.w};
+  const int s = lane & 15, g = lane >> 4;
+  const int pair = wv % NPAIR, rs = wv / NPAIR;
+  const int mt = pair & 1, nt = pair >> 1;
+  const int c0 = blockIdx.x * kTC;
+  v4f acc[9], accb = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int k = 0; k < 8; k++)
-      sdz[((hl * CO + cg * 8 + k) * TR + row) * kWRS + col] = (uint16_t)(q[k >> 1] >> (16 * (k & 1)));
-  }
-  const int nt = wv % NCT, row0 = wv / NCT;
-  v4f acc[9][2];
+  for (int t = 0; t < 9; t++) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  v8bf ones;
 #pragma unroll
-  for (int t = 0; t < 9; t++)
-#pragma unroll
-    for (int m = 0; m < 2; m++) acc[t][m] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-  for (int dx = 0; dx < 3; dx++) {
-    __syncthreads();  // the previous copy of x has been read
-    for (int i = threadIdx.x; i < (TR + 2) * kTC * (CIN / 8); i += NT) {
-      const int cg = i % (CIN / 8);
-      const int rest = i / (CIN / 8);
-      const int col = rest % kTC, row = rest / kTC;
-      const int gr = r0 + row - 1, gc = c0 + col + dx - 1;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (gr >= 0 && gr < H && gc >= 0 && gc < W)
-        v = *(const uint4*)(x + ((int64_t)gr * W + gc) * CIN + cg * 8);
-      const uint32_t q[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int k = 0; k < 8; k++)
-        sx[((cg * 8 + k) * (TR + 2) + row) * kWRS + col] = (uint16_t)(q[k >> 1] >> (16 * (k & 1)));
-    }
+  for (int e = 0; e < 8; e++) ones[e] = (__bf16)1.0f;
+  for (int tile = 0; tile < NTILE; tile++) {
+    const int r0 = (blockIdx.y * NTILE + tile) * kWgRows;
+    __syncthreads();  // the previous tile has been read
+    stage16<2 * kWgRows * kTC * 4, 256>(
+        [&](int i) {
+          const int hl = i / (kWgRows * kTC * 4), rem = i - hl * (kWgRows * kTC * 4);
+          const int pix = rem >> 2, cg = rem & 3;
+          const int gr = r0 + pix / kTC, gc = c0 + pix % kTC;
+          return (gr < H && gc < W)
+                     ? *(const uint4*)((hl ? dzl : dzh) + ((int64_t)gr * W + gc) * CO + cg * 8)
+                     : make_uint4(0u, 0u, 0u, 0u);
+        },
+        [&](int i, uint4 v) {
+          uint2* d = (uint2*)(sdz + (i >> 2) * kWgPZ + (i & 3) * 8);
+          d[0] = make_uint2(v.x, v.y);
+          d[1] = make_uint2(v.z, v.w);
+        });
+    stage16<XR * XC * (CIN / 8), 256>(
+        [&](int i) {
+          const int pix = i / (CIN / 8), cq = i - pix * (CIN / 8);
+          const int tr = pix / XC, tc = pix - tr * XC;
+          const int gr = r0 + tr - 1, gc = c0 + tc - 1;
+          return (gr >= 0 && gr < H && gc >= 0 && gc < W)
+                     ? *(const uint4*)(x + ((int64_t)gr * W + gc) * CIN + cq * 8)
+                     : make_uint4(0u, 0u, 0u, 0u);
+        },
+        [&](int i, uint4 v) {
+          uint2* d = (uint2*)(sx + (i / (CIN / 8)) * PX + (i % (CIN / 8)) * 8);
+          d[0] = make_uint2(v.x, v.y);
+          d[1] = make_uint2(v.z, v.w);
+        });
     __syncthreads();
-    for (int row = row0; row < TR; row += RSTEP) {
+    for (int r = rs; r < kWgRows; r += RSPLIT) {
 #pragma unroll
-      for (int dy = 0; dy < 3; dy++) {
-        const int tap = dy * 3 + dx;
+      for (int kc = 0; kc < kTC / 32; kc++) {
+        const int pa = r * kTC + kc * 32 + 8 * g + (s >> 2);
+        const int ca = mt * 16 + 4 * (s & 3);
+        const uint16_t* ah = sdz + pa * kWgPZ + ca;
+        const uint16_t* al = ah + kWgRows * kTC * kWgPZ;
+        const v8bf a_hi = tr_pair(ah, ah + 4 * kWgPZ);
+        const v8bf a_lo = tr_pair(al, al + 4 * kWgPZ);
+        if (nt == 0) {
+          accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, ones, accb, 0, 0, 0);
+          accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, ones, accb, 0, 0, 0);
+        }
+        const int cb = nt * 16 + 4 * (s & 3);
 #pragma unroll
-        for (int ks = 0; ks < kTC / 32; ks++) {
-          const v8bf b =
-              *(const v8bf*)(sx + ((nt * 16 + lr) * (TR + 2) + row + dy) * kWRS + ks * 32 + 8 * lk);
-#pragma unroll
-          for (int hl = 0; hl < 2; hl++)
-#pragma unroll
-            for (int mt = 0; mt < 2; mt++) {
-              const v8bf a =
-                  *(const v8bf*)(sdz + ((hl * CO + mt * 16 + lr) * TR + row) * kWRS + ks * 32 + 8 * lk);
-              acc[tap][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[tap][mt], 0, 0, 0);
-            }
+        for (int t = 0; t < 9; t++) {
+          const int dy = t / 3, dx = t - dy * 3;
+          const uint16_t* bp = sx + ((r + dy) * XC + kc * 32 + 8 * g + (s >> 2) + dx) * PX + cb;
+          const v8bf b = tr_pair(bp, bp + 4 * PX);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi, b, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo, b, acc[t], 0, 0, 0);
         }
       }
     }
   }
-  // bias: the block's sum of dz (hi + lo) per output channel
-  if (threadIdx.x < CO) {
-    float sb = 0.0f;
-    for (int row = 0; row < TR; row++)
-      for (int col = 0; col < kTC; col++)
-        sb += from_bf16(sdz[((0 * CO + threadIdx.x) * TR + row) * kWRS + col]) +
-              from_bf16(sdz[((1 * CO + threadIdx.x) * TR + row) * kWRS + col]);
-    sbias[threadIdx.x] = sb;
-  }
-  __syncthreads();
-  float* red = (float*)sdz;  // [co][ci][tap]
-  for (int i = threadIdx.x; i < NW; i += NT) red[i] = 0.0f;
-  __syncthreads();
-  for (int w = 0; w < NWAVE; w++) {
-    if (wv == w) {
+  float* out = part + (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * (NW + CO);
+  if constexpr (RSPLIT == 2) {
+    // the odd-row waves hand their sums to the even-row waves of the same pair
+    __syncthreads();
+    float* red = (float*)sdz;  // [pair][t][e][lane] + bias
+    if (rs == 1) {
 #pragma unroll
       for (int t = 0; t < 9; t++)
 #pragma unroll
-        for (int mt = 0; mt < 2; mt++)
+        for (int e = 0; e < 4; e++) red[((pair * 10 + t) * 4 + e) * 64 + lane] = acc[t][e];
 #pragma unroll
-          for (int e = 0; e < 4; e++) {
-            const int co = mt * 16 + 4 * lk + e, ci = nt * 16 + lr;
-            const int idx = (co * CIN + ci) * 9 + t;
-            red[idx] += acc[t][mt][e];
-          }
+      for (int e = 0; e < 4; e++) red[((pair * 10 + 9) * 4 + e) * 64 + lane] = accb[e];
     }
     __syncthreads();
+    if (rs == 1) return;
+#pragma unroll
+    for (int t = 0; t < 9; t++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) acc[t][e] += red[((pair * 10 + t) * 4 + e) * 64 + lane];
+#pragma unroll
+    for (int e = 0; e < 4; e++) accb[e] += red[((pair * 10 + 9) * 4 + e) * 64 + lane];
   }
-  const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-  float* out = part + (int64_t)blk * (NW + CO);
-  for (int i = threadIdx.x; i < NW; i += NT) out[i] = red[i];
-  if (threadIdx.x < CO) out[NW + threadIdx.x] = sbias[threadIdx.x];
+  // result lane: column ci = s of the tile, rows co = 4 g + e
+#pragma unroll
+  for (int t = 0; t < 9; t++)
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int co = mt * 16 + 4 * g + e, ci = nt * 16 + s;
+      out[(co * CIN + ci) * 9 + t] = acc[t][e];
+    }
+  if (nt == 0 && s == 0) {
+#pragma unroll
+    for (int e = 0; e < 4; e++) out[NW + mt * 16 + 4 * g + e] = accb[e];
+  }
 }
 
-// Weight (and bias) gradient of the 32 -> 2 output layer:
-// dW[co][tap][ci] = sum over pixels p of dz[p][co] x[p + off(tap)][ci].  A
-// half-wave (32 lanes, lane = input channel) takes kWoCols pixels of one
-// image row: it loads the 3 x (kWoCols + 2) input values of its channel
-// (64 contiguous bytes across the lanes per value) and the pixels' dz at
-// once, then adds up the 18 sums of its channel in column order; the block's
-// eight half-waves are added in a fixed order into one partial per block
-// (bias: lane 0 sums dz), so the result is reproducible.  Partial b covers
-// units 8 b .. 8 b + 7 (unit = row x column chunk).
-constexpr int kWoCols = 16;
-
+// Weight (and bias) gradient of the 32 -> 2 output layer on matrix cores,
+// laid out as k_bwd_weight_mfma: A = dz^T with the two output channels as
+// rows 0 and 1 of a 16-row operand (rows 2..15 zero), staged as 16-channel
+// pixel rows; dz is the loss gradient, a sign (-1, 0 or 1) exact in bf16, so
+// one product per pair.  Wave w takes ci tile w % 2 and the rows of parity
+// w / 2 (the two waves of a tile are added in LDS in fixed order).
+template <int NTILE>
 __global__ __launch_bounds__(256) void k_bwd_weight_out(const float* __restrict__ dz,
                                                         const uint16_t* __restrict__ x,
                                                         float* __restrict__ part, int H, int W) {
-  constexpr int CIN = 32, COUT = 2, NW = COUT * CIN * 9;
-  __shared__ float red[8][NW + COUT];
-  const int ci = threadIdx.x & 31, hw = threadIdx.x >> 5;
-  const int chunks = (W + kWoCols - 1) / kWoCols;
-  const int unit = blockIdx.x * 8 + hw;
-  float acc[COUT][9];
+  constexpr int CIN = 32, CO = 2, NW = CO * CIN * 9, PZ = 16 + 4, PX = CIN + 4;
+  constexpr int XC = kTC + 2, XR = kWgRows + 2;
+  __shared__ __attribute__((aligned(16))) uint16_t sdz[kWgRows * kTC * PZ];
+  __shared__ __attribute__((aligned(16))) uint16_t sx[XR * XC * PX];
+  __shared__ float red[2][10][4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int s = lane & 15, g = lane >> 4;
+  const int nt = wv & 1, rs = wv >> 1;
+  const int c0 = blockIdx.x * kTC;
+  for (int i = threadIdx.x; i < kWgRows * kTC * PZ / 2; i += 256) ((uint32_t*)sdz)[i] = 0u;
+  v4f acc[9], accb = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int c = 0; c < COUT; c++)
+  for (int t = 0; t < 9; t++) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  v8bf ones;
 #pragma unroll
-    for (int k = 0; k < 9; k++) acc[c][k] = 0.0f;
-  float bsum[COUT] = {0.0f, 0.0f};
-  if (unit < H * chunks) {
-    const int r = unit / chunks, c0 = (unit - r * chunks) * kWoCols;
-    auto ld = [&](int rr, int cc) -> float {
-      return (rr >= 0 && rr < H && cc >= 0 && cc < W)
-                 ? from_bf16(x[((int64_t)rr * W + cc) * CIN + ci])
-                 : 0.0f;
-    };
-    // the chunk's 3 x (kWoCols + 2) input values and its dz, loaded up front
-    // (independent loads in flight), then the sums in column order
-    float xv[3][kWoCols + 2];
-    float d[kWoCols][COUT];
-#pragma unroll
-    for (int dy = 0; dy < 3; dy++)
-#pragma unroll
-      for (int j = 0; j < kWoCols + 2; j++) xv[dy][j] = ld(r + dy - 1, c0 + j - 1);
-#pragma unroll
-    for (int j = 0; j < kWoCols; j++) {
-      const bool ok = c0 + j < W;
-      d[j][0] = ok ? dz[((int64_t)r * W + c0 + j) * COUT] : 0.0f;
-      d[j][1] = ok ? dz[((int64_t)r * W + c0 + j) * COUT + 1] : 0.0f;
+  for (int e = 0; e < 8; e++) ones[e] = (__bf16)1.0f;
+  for (int tile = 0; tile < NTILE; tile++) {
+    const int r0 = (blockIdx.y * NTILE + tile) * kWgRows;
+    __syncthreads();  // the previous tile has been read (and the zero fill is done)
+    {
+      const int pix = threadIdx.x;  // kWgRows * kTC == 256 pixels, one per thread
+      const int gr = r0 + pix / kTC, gc = c0 + pix % kTC;
+      float2 v = make_float2(0.0f, 0.0f);
+      if (gr < H && gc < W) v = *(const float2*)(dz + ((int64_t)gr * W + gc) * CO);
+      *(uint32_t*)(sdz + pix * PZ) = (uint32_t)to_bf16(v.x) | ((uint32_t)to_bf16(v.y) << 16);
     }
+    stage16<XR * XC * (CIN / 8), 256>(
+        [&](int i) {
+          const int pix = i / (CIN / 8), cq = i - pix * (CIN / 8);
+          const int tr = pix / XC, tc = pix - tr * XC;
+          const int gr = r0 + tr - 1, gc = c0 + tc - 1;
+          return (gr >= 0 && gr < H && gc >= 0 && gc < W)
+                     ? *(const uint4*)(x + ((int64_t)gr * W + gc) * CIN + cq * 8)
+                     : make_uint4(0u, 0u, 0u, 0u);
+        },
+        [&](int i, uint4 v) {
+          uint2* d = (uint2*)(sx + (i / (CIN / 8)) * PX + (i % (CIN / 8)) * 8);
+          d[0] = make_uint2(v.x, v.y);
+          d[1] = make_uint2(v.z, v.w);
+        });
+    __syncthreads();
+    for (int r = rs; r < kWgRows; r += 2) {
 #pragma unroll
-    for (int j = 0; j < kWoCols; j++) {
+      for (int kc = 0; kc < kTC / 32; kc++) {
+        const uint16_t* ap = sdz + (r * kTC + kc * 32 + 8 * g + (s >> 2)) * PZ + 4 * (s & 3);
+        const v8bf a = tr_pair(ap, ap + 4 * PZ);
+        if (nt == 0) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ones, accb, 0, 0, 0);
+        const int cb = nt * 16 + 4 * (s & 3);
 #pragma unroll
-      for (int k = 0; k < 9; k++) {
-        acc[0][k] = __builtin_fmaf(d[j][0], xv[k / 3][j + k % 3], acc[0][k]);
-        acc[1][k] = __builtin_fmaf(d[j][1], xv[k / 3][j + k % 3], acc[1][k]);
+        for (int t = 0; t < 9; t++) {
+          const int dy = t / 3, dx = t - dy * 3;
+          const uint16_t* bp = sx + ((r + dy) * XC + kc * 32 + 8 * g + (s >> 2) + dx) * PX + cb;
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, tr_pair(bp, bp + 4 * PX), acc[t], 0, 0, 0);
+        }
       }
-      bsum[0] += d[j][0];
-      bsum[1] += d[j][1];
     }
   }
+  // the odd-row waves hand their sums to the even-row waves of the same tile
+  if (rs == 1) {
 #pragma unroll
-  for (int c = 0; c < COUT; c++)
+    for (int t = 0; t < 9; t++)
 #pragma unroll
-    for (int k = 0; k < 9; k++) red[hw][(c * CIN + ci) * 9 + k] = acc[c][k];
-  if (ci == 0) {
-    red[hw][NW] = bsum[0];
-    red[hw][NW + 1] = bsum[1];
+      for (int e = 0; e < 4; e++) red[nt][t][e][lane] = acc[t][e];
+#pragma unroll
+    for (int e = 0; e < 4; e++) red[nt][9][e][lane] = accb[e];
   }
   __syncthreads();
-  float* out = part + (int64_t)blockIdx.x * (NW + COUT);
-  for (int i = threadIdx.x; i < NW + COUT; i += 256) {
-    float sum = 0.0f;
-    for (int g = 0; g < 8; g++) sum += red[g][i];
-    out[i] = sum;
+  if (rs == 1 || g != 0) return;  // rows co = 4 g + e: only g = 0, e < 2 exist
+  float* out = part + (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * (NW + CO);
+#pragma unroll
+  for (int e = 0; e < CO; e++) {
+    const int ci = nt * 16 + s;
+#pragma unroll
+    for (int t = 0; t < 9; t++) out[(e * CIN + ci) * 9 + t] = acc[t][e] + red[nt][t][e][lane];
+    if (nt == 0 && s == 0) out[NW + e] = accb[e] + red[nt][9][e][lane];
   }
 }
 
-int wo_blocks(int H, int W) { return (H * ((W + kWoCols - 1) / kWoCols) + 7) / 8; }
 
-// Two-stage fixed-order (deterministic) reduction of the weight-gradient
-// partials: stage 1 sums groups of kRedGroup consecutive tiles per parameter
-// (grid.y = group), stage 2 sums the groups and scales by 1 / count.
-constexpr int kRedGroup = 32;
+// Fixed-order (deterministic) reduction of the weight-gradient partials,
+// scaled by 1 / count: a block takes 64 parameters (one per lane); wave w of
+// its kRedWaves sums the partials w, w + kRedWaves, ... in order in double,
+// with eight loads in flight, and the wave sums are added in a fixed order.
+constexpr int kRedWaves = 16;
 
-__global__ __launch_bounds__(256) void k_reduce_parts(const float* part, int nb, int64_t np,
-                                                      double* mid) {
-  const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (o >= np) return;
-  const int b0 = blockIdx.y * kRedGroup, b1 = min(nb, b0 + kRedGroup);
-  double s = 0.0;
-  for (int b = b0; b < b1; b++) s += part[(int64_t)b * np + o];
-  mid[(int64_t)blockIdx.y * np + o] = s;
-}
-
-// Stage 2: a block takes 64 parameters (one per lane); wave w sums the
-// groups w, w + 4, ... in order, and the four sums are added in a fixed order.
-__global__ __launch_bounds__(256) void k_reduce_mid(const double* mid, int ng, int64_t np,
-                                                    const double* scal, float* grad) {
-  __shared__ double ws[4][64];
+__global__ __launch_bounds__(kRedWaves * 64) void k_reduce_grad(const float* __restrict__ part,
+                                                                int nb, int64_t np,
+                                                                const double* __restrict__ scal,
+                                                                float* __restrict__ grad) {
+  __shared__ double ws[kRedWaves][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t o = (int64_t)blockIdx.x * 64 + lane;
   double s = 0.0;
-  if (o < np)
-    for (int g = w; g < ng; g += 4) s += mid[(int64_t)g * np + o];
+  if (o < np) {
+    constexpr int U = 8;
+    for (int b0 = w; b0 < nb; b0 += kRedWaves * U) {
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int b = b0 + kRedWaves * u;
+        v[u] = b < nb ? part[(int64_t)b * np + o] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) s += (double)v[u];
+    }
+  }
   ws[w][lane] = s;
   __syncthreads();
-  if (w == 0 && o < np)
-    grad[o] = (float)(((ws[0][lane] + ws[1][lane]) + (ws[2][lane] + ws[3][lane])) * scal[1]);
+  if (w == 0 && o < np) {
+    double t = 0.0;
+    for (int k = 0; k < kRedWaves; k++) t += ws[k][lane];
+    grad[o] = (float)(t * scal[1]);
+  }
 }
 
 // Adam on the fp32 master weights; the bf16 copy is repacked afterwards.
@@ -786,14 +912,30 @@ __global__ __launch_bounds__(256) void k_adam(float* w, float* m, float* v, cons
 }
 
 // master W[co][ci][ky][kx] -> bf16 W[co][tap][ci]; biases copied (fp32)
-__global__ __launch_bounds__(256) void k_pack(const float* master, int cin, int cout,
-                                              uint16_t* wbf, float* bias) {
+// wtr (null for layers without a matrix-core input gradient): the same
+// weights transposed for it, wtr[(ci * 9 + t) * cout + co] = W[co][8 - t][ci].
+// One launch packs every layer: blockIdx.y = layer.
+struct PackArgs {
+  const float* master[kNL];
+  uint16_t* wbf[kNL];
+  float* bias[kNL];
+  uint16_t* wtr[kNL];
+};
+
+__global__ __launch_bounds__(256) void k_pack(PackArgs pa) {
+  const int l = blockIdx.y, cin = kCin[l], cout = kCout[l];
+  const float* master = pa.master[l];
+  uint16_t* wbf = pa.wbf[l];
+  uint16_t* wtr = pa.wtr[l];
+  float* bias = pa.bias[l];
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int nw = cout * cin * 9;
   if (i < nw) {
     const int co = i / (cin * 9), rest = i - co * cin * 9;
     const int ci = rest / 9, tap = rest - ci * 9;
-    wbf[(co * 9 + tap) * cin + ci] = to_bf16(master[i]);
+    const uint16_t b = to_bf16(master[i]);
+    wbf[(co * 9 + tap) * cin + ci] = b;
+    if (wtr) wtr[(ci * 9 + (8 - tap)) * cout + co] = b;
   } else if (i < nw + cout) {
     bias[i - nw] = master[i];
   }
@@ -845,13 +987,13 @@ struct sgt_net_t {
   int64_t off[kNL];
   float *master, *m, *v, *grad;
   uint16_t* wbf[kNL];
+  uint16_t* wtr[kNL];  // transposed copies for the matrix-core input gradient (else null)
   float* bias[kNL];
   uint16_t* act[kNL];  // input of each layer (bf16)
   float* out;
-  float *dz0, *dz1;    // fp32 gradient images (up to 32 channels)
+  float* dz0;          // fp32 loss gradient image (2 channels)
   uint16_t *dzh[2], *dzl[2];  // the same as bf16 pairs hi + lo (32 channels)
   float* part;         // weight-gradient partials, one per 16 x 16 tile
-  double* mid;         // partials summed over groups of kRedGroup tiles
   int part_blocks;
   double* lpart;
   double* scal;
@@ -863,11 +1005,17 @@ struct sgt_net_t {
 namespace {
 
 hipError_t pack_all(sgt_net_t* n) {
+  PackArgs pa;
+  int most = 0;
   for (int l = 0; l < kNL; l++) {
+    pa.master[l] = n->master + n->off[l];
+    pa.wbf[l] = n->wbf[l];
+    pa.bias[l] = n->bias[l];
+    pa.wtr[l] = n->wtr[l];
     const int cnt = kCout[l] * kCin[l] * 9 + kCout[l];
-    hipLaunchKernelGGL(k_pack, dim3(blocks_for(cnt)), dim3(256), 0, n->stream, n->master + n->off[l],
-                       kCin[l], kCout[l], n->wbf[l], n->bias[l]);
+    if (blocks_for(cnt) > most) most = blocks_for(cnt);
   }
+  hipLaunchKernelGGL(k_pack, dim3(most, kNL), dim3(256), 0, n->stream, pa);
   return hipGetLastError();
 }
 
@@ -924,9 +1072,8 @@ int32_t sgt_create(int32_t H, int32_t W, uint64_t seed, void* stream, sgt_net_t*
   // partial slots: the larger of the 16 x 16-tile VALU kernel's count and
   // the 4-row x 64-pixel matrix-core kernel's
   n->part_blocks = ((W + 15) / 16) * ((H + 15) / 16);
-  const int mfma_blocks = ((W + kTC - 1) / kTC) * ((H + 3) / 4);
+  const int mfma_blocks = ((W + kTC - 1) / kTC) * ((H + kWgRows * kWgTiles - 1) / (kWgRows * kWgTiles));
   if (mfma_blocks > n->part_blocks) n->part_blocks = mfma_blocks;
-  if (wo_blocks(H, W) > n->part_blocks) n->part_blocks = wo_blocks(H, W);
   int64_t maxlp = 0;
   for (int l = 0; l < kNL; l++) maxlp = layer_params(l) > maxlp ? layer_params(l) : maxlp;
   hipError_t e = hipSuccess;
@@ -939,18 +1086,17 @@ int32_t sgt_create(int32_t H, int32_t W, uint64_t seed, void* stream, sgt_net_t*
   al((void**)&n->grad, n->np * 4);
   for (int l = 0; l < kNL; l++) {
     al((void**)&n->wbf[l], (size_t)kCout[l] * kCin[l] * 9 * 2);
+    if (l >= 1 && l <= 3) al((void**)&n->wtr[l], (size_t)kCout[l] * kCin[l] * 9 * 2);
     al((void**)&n->bias[l], (size_t)kCout[l] * 4);
     al((void**)&n->act[l], (size_t)P * kCin[l] * 2);
   }
   al((void**)&n->out, P * 2 * 4);
-  al((void**)&n->dz0, P * 32 * 4);
-  al((void**)&n->dz1, P * 32 * 4);
+  al((void**)&n->dz0, P * 2 * 4);
   for (int k = 0; k < 2; k++) {
     al((void**)&n->dzh[k], P * 32 * 2);
     al((void**)&n->dzl[k], P * 32 * 2);
   }
   al((void**)&n->part, (size_t)n->part_blocks * maxlp * 4);
-  al((void**)&n->mid, (size_t)((n->part_blocks + kRedGroup - 1) / kRedGroup) * maxlp * 8);
   al((void**)&n->lpart, (size_t)4096 * 2 * 8);
   al((void**)&n->scal, 16);
   al((void**)&n->mean, kFeat * 4);
@@ -988,7 +1134,7 @@ int32_t sgt_create(int32_t H, int32_t W, uint64_t seed, void* stream, sgt_net_t*
 int32_t sgt_destroy(sgt_net_t* n) {
   if (!n) return MAP_OK;
   (void)hipStreamSynchronize(n->stream);
-  void* ps[] = {n->master, n->m, n->v, n->grad, n->out, n->dz0, n->dz1, n->part, n->mid,
+  void* ps[] = {n->master, n->m, n->v, n->grad, n->out, n->dz0, n->part,
                 n->lpart, n->scal, n->mean, n->stdv};
   for (void* p : ps) (void)gvom::dev_free(p);
   for (int k = 0; k < 2; k++) {
@@ -997,6 +1143,7 @@ int32_t sgt_destroy(sgt_net_t* n) {
   }
   for (int l = 0; l < kNL; l++) {
     (void)gvom::dev_free(n->wbf[l]);
+    (void)gvom::dev_free(n->wtr[l]);
     (void)gvom::dev_free(n->bias[l]);
     (void)gvom::dev_free(n->act[l]);
   }
@@ -1112,9 +1259,7 @@ int32_t sgt_loss_grad(sgt_net_t* n, const float* feat_dev, const float* label_de
   hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, n->stream, n->out, label_dev, P * 2, n->dz0,
                      n->lpart);
   hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, n->stream, n->lpart, lb, n->scal);
-  dim3 g16((W + 15) / 16, (H + 15) / 16);
-  float* dz = n->dz0;
-  float* dp = n->dz1;
+  const float* dz = n->dz0;  // the loss gradient (the output layer's dz)
   int hb = 0;  // bf16 pair holding dz (set by the layer above)
   dim3 g8((W + kTC - 1) / kTC, (H + 7) / 8);
   for (int l = kNL - 1; l >= 0; l--) {
@@ -1122,37 +1267,30 @@ int32_t sgt_loss_grad(sgt_net_t* n, const float* feat_dev, const float* label_de
     // weight gradients: the 2-channel output layer on the VALU, the others on
     // matrix cores (dz of those comes as the bf16 pair of the layer above)
     int nb;
+    const dim3 gw((W + kTC - 1) / kTC, (H + kWgRows * kWgTiles - 1) / (kWgRows * kWgTiles));
+    nb = (int)(gw.x * gw.y);
     if (l == 4) {
-      nb = wo_blocks(H, W);
-      hipLaunchKernelGGL(k_bwd_weight_out, dim3(nb), dim3(256), 0, n->stream, dz, n->act[l],
-                         n->part, H, W);
+      hipLaunchKernelGGL((k_bwd_weight_out<kWgTiles>), gw, dim3(256), 0, n->stream, dz,
+                         n->act[l], n->part, H, W);
     } else {
-      const dim3 gw((W + kTC - 1) / kTC, (H + 3) / 4);
       if (l == 0)
-        hipLaunchKernelGGL((k_bwd_weight_mfma<16, 4>), gw, dim3(256), 0, n->stream, n->dzh[hb],
-                           n->dzl[hb], n->act[l], n->part, H, W);
+        hipLaunchKernelGGL((k_bwd_weight_mfma<16, kWgTiles>), gw, dim3(256), 0, n->stream,
+                           n->dzh[hb], n->dzl[hb], n->act[l], n->part, H, W);
       else
-        hipLaunchKernelGGL((k_bwd_weight_mfma<32, 4>), gw, dim3(256), 0, n->stream, n->dzh[hb],
-                           n->dzl[hb], n->act[l], n->part, H, W);
-      nb = (int)(gw.x * gw.y);
+        hipLaunchKernelGGL((k_bwd_weight_mfma<32, kWgTiles>), gw, dim3(256), 0, n->stream,
+                           n->dzh[hb], n->dzl[hb], n->act[l], n->part, H, W);
     }
-    const int ng = (nb + kRedGroup - 1) / kRedGroup;
-    hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for(lp), ng), dim3(256), 0, n->stream, n->part,
-                       nb, lp, n->mid);
-    hipLaunchKernelGGL(k_reduce_mid, dim3((unsigned)((lp + 63) / 64)), dim3(256), 0, n->stream, n->mid, ng, lp,
-                       n->scal, n->grad + n->off[l]);
+    hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((lp + 63) / 64)), dim3(kRedWaves * 64), 0, n->stream,
+                       n->part, nb, lp, n->scal, n->grad + n->off[l]);
     if (l == 0) break;
     if (l == 4)
-      hipLaunchKernelGGL((k_bwd_data<32, 2>), g16, dim3(256), 0, n->stream, dz, n->wbf[l],
-                         n->act[l], dp, n->dzh[hb], n->dzl[hb], H, W);
+      hipLaunchKernelGGL(k_bwd_data_out, g8, dim3(512), 0, n->stream, dz, n->wbf[l], n->act[l],
+                         n->dzh[hb], n->dzl[hb], H, W);
     else
       hipLaunchKernelGGL((k_bwd_data_mfma<8>), g8, dim3(512), 0, n->stream, n->dzh[hb],
-                         n->dzl[hb], n->wbf[l], n->act[l], dp, n->dzh[hb ^ 1], n->dzl[hb ^ 1],
+                         n->dzl[hb], n->wtr[l], n->act[l], n->dzh[hb ^ 1], n->dzl[hb ^ 1],
                          H, W);
     if (l != 4) hb ^= 1;
-    float* t = dz;
-    dz = dp;
-    dp = t;
   }
   e = hipGetLastError();
   double scal[2] = {0.0, 0.0};
