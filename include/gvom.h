@@ -275,8 +275,9 @@ int32_t map_get_tuning(const map_t* m, map_tuning_t* out);
 
 /* Optional per-phase timing with HIP events recorded on the map's stream
  * around each kernel group (instrumentation for benchmarks).  Phases:
- * MAP_PROF_SCROLL (window clears), MAP_PROF_RAYS (transform, returns and the
- * ray-segment list), MAP_PROF_TRACE (ray traversal), MAP_PROF_COLUMN (column
+ * MAP_PROF_SCROLL (window clears), MAP_PROF_RAYS (transform, returns, ray
+ * records and wave items), MAP_PROF_TRACE (ray traversal and sensor-box
+ * fold), MAP_PROF_COLUMN (column
  * reduction), MAP_PROF_SURFACE (slope, roughness, negative obstacles),
  * MAP_PROF_LUT (lookup-table export).  map_profile_enable takes a mask (bit p
  * = phase p, 0 = off, MAP_PROF_ALL = every phase; each profiled phase costs

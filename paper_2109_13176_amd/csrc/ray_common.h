@@ -1,4 +1,4 @@
-// Device helpers shared by the ray passes (segmented and binned): point
+// Device helpers of the ray pass and the traversal: point
 // transform and return, dominant axis, exact segment entry voxel and the
 // exact integer voxel walk (Sec. III-C of arXiv 2109.13176).
 #pragma once
@@ -261,12 +261,13 @@ __device__ __forceinline__ bool budget_step(Walk& w, int32_t cnt[3], const bool 
   return out;
 }
 
-// a * b + c on the 24-bit multiplier (operands below 2^24).  Written out
-// because the compiler widens the plain expression into a 64-bit
-// multiply-add when the result feeds an address.
+// a * b + c on the 24-bit multiplier (operands below 2^24; b uniform across
+// the wave, taken from a scalar register).  Written out because the compiler
+// widens the plain expression into a 64-bit multiply-add when the result
+// feeds an address.
 __device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) {
   uint32_t r;
-  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
   return r;
 }
 

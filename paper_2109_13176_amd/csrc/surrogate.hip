@@ -1027,7 +1027,9 @@ int32_t st_of(hipError_t e) {
   return MAP_OK;
 }
 
-hipError_t forward_all(sgt_net_t* n, const float* feat) {
+// Forward of all layers; the output layer writes `out` (n->out for training,
+// the caller's buffer for inference).
+hipError_t forward_all(sgt_net_t* n, const float* feat, float* out) {
   const int H = n->H, W = n->W;
   dim3 g4((W + kTC - 1) / kTC, (H + 3) / 4), g8((W + kTC - 1) / kTC, (H + 7) / 8);
   hipLaunchKernelGGL((k_conv_mfma<16, 4, true>), g4, dim3(256), 0, n->stream, (const void*)feat,
@@ -1037,7 +1039,7 @@ hipError_t forward_all(sgt_net_t* n, const float* feat) {
                        (const void*)n->act[l], n->wbf[l], n->bias[l], n->act[l + 1], H, W,
                        (const float*)nullptr, (const float*)nullptr, (uint16_t*)nullptr);
   hipLaunchKernelGGL(k_conv_out, g8, dim3(512), 0, n->stream, n->act[4], n->wbf[4], n->bias[4],
-                     n->out, H, W);
+                     out, H, W);
   return hipGetLastError();
 }
 
@@ -1069,11 +1071,8 @@ int32_t sgt_create(int32_t H, int32_t W, uint64_t seed, void* stream, sgt_net_t*
     o += layer_params(l);
   }
   const int64_t P = (int64_t)H * W;
-  // partial slots: the larger of the 16 x 16-tile VALU kernel's count and
-  // the 4-row x 64-pixel matrix-core kernel's
-  n->part_blocks = ((W + 15) / 16) * ((H + 15) / 16);
-  const int mfma_blocks = ((W + kTC - 1) / kTC) * ((H + kWgRows * kWgTiles - 1) / (kWgRows * kWgTiles));
-  if (mfma_blocks > n->part_blocks) n->part_blocks = mfma_blocks;
+  // partial slots: one per block of the weight-gradient kernels
+  n->part_blocks = ((W + kTC - 1) / kTC) * ((H + kWgRows * kWgTiles - 1) / (kWgRows * kWgTiles));
   int64_t maxlp = 0;
   for (int l = 0; l < kNL; l++) maxlp = layer_params(l) > maxlp ? layer_params(l) : maxlp;
   hipError_t e = hipSuccess;
@@ -1241,11 +1240,7 @@ int32_t sgt_feature_sums(sgt_net_t* n, const float* feat_dev, double* sums_host)
 
 int32_t sgt_forward(sgt_net_t* n, const float* feat_dev, float* out_dev) {
   if (!n || !feat_dev || !out_dev) return MAP_E_INVALID;
-  hipError_t e = forward_all(n, feat_dev);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(out_dev, n->out, (size_t)n->H * n->W * 2 * 4, hipMemcpyDeviceToDevice,
-                       n->stream);
-  return st_of(e);
+  return st_of(forward_all(n, feat_dev, out_dev));
 }
 
 int32_t sgt_loss_grad(sgt_net_t* n, const float* feat_dev, const float* label_dev,
@@ -1253,7 +1248,7 @@ int32_t sgt_loss_grad(sgt_net_t* n, const float* feat_dev, const float* label_de
   if (!n || !feat_dev || !label_dev) return MAP_E_INVALID;
   const int H = n->H, W = n->W;
   const int64_t P = (int64_t)H * W;
-  hipError_t e = forward_all(n, feat_dev);
+  hipError_t e = forward_all(n, feat_dev, n->out);
   if (e != hipSuccess) return st_of(e);
   const int lb = blocks_for(P * 2) < 4096 ? blocks_for(P * 2) : 4096;
   hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, n->stream, n->out, label_dev, P * 2, n->dz0,
