@@ -101,13 +101,27 @@ __device__ __forceinline__ void column_body(const ColumnArgs& a, const int blk) 
     int cnt = 0;
     const int zlo = kg + a.n_lo;
     const int zhi = min(kg + a.n_hi, nz - 1);
-    for (int z = zlo; z <= zhi; z++) {
-      if (!test_bit(m, z)) continue;
-      const int64_t e = base + (wrap_add(z + a.d.ro[2], nz) << 4);
-      const int32_t h = a.hits[e];
-      sh += h;
-      sa += (int64_t)h + a.passes[e];
-      cnt++;
+    // the band's occupied levels in chunks of eight, all loads of a chunk in
+    // flight before the sums (one memory round trip per chunk)
+    for (int z0 = zlo; z0 <= zhi; z0 += 8) {
+      int32_t hv[8], pv[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        const int z = z0 + u;
+        hv[u] = pv[u] = -1;
+        if (z <= zhi && test_bit(m, z)) {
+          const int64_t e = base + (wrap_add(z + a.d.ro[2], nz) << 4);
+          hv[u] = a.hits[e];
+          pv[u] = a.passes[e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        if (hv[u] < 0) continue;
+        sh += hv[u];
+        sa += (int64_t)hv[u] + pv[u];
+        cnt++;
+      }
     }
     if (cnt > 0) {
       density = (float)((double)sh / (double)sa);
