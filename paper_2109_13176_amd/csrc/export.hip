@@ -27,8 +27,9 @@ __global__ __launch_bounds__(kBlock) void k_lut_write(LutArgs a, uint32_t nz_mag
 
 // Density of every voxel (the voxel-map output, Fig. 1), in window-local
 // table order: the storage region of the table export (4 x 16 columns) is
-// read in storage order, each voxel's density computed there and kept in LDS
-// rows in window-local z order; then every lane writes four consecutive
+// read in storage order (16-byte loads, all of a thread's loads in flight
+// before its LDS stores), each voxel's density computed there and kept in
+// LDS rows in window-local z order; then every lane writes four consecutive
 // densities of one column.
 __global__ __launch_bounds__(kBlock) void k_density(DensityArgs a, uint32_t nz_magic) {
   extern __shared__ __attribute__((aligned(16))) float lden[];  // [64][lut_row(nz)]
@@ -47,20 +48,43 @@ __global__ __launch_bounds__(kBlock) void k_density(DensityArgs a, uint32_t nz_m
     }
     sout[t] = o;
   }
+  // 16-byte word k4 of the region: brick b, level zs, brick row iy
+  // (k4 = 4 (b nz + zs) + iy), voxels ix = 0..3 (slot 16 ix + 4 b + iy)
   const int nbricks = min(4, a.d.nby - 4 * byr);
   const int64_t r0 = col_base(a.d, 4 * bxr, 16 * byr);
-  const int total = nbricks * nz * 16;
-  for (int k = threadIdx.x; k < total; k += kBlock) {
-    const int bz = k >> 4, l16 = k & 15;
-    const int b = nz == 1 ? bz : (int)__umulhi((uint32_t)bz, nz_magic);
-    const int zs = bz - b * nz;
-    const int lz = zs >= roz ? zs - roz : zs - roz + nz;
-    const int slot = (l16 & 3) * 16 + 4 * b + (l16 >> 2);
-    const int32_t h = a.hits[r0 + k], p = a.passes[r0 + k];
-    float v;
-    if (h >= 1) v = (float)((double)h / ((double)h + (double)p));
-    else v = p >= 1 ? 0.0f : __uint_as_float(kQNaN);
-    lden[slot * nzp + lz] = v;
+  const int nv4 = nbricks * nz * 4;
+  const int4* __restrict__ hsrc = (const int4*)(a.hits + r0);
+  const int4* __restrict__ psrc = (const int4*)(a.passes + r0);
+  for (int k0 = 0; k0 < nv4; k0 += kLutLoads * kBlock) {
+    int4 hv[kLutLoads], pv[kLutLoads];
+#pragma unroll
+    for (int u = 0; u < kLutLoads; u++) {
+      // clamped, not skipped: every lane loads (in bounds), the stores below
+      // skip the words past the region
+      const int k4 = min(k0 + u * kBlock + (int)threadIdx.x, nv4 - 1);
+      hv[u] = hsrc[k4];
+      pv[u] = psrc[k4];
+    }
+#pragma unroll
+    for (int u = 0; u < kLutLoads; u++) {
+      const int k4 = k0 + u * kBlock + threadIdx.x;
+      if (k4 < nv4) {
+        const int bz = k4 >> 2, iy = k4 & 3;
+        const int b = nz == 1 ? bz : (int)__umulhi((uint32_t)bz, nz_magic);
+        const int zs = bz - b * nz;
+        const int lz = zs >= roz ? zs - roz : zs - roz + nz;
+        const int32_t h4[4] = {hv[u].x, hv[u].y, hv[u].z, hv[u].w};
+        const int32_t p4[4] = {pv[u].x, pv[u].y, pv[u].z, pv[u].w};
+#pragma unroll
+        for (int ix = 0; ix < 4; ix++) {
+          const int32_t h = h4[ix], p = p4[ix];
+          float v;
+          if (h >= 1) v = (float)((double)h / ((double)h + (double)p));
+          else v = p >= 1 ? 0.0f : __uint_as_float(kQNaN);
+          lden[(16 * ix + 4 * b + iy) * nzp + lz] = v;
+        }
+      }
+    }
   }
   __syncthreads();
   const int nq = (nz + 3) >> 2;

@@ -52,6 +52,26 @@ __device__ __forceinline__ int rank_below(const Mask128& m, int z) {
   return __popcll(m.lo) + __popcll(m.hi & ((1ull << zh) - 1ull));
 }
 
+// Position of the set bit of rank r (0 = lowest) of m; r < popcount(m).
+// Halving search: at each width s the bits of the lower s positions are
+// counted and the search moves up past them when r is not among them.
+__device__ __forceinline__ int select_bit(const Mask128& m, int r) {
+  const int pl = __popcll(m.lo);
+  unsigned long long w = r < pl ? m.lo : m.hi;
+  int pos = r < pl ? 0 : 64;
+  r = r < pl ? r : r - pl;
+#pragma unroll
+  for (int sh = 32; sh >= 1; sh >>= 1) {
+    const int c = __popcll(w & ((1ull << sh) - 1ull));
+    if (r >= c) {
+      r -= c;
+      w >>= sh;
+      pos += sh;
+    }
+  }
+  return pos;
+}
+
 // One lane per map column (window-local pixel).  Ground voxel = lowest
 // occupied voxel; height = its lowest return.  The positive-obstacle band is
 // the occupied voxels n_lo..n_hi above the ground voxel; its density is
@@ -456,10 +476,16 @@ __device__ __forceinline__ void lut_scan_body(int32_t* base, const int nb, int64
 
 // Pass 3: block = a storage region of 4 x 16 columns (four 4 x 4 bricks,
 // contiguous in memory).  The passes of the region are read in storage order
-// into LDS rows in window-local z order, then every lane writes four
-// consecutive table entries of one column (a transpose through LDS keeps both
-// sides coalesced; one 16-byte LDS read and one 16-byte store per lane).
+// (16-byte loads, all of a thread's loads in flight before its LDS stores)
+// into LDS rows in window-local z order.  The occupied voxels' records are
+// written one thread per voxel (the region's occupied voxels are numbered
+// column by column, so a voxel's rank is its column base plus its number
+// within the column, and every gather is issued at once).  Then every lane
+// writes four consecutive table entries of one column (a transpose through
+// LDS keeps both sides coalesced; one 16-byte LDS read and one 16-byte store
+// per lane).
 constexpr int kRegCols = 64;
+constexpr int kLutLoads = 4;  // 16-byte region loads per thread per batch
 
 // LDS row stride of a column's passes: a multiple of 4 words.
 __host__ __device__ __forceinline__ int lut_row(int nz) { return ((nz + 3) & ~3) + 4; }
@@ -468,78 +494,112 @@ __device__ __forceinline__ void lut_write_body(const LutArgs& a, const uint32_t 
                                                const int bxr, const int byr) {
   extern __shared__ __attribute__((aligned(16))) int32_t lpass[];  // [64][lut_row(nz)]
   __shared__ unsigned long long slo[kRegCols], shi[kRegCols];
-  __shared__ int32_t sbase[kRegCols];
+  __shared__ int32_t sbase[kRegCols], spre[kRegCols + 1];
   __shared__ int64_t scb[kRegCols], slut[kRegCols];
   const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz, W = a.d.W, roz = a.d.ro[2];
   const int nzp = lut_row(nz);
-  if (threadIdx.x < kRegCols) {
-    const int t = threadIdx.x;
-    const int ix = t >> 4, jy = t & 15;
-    const int sx = 4 * bxr + ix, sy = 16 * byr + jy;
-    Mask128 m = {0ull, 0ull};
-    int32_t base = 0;
-    int64_t cb = -1, lrow = 0;
-    if (sx < nx && sy < ny) {
-      const int x = sx - a.d.ro[0] + (sx < a.d.ro[0] ? nx : 0);
-      const int y = sy - a.d.ro[1] + (sy < a.d.ro[1] ? ny : 0);
-      const int c = x * ny + y;
-      m = local_mask(a.occ, (int64_t)sx * ny + sy, W, nz, roz);
-      base = a.block_base[c >> 6] + a.colpre[c];
-      cb = col_base(a.d, sx, sy);
-      lrow = (int64_t)c * nz;
-    }
-    slo[t] = m.lo;
-    shi[t] = m.hi;
-    sbase[t] = base;
-    scb[t] = cb;
-    slut[t] = lrow;
-  }
-  // storage-order read of the region: brick b (0..3), level z, lane16 = 4 iy + ix
+  const int tid = threadIdx.x;
+  // storage-order read of the region: 16-byte word k4 holds brick b, level
+  // zs, brick row iy (k4 = 4 (b nz + zs) + iy), voxels ix = 0..3
   const int nbricks = min(4, a.d.nby - 4 * byr);
-  const int64_t r0 = col_base(a.d, 4 * bxr, 16 * byr);
-  const int total = nbricks * nz * 16;
-  const int32_t* __restrict__ passes = a.passes;
-#pragma unroll 4
-  for (int k = threadIdx.x; k < total; k += kBlock) {
-    const int bz = k >> 4, l16 = k & 15;
-    const int b = nz == 1 ? bz : (int)__umulhi((uint32_t)bz, nz_magic);
-    const int zs = bz - b * nz;
-    const int lz = zs >= roz ? zs - roz : zs - roz + nz;
-    const int slot = (l16 & 3) * 16 + 4 * b + (l16 >> 2);
-    lpass[slot * nzp + lz] = passes[r0 + k];
+  const int nv4 = nbricks * nz * 4;
+  const int4* __restrict__ src = (const int4*)(a.passes + col_base(a.d, 4 * bxr, 16 * byr));
+  for (int k0 = 0; k0 < nv4; k0 += kLutLoads * kBlock) {
+    int4 v[kLutLoads];
+#pragma unroll
+    for (int u = 0; u < kLutLoads; u++) {
+      // clamped, not skipped: every lane loads (in bounds), the stores below
+      // skip the words past the region
+      v[u] = src[min(k0 + u * kBlock + tid, nv4 - 1)];
+    }
+    if (k0 == 0 && tid < kRegCols) {
+      // wave 0, after the first region loads are issued: the region's columns
+      // (masks, rank bases, occupied-count prefix)
+      Mask128 m = {0ull, 0ull};
+      int32_t base = 0;
+      int64_t cb = -1, lrow = 0;
+      const int sx = 4 * bxr + (tid >> 4), sy = 16 * byr + (tid & 15);
+      if (sx < nx && sy < ny) {
+        const int x = sx - a.d.ro[0] + (sx < a.d.ro[0] ? nx : 0);
+        const int y = sy - a.d.ro[1] + (sy < a.d.ro[1] ? ny : 0);
+        const int c = x * ny + y;
+        base = a.block_base[c >> 6] + a.colpre[c];
+        m = local_mask(a.occ, (int64_t)sx * ny + sy, W, nz, roz);
+        cb = col_base(a.d, sx, sy);
+        lrow = (int64_t)c * nz;
+      }
+      const int cnt = __popcll(m.lo) + __popcll(m.hi);
+      int incl = cnt;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (tid >= o) incl += y;
+      }
+      slo[tid] = m.lo;
+      shi[tid] = m.hi;
+      sbase[tid] = base;
+      scb[tid] = cb;
+      slut[tid] = lrow;
+      spre[tid] = incl - cnt;
+      if (tid == kRegCols - 1) spre[kRegCols] = incl;
+    }
+#pragma unroll
+    for (int u = 0; u < kLutLoads; u++) {
+      const int k4 = k0 + u * kBlock + tid;
+      if (k4 < nv4) {
+        const int bz = k4 >> 2, iy = k4 & 3;
+        const int b = nz == 1 ? bz : (int)__umulhi((uint32_t)bz, nz_magic);
+        const int zs = bz - b * nz;
+        const int lz = zs >= roz ? zs - roz : zs - roz + nz;
+        int32_t* row = lpass + (4 * b + iy) * nzp + lz;  // slot = 16 ix + 4 b + iy
+        row[0] = v[u].x;
+        row[16 * nzp] = v[u].y;
+        row[32 * nzp] = v[u].z;
+        row[48 * nzp] = v[u].w;
+      }
+    }
   }
   __syncthreads();
+  // records of the occupied voxels: voxel o of the region lies in the column t
+  // with spre[t] <= o < spre[t + 1], at the set bit of rank o - spre[t]
+  const int nocc = spre[kRegCols];
+  for (int o = tid; o < nocc; o += kBlock) {
+    int t = 0;
+#pragma unroll
+    for (int step = kRegCols / 2; step >= 1; step >>= 1)
+      if (spre[t + step] <= o) t += step;
+    const int r = o - spre[t];
+    const int32_t rank = sbase[t] + r;
+    if (rank < a.cap) {
+      const int z = select_bit(Mask128{slo[t], shi[t]}, r);
+      const int64_t idx = scb[t] + ((int64_t)wrap_add(z + roz, nz) << 4);
+      map_voxel_t d;
+      d.hits = a.hits[idx];
+      d.passes = lpass[t * nzp + z];
+      d.min_qz = a.minqz[idx];
+      a.data[rank] = d;
+    }
+  }
   // items (column t, quad q): window-local z = 4q .. 4q+3; qs quads per column
   // rounded up to a power of two so that t and q are shifts
   const int nq = (nz + 3) >> 2;
   const int qsh = nq > 1 ? 32 - __clz(nq - 1) : 0;
   const bool vec = (nz & 3) == 0 && ((uintptr_t)a.lut & 15) == 0;
-  for (int i = threadIdx.x; i < (kRegCols << qsh); i += kBlock) {
+  for (int i = tid; i < (kRegCols << qsh); i += kBlock) {
     const int t = i >> qsh, q = i & ((1 << qsh) - 1);
     if (q >= nq || scb[t] < 0) continue;
-    const Mask128 m = {slo[t], shi[t]};
+    const Mask128 mt = {slo[t], shi[t]};
     const int z0 = 4 * q;
     const int4 pv = *(const int4*)(lpass + t * nzp + z0);
     const int32_t p4[4] = {pv.x, pv.y, pv.z, pv.w};
-    int32_t rank = sbase[t] + rank_below(m, z0);
+    int32_t rank = sbase[t] + rank_below(mt, z0);
     int32_t v[4];
 #pragma unroll
     for (int e = 0; e < 4; e++) {
       const int z = z0 + e;
-      if (z < nz && test_bit(m, z)) {
-        v[e] = rank;
-        if (rank < a.cap) {
-          const int64_t idx = scb[t] + ((int64_t)wrap_add(z + roz, nz) << 4);
-          map_voxel_t d;
-          d.hits = a.hits[idx];
-          d.passes = p4[e];
-          d.min_qz = a.minqz[idx];
-          a.data[rank] = d;
-        }
-        rank++;
-      } else {
-        v[e] = -1 - p4[e];
-      }
+      const bool occ = z < nz && test_bit(mt, z);
+      v[e] = occ ? rank : -1 - p4[e];
+      rank += occ;
     }
     // the table is written once and not read back here: streaming stores
     int32_t* __restrict__ lut = a.lut + slut[t] + z0;

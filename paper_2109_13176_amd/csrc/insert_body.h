@@ -70,6 +70,7 @@ __device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
   int32_t q[3];
   PointFlags pf;
   const bool ray = point_pass<DISTINCT>(a, i, q, pf);
+  const HitReads hr = record_hit_issue(a, pf);  // completed after the block's returning atomic
   const bool nonfinite = pf.nonfinite, outrange = pf.outrange, hit = pf.hit, dhit = pf.dhit;
 
   int nseg = 0;
@@ -149,6 +150,7 @@ __device__ __forceinline__ void rays_body(const InsertArgs& a, const int blk) {
     pr[3] = s5;
   }
   __syncthreads();
+  record_hit_finish(a, pf, hr, q[2]);
   const int gw = blk * kRayWaves + wv;  // this group's rays: 64 gw .. 64 gw + 63
   const unsigned long long off = wbase[wv];
   for (int j = lane; j < maxseg; j += 64) a.witems[off + j] = make_int2(gw, j);

@@ -35,10 +35,15 @@ __device__ __forceinline__ int dominant_axis(const int32_t n[3]) {
 }
 
 // Transform of point i (in firing order) and its return: q = Q16 world
-// coordinates; records the hit when the return lies in the window.  Returns
-// true when the ray can be traversed.
+// coordinates.  When the return lies in the window, f.hit is set and f.e /
+// f.ow / f.ob locate its voxel (storage index, occupancy word and bit); the
+// caller records the hit (record_hit_*).  Returns true when the ray can be
+// traversed.
 struct PointFlags {
   bool nonfinite = false, outrange = false, hit = false, dhit = false;
+  int32_t e = 0;
+  int64_t ow = 0;
+  unsigned long long ob = 0;
 };
 
 template <bool DISTINCT>
@@ -89,13 +94,9 @@ __device__ __forceinline__ bool point_pass(const InsertArgs& a, const int i, int
     const int32_t ez = wrap_add(l[2] + a.d.ro[2], dims[2]);
     const int32_t col = ex * dims[1] + ey;
     const int32_t e = col_base(a.d, ex, ey) + (ez << 4);
-    atomicAdd(&a.hits[e], 1);
-    // min and or only move one way: a plain read that already satisfies
-    // the update makes the atomic unnecessary
-    if (q[2] < a.minqz[e]) atomicMin(&a.minqz[e], q[2]);
-    unsigned long long* ow = &a.occ[(int64_t)col * a.d.W + (ez >> 6)];
-    const unsigned long long ob = 1ull << (ez & 63);
-    if (!(*ow & ob)) atomicOr(ow, ob);
+    f.e = e;
+    f.ow = (int64_t)col * a.d.W + (ez >> 6);
+    f.ob = 1ull << (ez & 63);
     f.hit = true;
     if (DISTINCT) {
       const uint32_t bit = 1u << (e & 31);
@@ -104,6 +105,35 @@ __device__ __forceinline__ bool point_pass(const InsertArgs& a, const int i, int
     }
   }
   return true;
+}
+
+// Recording a hit takes a count, a minimum and an or.  The minimum and the or
+// only move one way, so a plain read that already satisfies the update makes
+// that atomic unnecessary.  The reads are issued first (record_hit_issue) and
+// the conditional atomics later (record_hit_finish), so their round trip can
+// overlap other work of the caller; a stale read only costs a redundant
+// atomic.
+struct HitReads {
+  int32_t mz = 0;
+  unsigned long long ow = 0;
+};
+
+__device__ __forceinline__ HitReads record_hit_issue(const InsertArgs& a, const PointFlags& f) {
+  HitReads r;
+  if (f.hit) {
+    r.mz = a.minqz[f.e];
+    r.ow = a.occ[f.ow];
+    atomicAdd(&a.hits[f.e], 1);
+  }
+  return r;
+}
+
+__device__ __forceinline__ void record_hit_finish(const InsertArgs& a, const PointFlags& f,
+                                                  const HitReads& r, const int32_t qz) {
+  if (f.hit) {
+    if (qz < r.mz) atomicMin(&a.minqz[f.e], qz);
+    if (!(r.ow & f.ob)) atomicOr(&a.occ[f.ow], f.ob);
+  }
 }
 
 // Voxel at which the ray S -> q enters world cell c along axis dm (c is not
