@@ -229,18 +229,35 @@ __device__ __forceinline__ void surface_body(const SurfaceArgs& a, const int H, 
   constexpr int kVW = kPix / 64;     // 64-pixel groups of the tile
   constexpr int kPer = kPix / NT;    // tile pixels per thread
   // stage the heights row by row (a wave per row, lanes along y); the
-  // ballot of each 64-cell piece is that row's mask word
-  for (int r = wv; r < T; r += kWaves) {
-    const int gx = gx0 + r;
-    const bool rowok = gx >= 0 && gx < a.nx;
-    for (int w = 0; w < MW; w++) {
-      const int k = 64 * w + lane;
-      const int gy = gy0 + k;
-      int32_t v = INT32_MIN;
-      if (k < T && rowok && gy >= 0 && gy < a.ny) v = a.hq[(int64_t)gx * a.ny + gy];
-      if (k < T) th[r * TS + k] = v;
-      const unsigned long long b = __ballot(v != INT32_MIN);
-      if (lane == 0) rmask[r * MW + w] = b;
+  // ballot of each 64-cell piece is that row's mask word.  A wave issues the
+  // loads of kSurfRows rows before it stores any (addresses clamped into the
+  // map, so every load is in bounds; cells outside it take the empty value).
+  constexpr int kSurfRows = 4;
+  for (int r0 = wv; r0 < T; r0 += kSurfRows * kWaves) {
+    int32_t v[kSurfRows][kMaxMaskWords];
+#pragma unroll
+    for (int j = 0; j < kSurfRows; j++) {
+      const int64_t rowc = (int64_t)min(max(gx0 + r0 + j * kWaves, 0), a.nx - 1) * a.ny;
+#pragma unroll
+      for (int w = 0; w < kMaxMaskWords; w++)
+        v[j][w] = a.hq[rowc + min(max(gy0 + 64 * w + lane, 0), a.ny - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < kSurfRows; j++) {
+      const int r = r0 + j * kWaves;
+      if (r >= T) break;
+      const int gx = gx0 + r;
+      const bool rowok = gx >= 0 && gx < a.nx;
+#pragma unroll
+      for (int w = 0; w < kMaxMaskWords; w++) {
+        if (w >= MW) break;
+        const int k = 64 * w + lane;
+        const int gy = gy0 + k;
+        const int32_t x = rowok && k < T && gy >= 0 && gy < a.ny ? v[j][w] : INT32_MIN;
+        if (k < T) th[r * TS + k] = x;
+        const unsigned long long b = __ballot(x != INT32_MIN);
+        if (lane == 0) rmask[r * MW + w] = b;
+      }
     }
   }
   __syncthreads();
