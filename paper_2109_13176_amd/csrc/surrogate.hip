@@ -211,81 +211,91 @@ __device__ __forceinline__ void stage16(Load load, Store store) {
   }
 }
 
-// NORM (first layer): x holds the raw fp32 features; each is normalised as
-// bf16((float)((f - mean) / std)) (double arithmetic) while staged, and the
-// block's own pixels are also written to xn, the layer input the backward
-// pass reads.
-template <int CIN, int TR, bool NORM>
-__global__ __launch_bounds__(TR * 64) void k_conv_mfma(const void* __restrict__ xin,
+// Two arrays staged as by stage16, all loads of both issued before any store.
+// Loads and stores are unconditional, item indexes clamped to the last item
+// (load(i) must read in bounds for every i < N; lanes past the end store
+// the last item again, the same bytes): a load or store under a lane
+// condition lets the compiler sink the load into it, or wait for it before
+// the next one.
+template <int N1, int N2, int NT, class Load1, class Store1, class Load2, class Store2>
+__device__ __forceinline__ void stage16x2(Load1 load1, Store1 store1, Load2 load2,
+                                          Store2 store2) {
+  constexpr int IT1 = (N1 + NT - 1) / NT, IT2 = (N2 + NT - 1) / NT;
+  uint4 v1[IT1], v2[IT2];
+#pragma unroll
+  for (int k = 0; k < IT1; k++) v1[k] = load1(min((int)threadIdx.x + k * NT, N1 - 1));
+#pragma unroll
+  for (int k = 0; k < IT2; k++) v2[k] = load2(min((int)threadIdx.x + k * NT, N2 - 1));
+  __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the stores
+#pragma unroll
+  for (int k = 0; k < IT1; k++) store1(min((int)threadIdx.x + k * NT, N1 - 1), v1[k]);
+#pragma unroll
+  for (int k = 0; k < IT2; k++) store2(min((int)threadIdx.x + k * NT, N2 - 1), v2[k]);
+}
+
+// Normalised first-layer input, one thread per pixel and 8-channel group:
+// xn = bf16((float)((f - mean) / std)) in double arithmetic.  The backward
+// pass reads xn as the first layer's input.
+__global__ __launch_bounds__(256) void k_norm(const float* __restrict__ feat,
+                                              const float* __restrict__ mean,
+                                              const float* __restrict__ stdv,
+                                              uint16_t* __restrict__ xn, int64_t items) {
+  static_assert(kFeat == 16, "two 8-channel groups per pixel");
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= items) return;
+  const int cq = (int)(i & 1);
+  const float4 f0 = ((const float4*)feat)[2 * i], f1 = ((const float4*)feat)[2 * i + 1];
+  const float4 m0 = ((const float4*)mean)[2 * cq], m1 = ((const float4*)mean)[2 * cq + 1];
+  const float4 s0 = ((const float4*)stdv)[2 * cq], s1 = ((const float4*)stdv)[2 * cq + 1];
+  const float fv[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+  const float mu[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+  const float sd[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+  uint16_t b[8];
+#pragma unroll
+  for (int j = 0; j < 8; j++) b[j] = to_bf16((float)(((double)fv[j] - (double)mu[j]) / (double)sd[j]));
+  ((uint4*)xn)[i] = make_uint4((uint32_t)b[0] | ((uint32_t)b[1] << 16),
+                               (uint32_t)b[2] | ((uint32_t)b[3] << 16),
+                               (uint32_t)b[4] | ((uint32_t)b[5] << 16),
+                               (uint32_t)b[6] | ((uint32_t)b[7] << 16));
+}
+
+template <int CIN, int TR>
+__global__ __launch_bounds__(TR * 64) void k_conv_mfma(const uint16_t* __restrict__ xin,
                                                        const uint16_t* __restrict__ w,
                                                        const float* __restrict__ bias,
-                                                       uint16_t* __restrict__ y, int H, int W,
-                                                       const float* __restrict__ mean,
-                                                       const float* __restrict__ stdv,
-                                                       uint16_t* __restrict__ xn) {
+                                                       uint16_t* __restrict__ y, int H, int W) {
   constexpr int PS = CIN + kPad;  // LDS stride of a pixel and of a weight row
   constexpr int NT = TR * 64;
   __shared__ __attribute__((aligned(16))) uint16_t sx[(TR + 2) * (kTC + 2) * PS];
   __shared__ __attribute__((aligned(16))) uint16_t sw[32 * 9 * PS];
+  __shared__ __attribute__((aligned(16))) float sb[32];
   const int r0 = blockIdx.y * TR, c0 = blockIdx.x * kTC;
   constexpr int Q = CIN / 8;  // 8-channel groups per pixel
   constexpr int NX = (TR + 2) * (kTC + 2) * Q;
-  auto in_tile = [&](int i, int64_t* e) {
-    const int pix = i / Q, cq = i - pix * Q;
-    const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
-    const int gr = r0 + tr - 1, gc = c0 + tc - 1;
-    *e = ((int64_t)gr * W + gc) * CIN + cq * 8;
-    return gr >= 0 && gr < H && gc >= 0 && gc < W;
-  };
-  if constexpr (NORM) {
-    // raw features: all loads of the thread first, then normalise and store
-    constexpr int IT = (NX + NT - 1) / NT;
-    float4 f[IT][2];
-#pragma unroll
-    for (int k = 0; k < IT; k++) {
-      const int i = (int)threadIdx.x + k * NT;
-      int64_t e = 0;
-      f[k][0] = f[k][1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (i < NX && in_tile(i, &e)) {
-        f[k][0] = *(const float4*)((const float*)xin + e);
-        f[k][1] = *(const float4*)((const float*)xin + e + 4);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < IT; k++) {
-      const int i = (int)threadIdx.x + k * NT;
-      if (i >= NX) continue;
-      int64_t e = 0;
-      const bool in = in_tile(i, &e);
-      const int pix = i / Q, cq = i - pix * Q;
-      const float fv[8] = {f[k][0].x, f[k][0].y, f[k][0].z, f[k][0].w,
-                           f[k][1].x, f[k][1].y, f[k][1].z, f[k][1].w};
-      uint16_t b[8];
-#pragma unroll
-      for (int j = 0; j < 8; j++) {
-        const int ch = cq * 8 + j;
-        b[j] = in ? to_bf16((float)(((double)fv[j] - (double)mean[ch]) / (double)stdv[ch])) : 0;
-      }
-      const uint4 v = make_uint4((uint32_t)b[0] | ((uint32_t)b[1] << 16),
-                                 (uint32_t)b[2] | ((uint32_t)b[3] << 16),
-                                 (uint32_t)b[4] | ((uint32_t)b[5] << 16),
-                                 (uint32_t)b[6] | ((uint32_t)b[7] << 16));
-      const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
-      if (in && tr >= 1 && tr <= TR && tc >= 1 && tc <= kTC) *(uint4*)(xn + e) = v;
-      *(uint4*)(sx + pix * PS + cq * 8) = v;
-    }
-  } else {
-    stage16<NX, NT>(
-        [&](int i) {
-          int64_t e = 0;
-          return in_tile(i, &e) ? *(const uint4*)((const uint16_t*)xin + e)
-                                : make_uint4(0u, 0u, 0u, 0u);
-        },
-        [&](int i, uint4 v) { *(uint4*)(sx + (i / Q) * PS + (i % Q) * 8) = v; });
-  }
-  stage16<32 * 9 * Q, NT>(
+  // the bias goes through LDS with the tiles: read from memory in the
+  // epilogue it would cost one more memory latency there.  Unconditional
+  // (lanes past the eighth rewrite the last quarter, same bytes).
+  const float4 bq = ((const float4*)bias)[min((int)threadIdx.x, 7)];
+  // weights and input tile in one round of loads
+  stage16x2<32 * 9 * Q, NX, NT>(
       [&](int i) { return *(const uint4*)(w + (i / Q) * CIN + (i % Q) * 8); },
-      [&](int i, uint4 v) { *(uint4*)(sw + (i / Q) * PS + (i % Q) * 8) = v; });
+      [&](int i, uint4 v) { *(uint4*)(sw + (i / Q) * PS + (i % Q) * 8) = v; },
+      [&](int i) {
+        // halo pixels outside the map read a clamped pixel; the store zeroes them
+        const int pix = i / Q, cq = i - pix * Q;
+        const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
+        const int gr = min(max(r0 + tr - 1, 0), H - 1), gc = min(max(c0 + tc - 1, 0), W - 1);
+        return *(const uint4*)(xin + ((int64_t)gr * W + gc) * CIN + cq * 8);
+      },
+      [&](int i, uint4 v) {
+        const int pix = i / Q, tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
+        const int gr = r0 + tr - 1, gc = c0 + tc - 1;
+        // bitwise: a branch here would let the compiler sink the load into it
+        const bool ok = (gr >= 0) & (gr < H) & (gc >= 0) & (gc < W);
+        const uint32_t m = ok ? ~0u : 0u;
+        *(uint4*)(sx + pix * PS + (i % Q) * 8) = make_uint4(v.x & m, v.y & m, v.z & m, v.w & m);
+      });
+  ((float4*)sb)[min((int)threadIdx.x, 7)] = bq;
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -323,7 +333,7 @@ __global__ __launch_bounds__(TR * 64) void k_conv_mfma(const void* __restrict__ 
 #pragma unroll
   for (int mt = 0; mt < 2; mt++)
 #pragma unroll
-    for (int e = 0; e < 4; e++) bv[mt][e] = bias[mt * 16 + 4 * lk + e];
+    for (int e = 0; e < 4; e++) bv[mt][e] = sb[mt * 16 + 4 * lk + e];
 #pragma unroll
   for (int mt = 0; mt < 2; mt++)
 #pragma unroll
@@ -556,29 +566,47 @@ __global__ __launch_bounds__(TR * 64) void k_bwd_data_mfma(const uint16_t* __res
                                                            uint16_t* __restrict__ dpl, int H,
                                                            int W) {
   constexpr int C = 32, PS = C + kPad, NT = TR * 64, Q = C / 8;
+  constexpr int NX = (TR + 2) * (kTC + 2) * Q, IX = (NX + NT - 1) / NT;
   __shared__ __attribute__((aligned(16))) uint16_t sx[(TR + 2) * (kTC + 2) * PS];
   __shared__ __attribute__((aligned(16))) uint16_t sw[32 * 9 * PS];
   const int r0 = blockIdx.y * TR, c0 = blockIdx.x * kTC;
-  stage16<32 * 9 * Q, NT>(
+  // tile item i of a dz part: clamped (in-bounds) load, zero outside the map
+  // applied at the store (no lane conditions around the loads)
+  auto tile_load = [&](const uint16_t* src, int i) {
+    const int pix = i / Q, cq = i - pix * Q;
+    const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
+    const int gr = min(max(r0 + tr - 1, 0), H - 1), gc = min(max(c0 + tc - 1, 0), W - 1);
+    return *(const uint4*)(src + ((int64_t)gr * W + gc) * C + cq * 8);
+  };
+  auto tile_store = [&](int i, uint4 v) {
+    const int pix = i / Q, tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
+    const int gr = r0 + tr - 1, gc = c0 + tc - 1;
+    const uint32_t m = ((gr >= 0) & (gr < H) & (gc >= 0) & (gc < W)) ? ~0u : 0u;
+    *(uint4*)(sx + pix * PS + (i % Q) * 8) = make_uint4(v.x & m, v.y & m, v.z & m, v.w & m);
+  };
+  // the transposed weights and the high part of dz in one round of loads
+  stage16x2<32 * 9 * Q, NX, NT>(
       [&](int i) { return *(const uint4*)(wt + (i / Q) * C + (i % Q) * 8); },
-      [&](int i, uint4 v) { *(uint4*)(sw + (i / Q) * PS + (i % Q) * 8) = v; });
+      [&](int i, uint4 v) { *(uint4*)(sw + (i / Q) * PS + (i % Q) * 8) = v; },
+      [&](int i) { return tile_load(dzh, i); }, tile_store);
+  // the low part's loads stay in flight during the high part's products
+  uint4 lo[IX];
+#pragma unroll
+  for (int k = 0; k < IX; k++) lo[k] = tile_load(dzl, min((int)threadIdx.x + k * NT, NX - 1));
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   v4f acc[2][4];
   for (int m = 0; m < 2; m++)
     for (int n = 0; n < 4; n++) acc[m][n] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
   for (int part = 0; part < 2; part++) {
-    const uint16_t* src = part ? dzl : dzh;
-    stage16<(TR + 2) * (kTC + 2) * Q, NT>(
-        [&](int i) {
-          const int pix = i / Q, cq = i - pix * Q;
-          const int tr = pix / (kTC + 2), tc = pix - tr * (kTC + 2);
-          const int gr = r0 + tr - 1, gc = c0 + tc - 1;
-          return (gr >= 0 && gr < H && gc >= 0 && gc < W)
-                     ? *(const uint4*)(src + ((int64_t)gr * W + gc) * C + cq * 8)
-                     : make_uint4(0u, 0u, 0u, 0u);
-        },
-        [&](int i, uint4 v) { *(uint4*)(sx + (i / Q) * PS + (i % Q) * 8) = v; });
+    if (part == 1) {
+      // (the scheduler would hoist the low part's masking into the high
+      // part's products, and with it the wait for its loads)
+      __builtin_amdgcn_sched_barrier(0);
+      __syncthreads();  // every wave is done with the high part's tile
+#pragma unroll
+      for (int k = 0; k < IX; k++) tile_store(min((int)threadIdx.x + k * NT, NX - 1), lo[k]);
+    }
     __syncthreads();
 #pragma unroll
     for (int tap = 0; tap < 9; tap++) {
@@ -593,9 +621,18 @@ __global__ __launch_bounds__(TR * 64) void k_bwd_data_mfma(const uint16_t* __res
         acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc[1][nt], 0, 0, 0);
       }
     }
-    __syncthreads();  // the tile is restaged for the low part
   }
+  // the ReLU mask of the layer below: all eight of a lane's reads in flight
+  // (clamped into the map; pixels outside it are not written)
   const int r = r0 + wv;
+  uint2 xmv[2][4];
+#pragma unroll
+  for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++) {
+      const int col = min(c0 + nt * 16 + lr, W - 1);
+      xmv[mt][nt] = *(const uint2*)(x + ((int64_t)min(r, H - 1) * W + col) * C + mt * 16 + 4 * lk);
+    }
   if (r >= H) return;
 #pragma unroll
   for (int mt = 0; mt < 2; mt++)
@@ -605,7 +642,7 @@ __global__ __launch_bounds__(TR * 64) void k_bwd_data_mfma(const uint16_t* __res
       if (col >= W) continue;
       const int ci0 = mt * 16 + 4 * lk;
       const int64_t o = ((int64_t)r * W + col) * C + ci0;
-      const uint2 xm = *(const uint2*)(x + o);
+      const uint2 xm = xmv[mt][nt];
       const uint16_t xs[4] = {(uint16_t)(xm.x & 0xFFFFu), (uint16_t)(xm.x >> 16),
                               (uint16_t)(xm.y & 0xFFFFu), (uint16_t)(xm.y >> 16)};
       float v[4];
@@ -679,38 +716,62 @@ __global__ __launch_bounds__(256) void k_bwd_weight_mfma(const uint16_t* __restr
   v8bf ones;
 #pragma unroll
   for (int e = 0; e < 8; e++) ones[e] = (__bf16)1.0f;
-  for (int tile = 0; tile < NTILE; tile++) {
+  // Tile t's loads (both dz parts and the x tile with its halo) are issued
+  // before tile t - 1's products and stored to LDS after them: clamped
+  // in-bounds loads, zeros outside the map applied at the store.
+  constexpr int NZ = 2 * kWgRows * kTC * 4, NXI = XR * XC * (CIN / 8);
+  constexpr int IZ = (NZ + 255) / 256, IXI = (NXI + 255) / 256;
+  uint4 vz[IZ], vx[IXI];
+  auto load_tile = [&](int tile) {
     const int r0 = (blockIdx.y * NTILE + tile) * kWgRows;
+#pragma unroll
+    for (int k = 0; k < IZ; k++) {
+      const int i = min((int)threadIdx.x + k * 256, NZ - 1);
+      const int hl = i / (kWgRows * kTC * 4), rem = i - hl * (kWgRows * kTC * 4);
+      const int pix = rem >> 2, cg = rem & 3;
+      const int gr = min(r0 + pix / kTC, H - 1), gc = min(c0 + pix % kTC, W - 1);
+      vz[k] = *(const uint4*)((hl ? dzl : dzh) + ((int64_t)gr * W + gc) * CO + cg * 8);
+    }
+#pragma unroll
+    for (int k = 0; k < IXI; k++) {
+      const int i = min((int)threadIdx.x + k * 256, NXI - 1);
+      const int pix = i / (CIN / 8), cq = i - pix * (CIN / 8);
+      const int tr = pix / XC, tc = pix - tr * XC;
+      const int gr = min(max(r0 + tr - 1, 0), H - 1), gc = min(max(c0 + tc - 1, 0), W - 1);
+      vx[k] = *(const uint4*)(x + ((int64_t)gr * W + gc) * CIN + cq * 8);
+    }
+  };
+  auto store_tile = [&](int tile) {
+    const int r0 = (blockIdx.y * NTILE + tile) * kWgRows;
+#pragma unroll
+    for (int k = 0; k < IZ; k++) {
+      const int i = min((int)threadIdx.x + k * 256, NZ - 1);
+      const int rem = i % (kWgRows * kTC * 4), pix = rem >> 2;
+      const int gr = r0 + pix / kTC, gc = c0 + pix % kTC;
+      const uint32_t m = ((gr < H) & (gc < W)) ? ~0u : 0u;
+      uint2* d = (uint2*)(sdz + (i >> 2) * kWgPZ + (i & 3) * 8);
+      d[0] = make_uint2(vz[k].x & m, vz[k].y & m);
+      d[1] = make_uint2(vz[k].z & m, vz[k].w & m);
+    }
+#pragma unroll
+    for (int k = 0; k < IXI; k++) {
+      const int i = min((int)threadIdx.x + k * 256, NXI - 1);
+      const int pix = i / (CIN / 8), tr = pix / XC, tc = pix - tr * XC;
+      const int gr = r0 + tr - 1, gc = c0 + tc - 1;
+      const uint32_t m = ((gr >= 0) & (gr < H) & (gc >= 0) & (gc < W)) ? ~0u : 0u;
+      uint2* d = (uint2*)(sx + pix * PX + (i % (CIN / 8)) * 8);
+      d[0] = make_uint2(vx[k].x & m, vx[k].y & m);
+      d[1] = make_uint2(vx[k].z & m, vx[k].w & m);
+    }
+  };
+  load_tile(0);
+  for (int tile = 0; tile < NTILE; tile++) {
+    // (keeps the masking of the stores below out of the previous products)
+    __builtin_amdgcn_sched_barrier(0);
     __syncthreads();  // the previous tile has been read
-    stage16<2 * kWgRows * kTC * 4, 256>(
-        [&](int i) {
-          const int hl = i / (kWgRows * kTC * 4), rem = i - hl * (kWgRows * kTC * 4);
-          const int pix = rem >> 2, cg = rem & 3;
-          const int gr = r0 + pix / kTC, gc = c0 + pix % kTC;
-          return (gr < H && gc < W)
-                     ? *(const uint4*)((hl ? dzl : dzh) + ((int64_t)gr * W + gc) * CO + cg * 8)
-                     : make_uint4(0u, 0u, 0u, 0u);
-        },
-        [&](int i, uint4 v) {
-          uint2* d = (uint2*)(sdz + (i >> 2) * kWgPZ + (i & 3) * 8);
-          d[0] = make_uint2(v.x, v.y);
-          d[1] = make_uint2(v.z, v.w);
-        });
-    stage16<XR * XC * (CIN / 8), 256>(
-        [&](int i) {
-          const int pix = i / (CIN / 8), cq = i - pix * (CIN / 8);
-          const int tr = pix / XC, tc = pix - tr * XC;
-          const int gr = r0 + tr - 1, gc = c0 + tc - 1;
-          return (gr >= 0 && gr < H && gc >= 0 && gc < W)
-                     ? *(const uint4*)(x + ((int64_t)gr * W + gc) * CIN + cq * 8)
-                     : make_uint4(0u, 0u, 0u, 0u);
-        },
-        [&](int i, uint4 v) {
-          uint2* d = (uint2*)(sx + (i / (CIN / 8)) * PX + (i % (CIN / 8)) * 8);
-          d[0] = make_uint2(v.x, v.y);
-          d[1] = make_uint2(v.z, v.w);
-        });
+    store_tile(tile);
     __syncthreads();
+    if (tile + 1 < NTILE) load_tile(tile + 1);
     for (int r = rs; r < kWgRows; r += RSPLIT) {
 #pragma unroll
       for (int kc = 0; kc < kTC / 32; kc++) {
@@ -1032,12 +1093,14 @@ int32_t st_of(hipError_t e) {
 hipError_t forward_all(sgt_net_t* n, const float* feat, float* out) {
   const int H = n->H, W = n->W;
   dim3 g4((W + kTC - 1) / kTC, (H + 3) / 4), g8((W + kTC - 1) / kTC, (H + 7) / 8);
-  hipLaunchKernelGGL((k_conv_mfma<16, 4, true>), g4, dim3(256), 0, n->stream, (const void*)feat,
-                     n->wbf[0], n->bias[0], n->act[1], H, W, n->mean, n->stdv, n->act[0]);
+  const int64_t items = (int64_t)H * W * 2;
+  hipLaunchKernelGGL(k_norm, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, n->stream, feat,
+                     n->mean, n->stdv, n->act[0], items);
+  hipLaunchKernelGGL((k_conv_mfma<16, 4>), g4, dim3(256), 0, n->stream, n->act[0], n->wbf[0],
+                     n->bias[0], n->act[1], H, W);
   for (int l = 1; l < 4; l++)
-    hipLaunchKernelGGL((k_conv_mfma<32, 8, false>), g8, dim3(512), 0, n->stream,
-                       (const void*)n->act[l], n->wbf[l], n->bias[l], n->act[l + 1], H, W,
-                       (const float*)nullptr, (const float*)nullptr, (uint16_t*)nullptr);
+    hipLaunchKernelGGL((k_conv_mfma<32, 8>), g8, dim3(512), 0, n->stream, n->act[l], n->wbf[l],
+                       n->bias[l], n->act[l + 1], H, W);
   hipLaunchKernelGGL(k_conv_out, g8, dim3(512), 0, n->stream, n->act[4], n->wbf[4], n->bias[4],
                      out, H, W);
   return hipGetLastError();
