@@ -483,17 +483,29 @@ __global__ __launch_bounds__(512) void k_bwd_data_out(const float* __restrict__ 
                                                       uint16_t* __restrict__ dph,
                                                       uint16_t* __restrict__ dpl, int H, int W) {
   constexpr int TR = 8, C = 32, XC = kTC + 2;
-  __shared__ float sdz[(TR + 2) * XC * 2];
+  constexpr int NP = (TR + 2) * XC, IP = (NP + 511) / 512;
+  __shared__ float sdz[NP * 2];
   const int r0 = blockIdx.y * TR, c0 = blockIdx.x * kTC;
-  for (int i = threadIdx.x; i < (TR + 2) * XC; i += 512) {
+  // the dz tile with its halo: clamped loads all in flight, zeros outside
+  // the map applied at the store (lanes past the end rewrite the last pixel)
+  float2 vd[IP];
+#pragma unroll
+  for (int k = 0; k < IP; k++) {
+    const int i = min((int)threadIdx.x + k * 512, NP - 1);
     const int tr = i / XC, tc = i - tr * XC;
-    const int gr = r0 + tr - 1, gc = c0 + tc - 1;
-    float2 v = make_float2(0.0f, 0.0f);
-    if (gr >= 0 && gr < H && gc >= 0 && gc < W) v = *(const float2*)(dz + ((int64_t)gr * W + gc) * 2);
-    sdz[2 * i] = v.x;
-    sdz[2 * i + 1] = v.y;
+    const int gr = min(max(r0 + tr - 1, 0), H - 1), gc = min(max(c0 + tc - 1, 0), W - 1);
+    vd[k] = *(const float2*)(dz + ((int64_t)gr * W + gc) * 2);
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = r0 + wv;
+  // the ReLU mask of the layer below for all of the lane's outputs
+  uint2 xmv[kTC / 16][2];
+#pragma unroll
+  for (int nt = 0; nt < kTC / 16; nt++)
+#pragma unroll
+    for (int mt = 0; mt < 2; mt++)
+      xmv[nt][mt] = *(const uint2*)(x + ((int64_t)min(r, H - 1) * W + min(c0 + nt * 16 + (lane & 15), W - 1)) * C +
+                                    mt * 16 + 4 * (lane >> 4));
   const int lr = lane & 15, kg = lane >> 4;
   // A: row ci = 16 mt + lr, k = 8 kg + j -> (t, co) = (k / 2, k % 2)
   v8bf a[2];
@@ -505,8 +517,16 @@ __global__ __launch_bounds__(512) void k_bwd_data_out(const float* __restrict__ 
       const uint16_t wb = k < 18 ? w[(co * 9 + tap) * C + 16 * mt + lr] : (uint16_t)0;
       a[mt][j] = __builtin_bit_cast(__bf16, wb);
     }
+#pragma unroll
+  for (int k = 0; k < IP; k++) {
+    const int i = min((int)threadIdx.x + k * 512, NP - 1);
+    const int tr = i / XC, tc = i - tr * XC;
+    const int gr = r0 + tr - 1, gc = c0 + tc - 1;
+    const bool ok = (gr >= 0) & (gr < H) & (gc >= 0) & (gc < W);
+    sdz[2 * i] = ok ? vd[k].x : 0.0f;
+    sdz[2 * i + 1] = ok ? vd[k].y : 0.0f;
+  }
   __syncthreads();
-  const int r = r0 + wv;
 #pragma unroll
   for (int nt = 0; nt < kTC / 16; nt++) {
     const int pc = nt * 16 + lr;  // tile column of this lane's pixel
@@ -529,7 +549,7 @@ __global__ __launch_bounds__(512) void k_bwd_data_out(const float* __restrict__ 
     for (int mt = 0; mt < 2; mt++) {
       const int ci0 = mt * 16 + 4 * kg;
       const int64_t o = ((int64_t)r * W + col) * C + ci0;
-      const uint2 xm = *(const uint2*)(x + o);
+      const uint2 xm = xmv[nt][mt];
       const uint16_t xs[4] = {(uint16_t)(xm.x & 0xFFFFu), (uint16_t)(xm.x >> 16),
                               (uint16_t)(xm.y & 0xFFFFu), (uint16_t)(xm.y >> 16)};
       uint16_t hi[4], lo[4];
@@ -859,31 +879,51 @@ __global__ __launch_bounds__(256) void k_bwd_weight_out(const float* __restrict_
   v8bf ones;
 #pragma unroll
   for (int e = 0; e < 8; e++) ones[e] = (__bf16)1.0f;
-  for (int tile = 0; tile < NTILE; tile++) {
+  // Tile t's loads (dz, one pixel per thread, and the x tile with its halo)
+  // are issued before tile t - 1's products and stored to LDS after them:
+  // clamped in-bounds loads, zeros outside the map applied at the store.
+  static_assert(kWgRows * kTC == 256, "one dz pixel per thread");
+  constexpr int NXI = XR * XC * (CIN / 8), IXI = (NXI + 255) / 256;
+  float2 vz;
+  uint4 vx[IXI];
+  auto load_tile = [&](int tile) {
     const int r0 = (blockIdx.y * NTILE + tile) * kWgRows;
-    __syncthreads();  // the previous tile has been read (and the zero fill is done)
-    {
-      const int pix = threadIdx.x;  // kWgRows * kTC == 256 pixels, one per thread
-      const int gr = r0 + pix / kTC, gc = c0 + pix % kTC;
-      float2 v = make_float2(0.0f, 0.0f);
-      if (gr < H && gc < W) v = *(const float2*)(dz + ((int64_t)gr * W + gc) * CO);
-      *(uint32_t*)(sdz + pix * PZ) = (uint32_t)to_bf16(v.x) | ((uint32_t)to_bf16(v.y) << 16);
+    const int pix = threadIdx.x;
+    vz = *(const float2*)(dz + ((int64_t)min(r0 + pix / kTC, H - 1) * W + min(c0 + pix % kTC, W - 1)) * CO);
+#pragma unroll
+    for (int k = 0; k < IXI; k++) {
+      const int i = min((int)threadIdx.x + k * 256, NXI - 1);
+      const int pix = i / (CIN / 8), cq = i - pix * (CIN / 8);
+      const int tr = pix / XC, tc = pix - tr * XC;
+      const int gr = min(max(r0 + tr - 1, 0), H - 1), gc = min(max(c0 + tc - 1, 0), W - 1);
+      vx[k] = *(const uint4*)(x + ((int64_t)gr * W + gc) * CIN + cq * 8);
     }
-    stage16<XR * XC * (CIN / 8), 256>(
-        [&](int i) {
-          const int pix = i / (CIN / 8), cq = i - pix * (CIN / 8);
-          const int tr = pix / XC, tc = pix - tr * XC;
-          const int gr = r0 + tr - 1, gc = c0 + tc - 1;
-          return (gr >= 0 && gr < H && gc >= 0 && gc < W)
-                     ? *(const uint4*)(x + ((int64_t)gr * W + gc) * CIN + cq * 8)
-                     : make_uint4(0u, 0u, 0u, 0u);
-        },
-        [&](int i, uint4 v) {
-          uint2* d = (uint2*)(sx + (i / (CIN / 8)) * PX + (i % (CIN / 8)) * 8);
-          d[0] = make_uint2(v.x, v.y);
-          d[1] = make_uint2(v.z, v.w);
-        });
+  };
+  auto store_tile = [&](int tile) {
+    const int r0 = (blockIdx.y * NTILE + tile) * kWgRows;
+    const int pix = threadIdx.x;
+    const bool zok = (r0 + pix / kTC < H) & (c0 + pix % kTC < W);
+    const float2 v = zok ? vz : make_float2(0.0f, 0.0f);
+    *(uint32_t*)(sdz + pix * PZ) = (uint32_t)to_bf16(v.x) | ((uint32_t)to_bf16(v.y) << 16);
+#pragma unroll
+    for (int k = 0; k < IXI; k++) {
+      const int i = min((int)threadIdx.x + k * 256, NXI - 1);
+      const int pix = i / (CIN / 8), tr = pix / XC, tc = pix - tr * XC;
+      const int gr = r0 + tr - 1, gc = c0 + tc - 1;
+      const uint32_t m = ((gr >= 0) & (gr < H) & (gc >= 0) & (gc < W)) ? ~0u : 0u;
+      uint2* d = (uint2*)(sx + pix * PX + (i % (CIN / 8)) * 8);
+      d[0] = make_uint2(vx[k].x & m, vx[k].y & m);
+      d[1] = make_uint2(vx[k].z & m, vx[k].w & m);
+    }
+  };
+  load_tile(0);
+  for (int tile = 0; tile < NTILE; tile++) {
+    // (keeps the masking of the stores below out of the previous products)
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();  // the previous tile has been read (and the zero fill is done)
+    store_tile(tile);
     __syncthreads();
+    if (tile + 1 < NTILE) load_tile(tile + 1);
     for (int r = rs; r < kWgRows; r += 2) {
 #pragma unroll
       for (int kc = 0; kc < kTC / 32; kc++) {
@@ -939,14 +979,12 @@ __global__ __launch_bounds__(kRedWaves * 64) void k_reduce_grad(const float* __r
   if (o < np) {
     constexpr int U = 8;
     for (int b0 = w; b0 < nb; b0 += kRedWaves * U) {
+      // clamped loads (in bounds, no lane condition to wait on), masked adds
       float v[U];
 #pragma unroll
-      for (int u = 0; u < U; u++) {
-        const int b = b0 + kRedWaves * u;
-        v[u] = b < nb ? part[(int64_t)b * np + o] : 0.0f;
-      }
+      for (int u = 0; u < U; u++) v[u] = part[(int64_t)min(b0 + kRedWaves * u, nb - 1) * np + o];
 #pragma unroll
-      for (int u = 0; u < U; u++) s += (double)v[u];
+      for (int u = 0; u < U; u++) s += b0 + kRedWaves * u < nb ? (double)v[u] : 0.0;
     }
   }
   ws[w][lane] = s;
