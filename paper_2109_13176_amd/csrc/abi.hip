@@ -649,7 +649,8 @@ int32_t map_insert_scan(map_t* m, const float* xyz_dev, int64_t n, const float p
   prof_end(m, pm0);
   const bool distinct = (flags & MAP_STATS_DISTINCT) != 0;
   m->last_distinct = distinct;
-  if (e == hipSuccess) e = hipMemsetAsync(m->stats, 0, kStatsBytes, m->stream);
+  // the segment counters of stats start at zero: zeroed at creation and by
+  // the sensor-box fold that ends every insert with points
   if (distinct && e == hipSuccess) {
     const int64_t words = (n_store(m) + 31) / 32;
     if (!m->touch) e = dmalloc(&m->touch, words * 2 * 4);

@@ -461,8 +461,21 @@ __device__ __forceinline__ void lut_scan_body(int32_t* base, const int nb, int64
   const int t = threadIdx.x;
   const int per = (nb + NT - 1) / NT;
   const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
+  // the thread's counts in chunks of 8 loads in flight (clamped in-bounds
+  // loads, masked sums); the first chunk stays in registers for the writes
+  constexpr int kChunk = 8;
+  int32_t v0[kChunk];
   int64_t s = 0;
-  for (int b = b0; b < b1; b++) s += base[b];
+  for (int c = b0; c < b1; c += kChunk) {
+    int32_t v[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; k++) v[k] = base[min(c + k, nb - 1)];
+#pragma unroll
+    for (int k = 0; k < kChunk; k++) {
+      if (c + k < b1) s += v[k];
+      if (c == b0) v0[k] = v[k];
+    }
+  }
   const int lane = __lane_id(), w = t >> 6;
   int64_t v = s;
 #pragma unroll
@@ -483,7 +496,14 @@ __device__ __forceinline__ void lut_scan_body(int32_t* base, const int nb, int64
   }
   __syncthreads();
   int64_t run = wsum[w] + v - s;  // exclusive prefix of this thread's range
-  for (int b = b0; b < b1; b++) {
+#pragma unroll
+  for (int k = 0; k < kChunk; k++) {
+    if (b0 + k < b1) {
+      base[b0 + k] = (int32_t)run;
+      run += v0[k];
+    }
+  }
+  for (int b = b0 + kChunk; b < b1; b++) {
     const int32_t q = base[b];
     base[b] = (int32_t)run;
     run += q;

@@ -459,9 +459,12 @@ static_assert(kBoxReps % kFoldReps == 0, "replica groups");
 
 constexpr int kFoldCellBlocks = (kBoxCells + kBlock - 1) / kBlock;
 
-// Fold block (cell block bx, replica group by) of one map.
+// Fold block (cell block bx, replica group by) of one map.  Block (0, 0)
+// also zeroes the ray pass's segment counters for the next insert (the
+// traversal, which read them, has finished).
 template <bool DISTINCT>
 __device__ __forceinline__ void box_fold_body(const InsertArgs& a, const int bx, const int by) {
+  if (bx == 0 && by == 0 && threadIdx.x < kStripes) a.stats[8 + threadIdx.x] = 0ull;
   const int i = bx * kBlock + threadIdx.x;
   int n_dpass = 0;
   if (i < kBoxCells) {
