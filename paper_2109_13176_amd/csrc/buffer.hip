@@ -155,6 +155,16 @@ __global__ __launch_bounds__(kBrickThreads) void k_slot_write(SlotArgs a) {
         bits |= (unsigned)(m & 1ull) << e;
       }
     }
+    // the item's words are read before the rank scan, so their latency
+    // overlaps it: passes always, hits and lowest returns (one 16-byte load
+    // each) where a voxel of the item is occupied
+    const int64_t s = s_b + 16 * z + 4 * q;
+    int4 p = make_int4(0, 0, 0, 0), h4, m4;
+    if (i < items) p = *(const int4*)(a.passes + s);
+    if (bits) {
+      h4 = *(const int4*)(a.hits + s);
+      m4 = *(const int4*)(a.minqz + s);
+    }
     const int c = __popc(bits);
     int incl = c;
 #pragma unroll
@@ -174,18 +184,18 @@ __global__ __launch_bounds__(kBrickThreads) void k_slot_write(SlotArgs a) {
     int32_t rank = run + before + incl - c;
     run += total;
     if (i < items) {
-      const int64_t s = s_b + 16 * z + 4 * q;
-      const int4 p = *(const int4*)(a.passes + s);
       const int32_t pv[4] = {p.x, p.y, p.z, p.w};
       int32_t v[4];
 #pragma unroll
       for (int e = 0; e < 4; e++) {
         if ((bits >> e) & 1u) {
           if (rank < a.cap) {
+            const int32_t hv[4] = {h4.x, h4.y, h4.z, h4.w};
+            const int32_t mv[4] = {m4.x, m4.y, m4.z, m4.w};
             map_voxel_t dv;
-            dv.hits = a.hits[s + e];
+            dv.hits = hv[e];
             dv.passes = pv[e];
-            dv.min_qz = a.minqz[s + e];
+            dv.min_qz = mv[e];
             a.data[rank] = dv;
           }
           a.hits[s + e] = 0;
@@ -253,6 +263,59 @@ __device__ __forceinline__ void sum_maps(const CombineArgs& a, const int64_t s,
   }
 }
 
+// The same with the tables of kSumBatch maps read at once (for the full
+// combine, where every item reads every map; the in-place update's rare full
+// recombinations keep the lean one-map-at-a-time form above).
+__device__ __forceinline__ void sum_maps_batched(const CombineArgs& a, const int64_t s,
+                                         const int32_t gx[4], const int32_t gy,
+                                         const int32_t gz, const unsigned mask, int32_t h[4],
+                                         int32_t p[4], int32_t mq[4]) {
+  const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    if ((mask >> e) & 1u) {
+      h[e] = 0;
+      p[e] = 0;
+      mq[e] = INT32_MAX;
+    }
+  }
+  // the tables of kSumBatch maps are read at once (every map's table holds
+  // index s, so the loads need no window test; clamped to the last map),
+  // then each map's entries are taken where its window holds the voxel
+  constexpr int kSumBatch = 8;
+  for (int k0 = 0; k0 < a.k; k0 += kSumBatch) {
+    int4 vb[kSumBatch];
+#pragma unroll
+    for (int j = 0; j < kSumBatch; j++) vb[j] = *(const int4*)(a.lut[min(k0 + j, a.k - 1)] + s);
+#pragma unroll
+    for (int j = 0; j < kSumBatch; j++) {
+      const int k = k0 + j;
+      if (k >= a.k) break;
+      if ((uint32_t)(gy - a.org[k][1]) >= (uint32_t)ny ||
+          (uint32_t)(gz - a.org[k][2]) >= (uint32_t)nz)
+        continue;
+      bool in[4];
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        in[e] = ((mask >> e) & 1u) && (uint32_t)(gx[e] - a.org[k][0]) < (uint32_t)nx;
+      const int32_t v[4] = {vb[j].x, vb[j].y, vb[j].z, vb[j].w};
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        if (!in[e]) continue;
+        if (v[e] >= 0) {
+          if (v[e] >= a.cap[k]) continue;
+          const map_voxel_t dv = a.data[k][v[e]];
+          h[e] += dv.hits;
+          p[e] += dv.passes;
+          mq[e] = min(mq[e], dv.min_qz);
+        } else {
+          p[e] += -1 - v[e];
+        }
+      }
+    }
+  }
+}
+
 // World coordinates of an item's voxels in the combined window.
 __device__ __forceinline__ unsigned item_world(const CombineArgs& a, const int bx, const int by,
                                                const int z, const int q, int32_t gx[4],
@@ -299,7 +362,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_combine(const CombineArgs a) 
     const unsigned valid = item_world(a, bx, by, z, q, gx, gy, gz);
     int32_t h[4] = {0, 0, 0, 0}, p[4] = {0, 0, 0, 0};
     int32_t mq[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
-    sum_maps(a, s, gx, gy, gz, valid, h, p, mq);
+    sum_maps_batched(a, s, gx, gy, gz, valid, h, p, mq);
     *(int4*)(a.hits + s) = make_int4(h[0], h[1], h[2], h[3]);
     *(int4*)(a.passes + s) = make_int4(p[0], p[1], p[2], p[3]);
     *(int4*)(a.minqz + s) = make_int4(mq[0], mq[1], mq[2], mq[3]);
