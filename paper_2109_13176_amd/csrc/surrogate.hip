@@ -962,37 +962,51 @@ __global__ __launch_bounds__(256) void k_bwd_weight_out(const float* __restrict_
 }
 
 
-// Fixed-order (deterministic) reduction of the weight-gradient partials,
-// scaled by 1 / count: a block takes 64 parameters (one per lane); wave w of
-// its kRedWaves sums the partials w, w + kRedWaves, ... in order in double,
-// with eight loads in flight, and the wave sums are added in a fixed order.
+// Fixed-order (deterministic) reduction of the weight-gradient partials of
+// every layer in one launch, scaled by 1 / count: layer l's partials sit at
+// part + nb * off[l], one row of the layer's lp parameters per weight-gradient
+// block.  A block takes 64 parameters (one per lane, possibly of two
+// layers); wave w of its kRedWaves sums the partials w, w + kRedWaves, ... in
+// order in double, with eight loads in flight, and the wave sums are added in
+// a fixed order.
 constexpr int kRedWaves = 16;
 
-__global__ __launch_bounds__(kRedWaves * 64) void k_reduce_grad(const float* __restrict__ part,
-                                                                int nb, int64_t np,
-                                                                const double* __restrict__ scal,
-                                                                float* __restrict__ grad) {
+struct RedArgs {
+  const float* part;
+  int nb;                  // partials per parameter (weight-gradient blocks)
+  int64_t off[kNL + 1];    // first parameter of each layer; off[kNL] = all
+  const double* scal;
+  float* grad;
+};
+
+__global__ __launch_bounds__(kRedWaves * 64) void k_reduce_grad(const RedArgs r) {
   __shared__ double ws[kRedWaves][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t o = (int64_t)blockIdx.x * 64 + lane;
+  const int nb = r.nb;
   double s = 0.0;
-  if (o < np) {
+  if (o < r.off[kNL]) {
+    int l = 0;
+#pragma unroll
+    for (int k = 1; k < kNL; k++) l += o >= r.off[k];
+    const int64_t lp = r.off[l + 1] - r.off[l];
+    const float* base = r.part + (int64_t)nb * r.off[l] + (o - r.off[l]);
     constexpr int U = 8;
     for (int b0 = w; b0 < nb; b0 += kRedWaves * U) {
       // clamped loads (in bounds, no lane condition to wait on), masked adds
       float v[U];
 #pragma unroll
-      for (int u = 0; u < U; u++) v[u] = part[(int64_t)min(b0 + kRedWaves * u, nb - 1) * np + o];
+      for (int u = 0; u < U; u++) v[u] = base[(int64_t)min(b0 + kRedWaves * u, nb - 1) * lp];
 #pragma unroll
       for (int u = 0; u < U; u++) s += b0 + kRedWaves * u < nb ? (double)v[u] : 0.0;
     }
   }
   ws[w][lane] = s;
   __syncthreads();
-  if (w == 0 && o < np) {
+  if (w == 0 && o < r.off[kNL]) {
     double t = 0.0;
     for (int k = 0; k < kRedWaves; k++) t += ws[k][lane];
-    grad[o] = (float)(t * scal[1]);
+    r.grad[o] = (float)(t * r.scal[1]);
   }
 }
 
@@ -1174,8 +1188,6 @@ int32_t sgt_create(int32_t H, int32_t W, uint64_t seed, void* stream, sgt_net_t*
   const int64_t P = (int64_t)H * W;
   // partial slots: one per block of the weight-gradient kernels
   n->part_blocks = ((W + kTC - 1) / kTC) * ((H + kWgRows * kWgTiles - 1) / (kWgRows * kWgTiles));
-  int64_t maxlp = 0;
-  for (int l = 0; l < kNL; l++) maxlp = layer_params(l) > maxlp ? layer_params(l) : maxlp;
   hipError_t e = hipSuccess;
   auto al = [&](void** p, size_t b) {
     if (e == hipSuccess) e = gvom::dev_alloc(p, b < 16 ? 16 : b);
@@ -1196,7 +1208,7 @@ int32_t sgt_create(int32_t H, int32_t W, uint64_t seed, void* stream, sgt_net_t*
     al((void**)&n->dzh[k], P * 32 * 2);
     al((void**)&n->dzl[k], P * 32 * 2);
   }
-  al((void**)&n->part, (size_t)n->part_blocks * maxlp * 4);
+  al((void**)&n->part, (size_t)n->part_blocks * n->np * 4);  // every layer's partials
   al((void**)&n->lpart, (size_t)4096 * 2 * 8);
   al((void**)&n->scal, 16);
   al((void**)&n->mean, kFeat * 4);
@@ -1359,26 +1371,36 @@ int32_t sgt_loss_grad(sgt_net_t* n, const float* feat_dev, const float* label_de
   int hb = 0;  // bf16 pair holding dz (set by the layer above)
   dim3 g8((W + kTC - 1) / kTC, (H + 7) / 8);
   for (int l = kNL - 1; l >= 0; l--) {
-    const int64_t lp = layer_params(l);
     // weight gradients: the 2-channel output layer on the VALU, the others on
     // matrix cores (dz of those comes as the bf16 pair of the layer above)
     int nb;
     const dim3 gw((W + kTC - 1) / kTC, (H + kWgRows * kWgTiles - 1) / (kWgRows * kWgTiles));
     nb = (int)(gw.x * gw.y);
+    float* const part = n->part + (size_t)nb * n->off[l];  // this layer's partials
     if (l == 4) {
       hipLaunchKernelGGL((k_bwd_weight_out<kWgTiles>), gw, dim3(256), 0, n->stream, dz,
-                         n->act[l], n->part, H, W);
+                         n->act[l], part, H, W);
     } else {
       if (l == 0)
         hipLaunchKernelGGL((k_bwd_weight_mfma<16, kWgTiles>), gw, dim3(256), 0, n->stream,
-                           n->dzh[hb], n->dzl[hb], n->act[l], n->part, H, W);
+                           n->dzh[hb], n->dzl[hb], n->act[l], part, H, W);
       else
         hipLaunchKernelGGL((k_bwd_weight_mfma<32, kWgTiles>), gw, dim3(256), 0, n->stream,
-                           n->dzh[hb], n->dzl[hb], n->act[l], n->part, H, W);
+                           n->dzh[hb], n->dzl[hb], n->act[l], part, H, W);
     }
-    hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((lp + 63) / 64)), dim3(kRedWaves * 64), 0, n->stream,
-                       n->part, nb, lp, n->scal, n->grad + n->off[l]);
-    if (l == 0) break;
+    if (l == 0) {
+      // every layer's partials in one reduction
+      RedArgs ra;
+      ra.part = n->part;
+      ra.nb = nb;
+      for (int k = 0; k < kNL; k++) ra.off[k] = n->off[k];
+      ra.off[kNL] = n->np;
+      ra.scal = n->scal;
+      ra.grad = n->grad;
+      hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((n->np + 63) / 64)), dim3(kRedWaves * 64),
+                         0, n->stream, ra);
+      break;
+    }
     if (l == 4)
       hipLaunchKernelGGL(k_bwd_data_out, g8, dim3(512), 0, n->stream, dz, n->wbf[l], n->act[l],
                          n->dzh[hb], n->dzl[hb], H, W);
