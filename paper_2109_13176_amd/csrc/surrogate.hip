@@ -448,9 +448,20 @@ __global__ __launch_bounds__(256) void k_loss(const float* out, const float* lab
 __global__ __launch_bounds__(256) void k_loss_total(const double* part, int nb, double* scal) {
   __shared__ double s[2][256];
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256) {
-    a += part[2 * i];
-    b += part[2 * i + 1];
+  // a thread's pairs i = t, t + 256, ... summed in that order; sixteen
+  // 16-byte loads in flight per round (clamped in-bounds loads, masked adds)
+  constexpr int U = 16;
+  for (int i0 = threadIdx.x; i0 < nb; i0 += 256 * U) {
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) v[u] = ((const double2*)part)[min(i0 + 256 * u, nb - 1)];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if (i0 + 256 * u < nb) {
+        a += v[u].x;
+        b += v[u].y;
+      }
+    }
   }
   s[0][threadIdx.x] = a;
   s[1][threadIdx.x] = b;
